@@ -1,0 +1,507 @@
+/*
+ * Oracle for the monodomain explicit step -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, FP64, scalar-loop reference of what the GPU library computes.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or helper with the
+ * GPU library; the two meet only through caller-supplied arrays.
+ *
+ * Paper: Antonioletti et al., "BeatBox -- HPC simulation environment for
+ * biophysically and anatomically realistic cardiac electrophysiology"
+ * (arXiv:1605.06015).  Citations name the paper's sections and equations.
+ *
+ * Layout: box index idx = x + nx*(y + ny*z); tissue ("active") voxels are
+ * listed in increasing box order in act[]; state is [nvar][nbox] (only tissue
+ * entries are read or written).  Stencil weights are kept literally, 27 per
+ * tissue voxel, q = (dx,dy,dz) stored at (dz+1)*9 + (dy+1)*3 + (dx+1).
+ *
+ * Parity status (every function below is pinned by the CPU tests unless this
+ * list says otherwise):
+ *   - weights, diffusion, Euler, Rush-Larsen, Barkley/ZFK/FHN steps: pinned
+ *     (closed forms, invariants, brute force, plane-wave speed).
+ *   - weights at boundary voxels with variable fibres (reading G6 of the
+ *     design notes: a void neighbour's tensor is replaced by the centre's):
+ *     parity unpinned -- the paper leaves that case undefined.
+ *   - Courtemanche-Ramirez-Nattel 1998 cell model: transcribed from the
+ *     original model publication (not part of the paper); pinned only loosely
+ *     by that publication's resting state and action-potential shape.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4 };
+enum { S_ADDITIVE = 0, S_SPLIT = 1 };
+
+#define NVAR_MAX 32
+
+/* ------------------------------------------------------------------------- */
+/* Geometry: "Monodomain diffusion and boundary conditions", eqs (Lu),      */
+/* (nonflux), (sigma) and the weight formulas that follow them.             */
+/* ------------------------------------------------------------------------- */
+
+/* D_jk = Dperp delta_jk + (Dpar - Dperp) f_j f_k  -- eq (sigma), f a unit vector.
+ * With no fibre field the tissue is isotropic with coefficient Dperp. */
+static int tensor_of(const double *fibre, int64_t idx, double Dpar, double Dperp,
+                     double D[3][3])
+{
+    double f[3] = {0, 0, 0};
+    double g = 0.0;
+    if (fibre) {
+        for (int j = 0; j < 3; j++) f[j] = fibre[3 * idx + j];
+        double n = sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+        if (!(n >= 1e-12)) return -1;   /* cannot be a unit vector */
+        for (int j = 0; j < 3; j++) f[j] /= n;
+        g = Dpar - Dperp;
+    }
+    for (int j = 0; j < 3; j++)
+        for (int k = 0; k < 3; k++)
+            D[j][k] = (j == k ? Dperp : 0.0) + g * f[j] * f[k];
+    return 0;
+}
+
+static int in_box(int nx, int ny, int nz, int x, int y, int z)
+{
+    return x >= 0 && y >= 0 && z >= 0 && x < nx && y < ny && z < nz;
+}
+
+/* chi_p: grid indicator of the tissue; outside the box counts as void. */
+static int chi(int nx, int ny, int nz, const uint8_t *mask, int x, int y, int z)
+{
+    if (!in_box(nx, ny, nz, x, y, z)) return 0;
+    return mask[(int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z)] != 0;
+}
+
+/* Stencil weights W^p_q = Wbar^p_q + Wtilde^p_q for every tissue voxel p and
+ * q in {0,+-1}^3, with W^p_0 = -sum_{q!=0} W^p_q.
+ *  Wbar:   chi_{p+q}/h^2 * { D^p_jj on faces q=+-q_j;
+ *                            +D^p_jk/2 on edges q=+-(q_j+q_k);
+ *                            -D^p_jk/2 on edges q=+-(q_j-q_k);  0 on corners }
+ *          (each unordered pair j<k gives one edge weight: reading G5);
+ *  Wtilde: chi_{p+q} chi_{p-q}/(4h^2) * (+-) sum_j (D^{p+q_j}_jk - D^{p-q_j}_jk)
+ *          on faces q=+-q_k, 0 elsewhere.
+ * D at a void or out-of-box neighbour inside Wtilde is replaced by D^p
+ * (reading G6).  Returns 0, or -1 if a tissue fibre has (near) zero length. */
+int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
+                const double *fibre, double Dpar, double Dperp,
+                int64_t nact, const int64_t *act, double *W)
+{
+    const double ih2 = 1.0 / (h * h);
+    for (int64_t a = 0; a < nact; a++) {
+        int64_t idx = act[a];
+        int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
+        double Dp[3][3];
+        if (tensor_of(fibre, idx, Dpar, Dperp, Dp)) return -1;
+
+        /* D at p+q_j and p-q_j for j = 0..2 (substituted by D^p when void). */
+        double Dplus[3][3][3], Dminus[3][3][3];
+        for (int j = 0; j < 3; j++) {
+            int e[3] = {0, 0, 0};
+            e[j] = 1;
+            for (int s = -1; s <= 1; s += 2) {
+                int xx = x + s * e[0], yy = y + s * e[1], zz = z + s * e[2];
+                double (*dst)[3] = (s > 0) ? Dplus[j] : Dminus[j];
+                if (chi(nx, ny, nz, mask, xx, yy, zz)) {
+                    int64_t nidx = (int64_t)xx + (int64_t)nx * ((int64_t)yy + (int64_t)ny * zz);
+                    if (tensor_of(fibre, nidx, Dpar, Dperp, dst)) return -1;
+                } else {
+                    memcpy(dst, Dp, sizeof(Dp));
+                }
+            }
+        }
+
+        double *w = W + 27 * a;
+        double sum = 0.0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int qi = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                    int q[3] = {dx, dy, dz};
+                    int nnz = (dx != 0) + (dy != 0) + (dz != 0);
+                    double val = 0.0;
+                    if (nnz == 0) { w[qi] = 0.0; continue; }
+                    int cp = chi(nx, ny, nz, mask, x + dx, y + dy, z + dz);
+                    int cm = chi(nx, ny, nz, mask, x - dx, y - dy, z - dz);
+                    if (nnz == 1) {
+                        int k = (dx != 0) ? 0 : (dy != 0) ? 1 : 2;
+                        double sgn = (double)q[k];
+                        val += cp * Dp[k][k] * ih2;                         /* Wbar, face */
+                        double div = 0.0;
+                        for (int j = 0; j < 3; j++) div += Dplus[j][j][k] - Dminus[j][j][k];
+                        val += cp * cm * 0.25 * ih2 * sgn * div;            /* Wtilde */
+                    } else if (nnz == 2) {
+                        int j = -1, k = -1;
+                        for (int t = 0; t < 3; t++)
+                            if (q[t] != 0) { if (j < 0) j = t; else k = t; }
+                        double sgn = (q[j] == q[k]) ? 0.5 : -0.5;           /* +-(q_j+q_k) vs +-(q_j-q_k) */
+                        val += cp * sgn * Dp[j][k] * ih2;                   /* Wbar, edge */
+                    }
+                    w[qi] = val;
+                    sum += val;
+                }
+        w[13] = -sum;
+    }
+    return 0;
+}
+
+/* (L u)_p = sum_q W^p_q u_{p+q}, written in the equivalent difference form
+ * sum_{q!=0} W^p_q (u_{p+q} - u_p) (reading G13); out-of-box q have W = 0. */
+static double apply_L(int nx, int ny, int nz, const double *w, const double *u, int64_t idx)
+{
+    int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
+    double up = u[idx], acc = 0.0;
+    for (int dz = -1; dz <= 1; dz++)
+        for (int dy = -1; dy <= 1; dy++)
+            for (int dx = -1; dx <= 1; dx++) {
+                int qi = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1);
+                if (qi == 13 || w[qi] == 0.0) continue;
+                if (!in_box(nx, ny, nz, x + dx, y + dy, z + dz)) continue;
+                int64_t n = (int64_t)(x + dx) + (int64_t)nx * ((int64_t)(y + dy) + (int64_t)ny * (z + dz));
+                acc += w[qi] * (u[n] - up);
+            }
+    return acc;
+}
+
+/* Apply L once to a field (used by the invariant tests). */
+void orc_apply_L(int nx, int ny, int nz, int64_t nact, const int64_t *act,
+                 const double *W, const double *u, double *out)
+{
+    for (int64_t a = 0; a < nact; a++) out[a] = apply_L(nx, ny, nz, W + 27 * a, u, act[a]);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cell models.  Each fills, for state y (y[0] = V):                          */
+/*   rate[i]  = dy_i/dt for variables advanced by forward Euler               */
+/*              (rate[0] = -I_ion: the kinetic part of the voltage equation);  */
+/*   inf[i], tau[i] for gating variables advanced by Rush-Larsen.             */
+/* ------------------------------------------------------------------------- */
+
+int orc_nvar(int model)
+{
+    switch (model) {
+    case M_NONE: return 1;
+    case M_BARKLEY: return 2;
+    case M_ZFK: return 1;
+    case M_FHN: return 2;
+    case M_CRN: return 21;
+    default: return -1;
+    }
+}
+
+int orc_nparams(int model)
+{
+    switch (model) {
+    case M_NONE: return 0;
+    case M_BARKLEY: return 3;
+    case M_ZFK: return 1;
+    case M_FHN: return 3;
+    case M_CRN: return 0;
+    default: return -1;
+    }
+}
+
+/* Which variables are gates (Rush-Larsen) for a model. */
+static int is_gate(int model, int i)
+{
+    if (model == M_CRN) return i >= 6;
+    return 0;
+}
+
+/* Barkley (1991): u' = eps^-1 u (1-u) (u - (v+b)/a),  v' = u - v.
+ * The paper uses it as `fhnbkl` (Cell models; ez.bbs) without printing it. */
+static void barkley_rates(const double *p, const double *y, double *rate)
+{
+    double a = p[0], b = p[1], eps = p[2];
+    double u = y[0], v = y[1];
+    rate[0] = u * (1.0 - u) * (u - (v + b) / a) / eps;
+    rate[1] = u - v;
+}
+
+/* ZFK / Nagumo / Schloegl kinetics, eq (ZFKbidomV): V' = V (V - alpha)(1 - V). */
+static void zfk_rates(const double *p, const double *y, double *rate)
+{
+    double al = p[0], V = y[0];
+    rate[0] = V * (V - al) * (1.0 - V);
+}
+
+/* Cubic FitzHugh-Nagumo `fhncub`, eq (FHN): u' = (u - u^3/3 - v)/eps,
+ * v' = eps (u + beta - gamma v) (cubic term per eq (fhn): reading G3). */
+static void fhn_rates(const double *p, const double *y, double *rate)
+{
+    double eps = p[0], bet = p[1], gam = p[2];
+    double u = y[0], v = y[1];
+    rate[0] = (u - u * u * u / 3.0 - v) / eps;
+    rate[1] = eps * (u + bet - gam * v);
+}
+
+/* z / (exp(z) - 1), continued by its limit 1 at z = 0. */
+static double z_over_expm1(double z)
+{
+    return z == 0.0 ? 1.0 : z / expm1(z);
+}
+
+/* Courtemanche, Ramirez & Nattel (1998) human atrial cell model, as cited in
+ * "Cell models" and used for the scaling runs.  Transcribed from the original
+ * model publication (its equations are not printed in the paper).  Currents
+ * are in pA/pF (membrane capacitance 100 pF), concentrations in mM, time in ms.
+ * State order: V, Na_i, K_i, Ca_i, Ca_up, Ca_rel, m, h, j, oa, oi, ua, ui,
+ * xr, xs, d, f, fCa, u, v, w. */
+static void crn_rates(const double *y, double *rate, double *inf, double *tau)
+{
+    const double R = 8.3143, T = 310.0, F = 96.4867;
+    const double Cm = 100.0, Vi = 13668.0, Vup = 1109.52, Vrel = 96.48;
+    const double Ko = 5.4, Nao = 140.0, Cao = 1.8;
+    const double gNa = 7.8, gK1 = 0.09, gto = 0.1652, gKr = 0.029411765, gKs = 0.12941176;
+    const double gCaL = 0.12375, gbCa = 0.001131, gbNa = 0.0006744375;
+    const double INaKmax = 0.59933874, INaCamax = 1600.0, IpCamax = 0.275, Iupmax = 0.005;
+    const double KmNai = 10.0, KmKo = 1.5, KmNa = 87.5, KmCa = 1.38, ksat = 0.1, gam = 0.35;
+    const double krel = 30.0, Kup = 0.00092, Caupmax = 15.0;
+    const double CMDNmax = 0.05, TRPNmax = 0.07, CSQNmax = 10.0;
+    const double KmCMDN = 0.00238, KmTRPN = 0.0005, KmCSQN = 0.8;
+    const double KQ10 = 3.0, tau_tr = 180.0;
+
+    double V = y[0], Nai = y[1], Ki = y[2], Cai = y[3], Caup = y[4], Carel = y[5];
+    double m = y[6], h = y[7], j = y[8], oa = y[9], oi = y[10], ua = y[11], ui = y[12];
+    double xr = y[13], xs = y[14], d = y[15], f = y[16], fCa = y[17];
+    double u = y[18], v = y[19], w = y[20];
+
+    double RTF = R * T / F;
+    double ENa = RTF * log(Nao / Nai);
+    double EK = RTF * log(Ko / Ki);
+    double ECa = 0.5 * RTF * log(Cao / Cai);
+
+    /* membrane currents, pA/pF */
+    double INa = gNa * m * m * m * h * j * (V - ENa);
+    double IK1 = gK1 * (V - EK) / (1.0 + exp(0.07 * (V + 80.0)));
+    double Ito = gto * oa * oa * oa * oi * (V - EK);
+    double gKur = 0.005 + 0.05 / (1.0 + exp((V - 15.0) / -13.0));
+    double IKur = gKur * ua * ua * ua * ui * (V - EK);
+    double IKr = gKr * xr * (V - EK) / (1.0 + exp((V + 15.0) / 22.4));
+    double IKs = gKs * xs * xs * (V - EK);
+    double ICaL = gCaL * d * f * fCa * (V - 65.0);
+    double sigma = (exp(Nao / 67.3) - 1.0) / 7.0;
+    double fNaK = 1.0 / (1.0 + 0.1245 * exp(-0.1 * V / RTF) + 0.0365 * sigma * exp(-V / RTF));
+    double INaK = INaKmax * fNaK / (1.0 + pow(KmNai / Nai, 1.5)) * Ko / (Ko + KmKo);
+    double INaCa = INaCamax * (exp(gam * V / RTF) * Nai * Nai * Nai * Cao
+                               - exp((gam - 1.0) * V / RTF) * Nao * Nao * Nao * Cai)
+                   / ((KmNa * KmNa * KmNa + Nao * Nao * Nao) * (KmCa + Cao)
+                      * (1.0 + ksat * exp((gam - 1.0) * V / RTF)));
+    double IbCa = gbCa * (V - ECa);
+    double IbNa = gbNa * (V - ENa);
+    double IpCa = IpCamax * Cai / (0.0005 + Cai);
+
+    /* calcium handling, mM/ms */
+    double Irel = krel * u * u * v * w * (Carel - Cai);
+    double Itr = (Caup - Carel) / tau_tr;
+    double Iup = Iupmax / (1.0 + Kup / Cai);
+    double Iupleak = Iupmax * Caup / Caupmax;
+
+    double Iion = INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL;
+    rate[0] = -Iion;
+    rate[1] = (-3.0 * INaK - 3.0 * INaCa - IbNa - INa) * Cm / (Vi * F);
+    rate[2] = (2.0 * INaK - IK1 - Ito - IKur - IKr - IKs) * Cm / (Vi * F);
+    double B1 = (2.0 * INaCa - IpCa - ICaL - IbCa) * Cm / (2.0 * Vi * F)
+                + (Vup * (Iupleak - Iup) + Irel * Vrel) / Vi;
+    double B2 = 1.0 + TRPNmax * KmTRPN / ((Cai + KmTRPN) * (Cai + KmTRPN))
+                + CMDNmax * KmCMDN / ((Cai + KmCMDN) * (Cai + KmCMDN));
+    rate[3] = B1 / B2;
+    rate[4] = Iup - Iupleak - Itr * Vrel / Vup;
+    rate[5] = (Itr - Irel) / (1.0 + CSQNmax * KmCSQN / ((Carel + KmCSQN) * (Carel + KmCSQN)));
+
+    /* gates: inf and tau */
+    double am = 3.2 * z_over_expm1(-0.1 * (V + 47.13));
+    double bm = 0.08 * exp(-V / 11.0);
+    double ah, bh, aj, bj;
+    if (V < -40.0) {
+        ah = 0.135 * exp((V + 80.0) / -6.8);
+        bh = 3.56 * exp(0.079 * V) + 3.1e5 * exp(0.35 * V);
+        aj = (-127140.0 * exp(0.2444 * V) - 3.474e-5 * exp(-0.04391 * V)) * (V + 37.78)
+             / (1.0 + exp(0.311 * (V + 79.23)));
+        bj = 0.1212 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
+    } else {
+        ah = 0.0;
+        bh = 1.0 / (0.13 * (1.0 + exp((V + 10.66) / -11.1)));
+        aj = 0.0;
+        bj = 0.3 * exp(-2.535e-7 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
+    }
+    tau[6] = 1.0 / (am + bm); inf[6] = am * tau[6];
+    tau[7] = 1.0 / (ah + bh); inf[7] = ah * tau[7];
+    tau[8] = 1.0 / (aj + bj); inf[8] = aj * tau[8];
+
+    double aoa = 0.65 / (exp((V + 10.0) / -8.5) + exp((V - 30.0) / -59.0));
+    double boa = 0.65 / (2.5 + exp((V + 82.0) / 17.0));
+    tau[9] = 1.0 / (aoa + boa) / KQ10;
+    inf[9] = 1.0 / (1.0 + exp((V + 20.47) / -17.54));
+    double aoi = 1.0 / (18.53 + exp((V + 113.7) / 10.95));
+    double boi = 1.0 / (35.56 + exp((V + 1.26) / -7.44));
+    tau[10] = 1.0 / (aoi + boi) / KQ10;
+    inf[10] = 1.0 / (1.0 + exp((V + 43.1) / 5.3));
+
+    tau[11] = tau[9];   /* alpha_ua, beta_ua have the same form as alpha_oa, beta_oa */
+    inf[11] = 1.0 / (1.0 + exp((V + 30.3) / -9.6));
+    double aui = 1.0 / (21.0 + exp((V - 185.0) / -28.0));
+    double bui = exp((V - 158.0) / 16.0);
+    tau[12] = 1.0 / (aui + bui) / KQ10;
+    inf[12] = 1.0 / (1.0 + exp((V - 99.45) / 27.48));
+
+    double axr = 0.0003 * 5.0 * z_over_expm1(-(V + 14.1) / 5.0);
+    double bxr = 7.3898e-5 * 5.1237 * z_over_expm1((V - 3.3328) / 5.1237);
+    tau[13] = 1.0 / (axr + bxr);
+    inf[13] = 1.0 / (1.0 + exp((V + 14.1) / -6.5));
+    double axs = 4e-5 * 17.0 * z_over_expm1(-(V - 19.9) / 17.0);
+    double bxs = 3.5e-5 * 9.0 * z_over_expm1((V - 19.9) / 9.0);
+    tau[14] = 0.5 / (axs + bxs);
+    inf[14] = 1.0 / sqrt(1.0 + exp((V - 19.9) / -12.7));
+
+    double zd = (V + 10.0) / 6.24;
+    tau[15] = 1.0 / (0.035 * 6.24 * z_over_expm1(-zd) * (1.0 + exp(-zd)));
+    inf[15] = 1.0 / (1.0 + exp((V + 10.0) / -8.0));
+    tau[16] = 9.0 / (0.0197 * exp(-0.0337 * 0.0337 * (V + 10.0) * (V + 10.0)) + 0.02);
+    inf[16] = 1.0 / (1.0 + exp((V + 28.0) / 6.9));
+    tau[17] = 2.0;
+    inf[17] = 1.0 / (1.0 + Cai / 0.00035);
+
+    /* Fn: release trigger, from SR release and sarcolemmal Ca flux (currents in pA) */
+    double Fn = 1e-12 * Vrel * Irel - 5e-13 / F * (0.5 * ICaL * Cm - 0.2 * INaCa * Cm);
+    tau[18] = 8.0;
+    inf[18] = 1.0 / (1.0 + exp(-(Fn - 3.4175e-13) / 13.67e-16));
+    tau[19] = 1.91 + 2.09 / (1.0 + exp(-(Fn - 3.4175e-13) / 13.67e-16));
+    inf[19] = 1.0 - 1.0 / (1.0 + exp(-(Fn - 6.835e-14) / 13.67e-16));
+    double zw = (V - 7.9) / 5.0;
+    tau[20] = 6.0 / (5.0 * z_over_expm1(-zw) * (1.0 + 0.3 * exp(-zw)));
+    inf[20] = 1.0 - 1.0 / (1.0 + exp(-(V - 40.0) / 17.0));
+}
+
+static void model_eval(int model, const double *p, const double *y,
+                       double *rate, double *inf, double *tau)
+{
+    switch (model) {
+    case M_NONE: rate[0] = 0.0; break;
+    case M_BARKLEY: barkley_rates(p, y, rate); break;
+    case M_ZFK: zfk_rates(p, y, rate); break;
+    case M_FHN: fhn_rates(p, y, rate); break;
+    case M_CRN: crn_rates(y, rate, inf, tau); break;
+    }
+}
+
+/* Expose the kinetic right-hand side of one cell (for tests). */
+int orc_model_eval(int model, const double *p, const double *y,
+                   double *rate, double *inf, double *tau)
+{
+    int nv = orc_nvar(model);
+    if (nv < 0) return -1;
+    for (int i = 0; i < nv; i++) { rate[i] = 0.0; inf[i] = 0.0; tau[i] = 0.0; }
+    model_eval(model, p, y, rate, inf, tau);
+    return nv;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Stimulus: I_stim,p(n) = sum_s A_s [p in R_s] [step n inside a window of s] */
+/* (external current term of eq (monodomain); reading G4: positive A         */
+/* depolarises; reading G12: windows in whole steps).                        */
+/* ------------------------------------------------------------------------- */
+static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t count)
+{
+    if (n < n0 || len <= 0) return 0;
+    int64_t r = n - n0;
+    if (period <= 0) return r < len;
+    int64_t c = r / period;
+    if (count > 0 && c >= count) return 0;
+    return (r - c * period) < len;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Time stepping ("Splitting the problem into parts"; eq (Euler); eqs (RL),  */
+/* (RLcoeff) in the corrected order y_{n+1} = B + A y_n: reading G1).        */
+/* ------------------------------------------------------------------------- */
+/*
+ * Advances state (box layout [nvar][nbox]) by nsteps steps, the first of
+ * which has index n0 (t_n = n dt).  vnext is an nbox scratch buffer.
+ *  additive scheme: V+ = V + dt(-I_ion(V,g) + I_stim + LV), kinetics at (V, g);
+ *  split scheme:    V* = V + dt LV, then V+ = V* + dt(-I_ion(V*,g) + I_stim),
+ *                   kinetics at (V*, g).
+ * Non-gates use forward Euler; gates y+ = yinf + (y - yinf) exp(-dt/tau).
+ * If record != 0, activation time, peak and APD90 are detected from the pair
+ * (V_n, V_{n+1}) per voxel (reading G23): status 0 -> 1 on the first upward
+ * crossing of theta (AT linearly interpolated), 1 -> 2 at the first decrease
+ * (vmax = V_n), 2 -> 3 at the first downward crossing of
+ * vrest + 0.1 (vmax - vrest) (APD90 = interpolated time - AT).
+ */
+int orc_run(int nx, int ny, int nz, int64_t nact, const int64_t *act, const double *W,
+            int model, const double *params, double dt, int scheme,
+            int nstim, const uint8_t *stim_region, const double *stim_amp,
+            const int64_t *stim_n0, const int64_t *stim_len, const int64_t *stim_period,
+            const int64_t *stim_count,
+            double *state, double *vnext, int64_t n0, int64_t nsteps,
+            int record, double theta, uint8_t *status, double *at, double *vmax,
+            double *apd, const double *vrest, int nthreads)
+{
+    int nv = orc_nvar(model);
+    if (nv < 0) return -1;
+    const int64_t nbox = (int64_t)nx * ny * nz;
+    double *V = state;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    (void)nthreads;
+#endif
+
+    for (int64_t s = 0; s < nsteps; s++) {
+        const int64_t n = n0 + s;
+        const double tn = (double)n * dt;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) num_threads(nthreads)
+#endif
+        for (int64_t a = 0; a < nact; a++) {
+            int64_t p = act[a];
+            double y[NVAR_MAX], rate[NVAR_MAX], inf[NVAR_MAX], tau[NVAR_MAX];
+            double LV = apply_L(nx, ny, nz, W + 27 * a, V, p);
+            double Is = 0.0;
+            for (int k = 0; k < nstim; k++)
+                if (stim_region[(int64_t)k * nbox + p] &&
+                    stim_on(n, stim_n0[k], stim_len[k], stim_period[k], stim_count[k]))
+                    Is += stim_amp[k];
+            for (int i = 0; i < nv; i++) y[i] = state[(int64_t)i * nbox + p];
+            double Vold = y[0];
+            if (scheme == S_SPLIT) y[0] = Vold + dt * LV;
+            model_eval(model, params, y, rate, inf, tau);
+            double Vnew = (scheme == S_SPLIT) ? y[0] + dt * (rate[0] + Is)
+                                              : Vold + dt * (rate[0] + Is + LV);
+            for (int i = 1; i < nv; i++) {
+                double yi = y[i];
+                if (is_gate(model, i))
+                    yi = inf[i] + (yi - inf[i]) * exp(-dt / tau[i]);
+                else
+                    yi = yi + dt * rate[i];
+                state[(int64_t)i * nbox + p] = yi;
+            }
+            vnext[p] = Vnew;
+
+            if (record) {
+                uint8_t st = status[a];
+                if (st == 0 && Vold < theta && Vnew >= theta) {
+                    at[a] = tn + dt * (theta - Vold) / (Vnew - Vold);
+                    st = 1;
+                }
+                if (st == 1 && Vnew < Vold) {
+                    vmax[a] = Vold;
+                    st = 2;
+                }
+                if (st == 2) {
+                    double vr = vrest[a] + 0.1 * (vmax[a] - vrest[a]);
+                    if (Vold >= vr && Vnew < vr) {
+                        apd[a] = tn + dt * (Vold - vr) / (Vold - Vnew) - at[a];
+                        st = 3;
+                    }
+                }
+                status[a] = st;
+            }
+        }
+        for (int64_t a = 0; a < nact; a++) V[act[a]] = vnext[act[a]];
+    }
+    return 0;
+}

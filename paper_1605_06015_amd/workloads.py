@@ -1,0 +1,170 @@
+"""Seeded synthetic inputs shared by the GPU library's tests, the oracle's tests
+and the benchmark.
+
+This module only *generates inputs* (tissue masks, fibre fields, initial
+states, stimulus regions).  It contains none of the method's arithmetic: no
+stencil weights, no kinetics, no time stepping.  Both the oracle and the GPU
+library consume the arrays it returns, byte for byte.
+
+Array conventions: masks are uint8 of shape (nz, ny, nx) (x fastest in
+memory), fibres float64 of shape (nz, ny, nx, 3).
+
+The paper's anatomical meshes (rabbit ventricles, human atrium; "Parallel
+scaling performance") are not available; the ellipsoidal shells below stand
+in for them by active fraction and shape class.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+# Published initial state of the Courtemanche-Ramirez-Nattel (1998) atrial cell
+# model, in the state order V, Na_i, K_i, Ca_i, Ca_up, Ca_rel, m, h, j, oa, oi,
+# ua, ui, xr, xs, d, f, fCa, u, v, w (units mV, mM, dimensionless).
+CRN_NAMES = ("V", "Nai", "Ki", "Cai", "Caup", "Carel", "m", "h", "j", "oa", "oi",
+             "ua", "ui", "xr", "xs", "d", "f", "fCa", "u", "v", "w")
+CRN_INITIAL = (-81.18, 11.17, 139.0, 1.013e-4, 1.488, 1.488, 2.908e-3, 0.9649, 0.9775,
+               3.043e-2, 0.9992, 4.966e-3, 0.9986, 3.296e-5, 1.869e-2, 1.367e-4, 0.9996,
+               0.7755, 0.0, 1.0, 0.9992)
+
+
+# --------------------------------------------------------------------------
+# Barkley 2D: 100x100, cross-field initial condition + seeded uniform noise
+# --------------------------------------------------------------------------
+BARKLEY_2D = dict(nx=100, ny=100, nz=1, h=0.2, dt=0.008, D=1.0, a=0.75, b=0.02, eps=0.02,
+                  steps=2000)
+
+
+def barkley_cross_field(nx: int = 100, ny: int = 100, seed: int = 0, noise: float = 1e-3):
+    """u = 1 where the x index < nx/2, v = 0.5 where the y index < ny/2 (indices
+    from 0), plus i.i.d. U(-noise, +noise) added to both fields at every voxel."""
+    rng = np.random.default_rng(seed)
+    u = np.zeros((1, ny, nx))
+    v = np.zeros((1, ny, nx))
+    u[0, :, : nx // 2] = 1.0
+    v[0, : ny // 2, :] = 0.5
+    u += rng.uniform(-noise, noise, size=u.shape)
+    v += rng.uniform(-noise, noise, size=v.shape)
+    return u, v
+
+
+# --------------------------------------------------------------------------
+# Ellipsoidal cup shell with transmural fibre rotation (atrial/ventricular stand-in)
+# --------------------------------------------------------------------------
+def _shell_s(nx, ny, nz, h, axes, centre):
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X = (x + 0.5) * h - centre[0]
+    Y = (y + 0.5) * h - centre[1]
+    Z = (z + 0.5) * h - centre[2]
+    s = np.sqrt((X / axes[0]) ** 2 + (Y / axes[1]) ** 2 + (Z / axes[2]) ** 2)
+    return s, X, Y, Z
+
+
+def _fibres_from_normal(nx_, ny_, nz_, e, angle_lo=-60.0, angle_hi=60.0):
+    """Fibre f = cos(a) c + sin(a) l with a = lo + (hi-lo) e, c the circumferential
+    direction normalise(z x n) and l = n x c; c := x where n is parallel to z."""
+    n = np.stack([nx_, ny_, nz_], axis=-1)
+    n = n / np.maximum(np.linalg.norm(n, axis=-1, keepdims=True), 1e-30)
+    zhat = np.array([0.0, 0.0, 1.0])
+    c = np.cross(np.broadcast_to(zhat, n.shape), n)
+    cn = np.linalg.norm(c, axis=-1, keepdims=True)
+    xhat = np.broadcast_to(np.array([1.0, 0.0, 0.0]), n.shape)
+    c = np.where(cn > 1e-9, c / np.maximum(cn, 1e-30), xhat)
+    l = np.cross(n, c)
+    a = np.deg2rad(angle_lo + (angle_hi - angle_lo) * np.clip(e, 0.0, 1.0))[..., None]
+    f = np.cos(a) * c + np.sin(a) * l
+    return f / np.linalg.norm(f, axis=-1, keepdims=True)
+
+
+def cup_shell(nx=128, ny=128, nz=64, h=0.25, active_frac=0.35, seed=1, tol=0.005):
+    """Half-ellipsoidal cup: outer semi-axes 15.5 mm x (1 +- 0.05, seeded), base at
+    the top z face, apex at the bottom; inner scale s_in found by bisection so
+    that the active fraction is active_frac +- tol.
+
+    Returns dict(mask, fibre, apex (mm), s, s_in)."""
+    rng = np.random.default_rng(seed)
+    L = np.array([nx * h, ny * h, nz * h])
+    axes = 0.5 * min(L[0], L[1]) - 0.5
+    axes = np.array([axes, axes, min(axes, L[2] - 0.5)]) * (1.0 + rng.uniform(-0.05, 0.05, 3))
+    axes = np.minimum(axes, [0.5 * L[0] - 0.25 * h, 0.5 * L[1] - 0.25 * h, L[2] - 0.25 * h])
+    centre = np.array([0.5 * L[0], 0.5 * L[1], L[2]])
+    s, X, Y, Z = _shell_s(nx, ny, nz, h, axes, centre)
+    inside = (s <= 1.0) & (Z <= 0.0)
+    target = active_frac * s.size
+    lo, hi = 0.0, 1.0
+    for _ in range(60):
+        mid = 0.5 * (lo + hi)
+        cnt = np.count_nonzero(inside & (s >= mid))
+        if cnt > target:
+            lo = mid
+        else:
+            hi = mid
+    s_in = 0.5 * (lo + hi)
+    mask = (inside & (s >= s_in)).astype(np.uint8)
+    frac = mask.mean()
+    if abs(frac - active_frac) > tol:
+        raise RuntimeError(f"cup_shell: active fraction {frac:.4f} misses {active_frac}")
+    e = (s - s_in) / (1.0 - s_in)
+    gx, gy, gz = X / axes[0] ** 2, Y / axes[1] ** 2, Z / axes[2] ** 2
+    fibre = _fibres_from_normal(gx, gy, gz, e)
+    fibre[mask == 0] = 0.0
+    apex = centre - np.array([0.0, 0.0, axes[2]])
+    return dict(mask=mask, fibre=fibre, apex=apex, s_in=s_in, axes=axes, centre=centre)
+
+
+def region_near(mask, h, point_mm, radius_mm):
+    """uint8 region: tissue voxels whose centre lies within radius of a point."""
+    nz, ny, nx = mask.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    d2 = (((x + 0.5) * h - point_mm[0]) ** 2 + ((y + 0.5) * h - point_mm[1]) ** 2
+          + ((z + 0.5) * h - point_mm[2]) ** 2)
+    return ((d2 <= radius_mm ** 2) & (mask != 0)).astype(np.uint8)
+
+
+# The 3D CRN workload: 128x128x64 cup at 35% active, D_par 0.3, D_perp 0.03 mm^2/ms,
+# h 0.25 mm, dt 0.01 ms, 2 ms of 40 pA/pF at the apex, 500 ms.
+CRN_3D = dict(nx=128, ny=128, nz=64, h=0.25, dt=0.01, Dpar=0.3, Dperp=0.03, active=0.35,
+              stim_amp=40.0, stim_ms=2.0, t_end=500.0, seed=1, theta=-40.0)
+
+
+def crn_cup(nx=128, ny=128, nz=64, seed=1, active=0.35, h=0.25):
+    """Geometry, stimulus region (within 1 mm of the apex) and the uniform
+    resting initial state of the 3D CRN workload."""
+    g = cup_shell(nx, ny, nz, h, active, seed)
+    stim = region_near(g["mask"], h, g["apex"], 1.0)
+    if stim.sum() == 0:
+        raise RuntimeError("crn_cup: empty stimulus region")
+    state = np.stack([np.full(g["mask"].shape, v) for v in CRN_INITIAL])
+    state[:, g["mask"] == 0] = 0.0
+    g.update(stim=stim, state=state)
+    return g
+
+
+def full_box_rotating(nx, ny, nz, angle_lo=-60.0, angle_hi=60.0):
+    """All-tissue box; fibres lie in the xy plane at an angle rotating linearly
+    with z from angle_lo to angle_hi degrees."""
+    mask = np.ones((nz, ny, nx), np.uint8)
+    zz = (np.arange(nz) + 0.5) / nz if nz > 1 else np.array([0.5])
+    a = np.deg2rad(angle_lo + (angle_hi - angle_lo) * zz)
+    fibre = np.zeros((nz, ny, nx, 3))
+    fibre[..., 0] = np.cos(a)[:, None, None]
+    fibre[..., 1] = np.sin(a)[:, None, None]
+    return mask, fibre
+
+
+def random_blob_mask(nx, ny, nz, seed, frac=0.6, smooth=2):
+    """Smooth random tissue blob (a thresholded, box-filtered noise field)."""
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal((nz, ny, nx))
+    for ax in range(3):
+        if f.shape[ax] > 1:
+            for _ in range(smooth):
+                f = (np.roll(f, 1, ax) + f + np.roll(f, -1, ax)) / 3.0
+    thr = np.quantile(f, 1.0 - frac)
+    return (f >= thr).astype(np.uint8)
+
+
+def random_fibres(shape, seed):
+    """Unit fibre vectors of random direction at every voxel."""
+    rng = np.random.default_rng(seed)
+    f = rng.standard_normal(tuple(shape) + (3,))
+    return f / np.linalg.norm(f, axis=-1, keepdims=True)

@@ -1,0 +1,261 @@
+"""Pins of the oracle's kinetics and time stepping: forward Euler on a linear
+test system (eq (Euler)), Rush-Larsen exactness for frozen voltage (eqs (RL),
+(RLcoeff), corrected order), first-order convergence of the coupled
+Euler/Rush-Larsen stepper to an accurate ODE solution, the special cases of
+the Barkley / FHN / ZFK kinetics, and the published resting state and action
+potential of the Courtemanche-Ramirez-Nattel model."""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import oracle as O
+from paper_1605_06015_amd import workloads as WL
+
+ONE = np.ones((1, 1, 1), np.uint8)
+
+
+def cell(model, params, y0, dt, stim=None):
+    s = O.Sim(ONE, 1.0, None, 1.0, 1.0, model, list(params), dt)
+    for i, v in enumerate(y0):
+        s.set_state(i, v)
+    if stim:
+        s.stimuli.extend(stim)
+    return s
+
+
+def test_euler_linear_test_system():
+    """Two coupled voxels: d' = -2 w d with w = D/h^2; forward Euler gives (1 - 2 k w)^n exactly."""
+    mask = np.ones((1, 1, 2), np.uint8)
+    D, h, k = 0.7, 0.5, 0.05
+    s = O.Sim(mask, h, None, D, D, O.MODEL_NONE, [], k)
+    s.set_state(0, np.array([[[1.0, -0.25]]]))
+    for n in range(1, 40):
+        s.step(1)
+        v = s.state[0, 0, 0]
+        w = D / h ** 2
+        assert abs((v[0] - v[1]) - 1.25 * (1 - 2 * k * w) ** n) < 1e-14
+        assert abs(v.sum() - 0.75) < 1e-14
+
+
+def crn_state(V=-60.0):
+    y = np.array(WL.CRN_INITIAL, float)
+    y[0] = V
+    return y
+
+
+@pytest.mark.parametrize("V", [-85.0, -47.13, -20.0, 7.9, 30.0])
+def test_rush_larsen_exact_for_frozen_voltage(V):
+    """One oracle step of the gates equals the exact solution of y' = (yinf - y)/tau with
+    the coefficients frozen at V_n, integrated by an independent high-accuracy solver."""
+    y0 = crn_state(V)
+    dt = 0.05
+    rate, inf, tau = O.model_eval(O.MODEL_CRN, [], y0)
+    s = cell(O.MODEL_CRN, [], y0, dt)
+    s.step(1)
+    y1 = s.state[:, 0, 0, 0]
+    for i in range(6, 21):
+        sol = solve_ivp(lambda t, y: (inf[i] - y) / tau[i], (0, dt), [y0[i]],
+                        method="DOP853", rtol=1e-13, atol=1e-16)
+        assert abs(y1[i] - sol.y[0, -1]) <= 1e-11 * max(1.0, abs(y0[i])), i
+    # non-gates: forward Euler with the kinetic rates
+    for i in range(0, 6):
+        assert abs(y1[i] - (y0[i] + dt * rate[i])) <= 1e-13 * max(1.0, abs(y0[i]))
+
+
+def test_rush_larsen_unconditionally_bounded():
+    for V in (-90.0, -40.0, 0.0, 40.0):
+        y0 = crn_state(V)
+        _, _, tau = O.model_eval(O.MODEL_CRN, [], y0)
+        s = cell(O.MODEL_CRN, [], y0, 100.0 * tau[6:].max())
+        s.step(1)
+        g = s.state[6:, 0, 0, 0]
+        assert np.all(g >= 0.0) and np.all(g <= 1.0)
+
+
+def _converge(model, params, y0, T, dts, stim_amp=0.0, stim_ms=0.0):
+    """Max-norm error of the oracle's stepper at time T vs a tight implicit ODE solve of
+    the same kinetics (gates as y' = (inf - y)/tau)."""
+    nv = len(y0)
+    gate = np.zeros(nv, bool)
+    if model == O.MODEL_CRN:
+        gate[6:] = True
+
+    def rhs(t, y):
+        r, inf, tau = O.model_eval(model, params, y)
+        d = r.copy()
+        d[gate] = (inf[gate] - y[gate]) / tau[gate]
+        if t < stim_ms:
+            d[0] += stim_amp
+        return d
+
+    ref = solve_ivp(rhs, (0, T), y0, method="Radau", rtol=1e-11, atol=1e-13,
+                    max_step=stim_ms if stim_ms else np.inf)
+    scale = np.maximum(np.abs(ref.y).max(axis=1), 1e-12)
+    errs = []
+    for dt in dts:
+        st = []
+        if stim_amp:
+            st = [O.Stimulus(ONE, stim_amp, 0, int(round(stim_ms / dt)))]
+        s = cell(model, params, y0, dt, st)
+        s.step(int(round(T / dt)))
+        errs.append(np.max(np.abs(s.state[:, 0, 0, 0] - ref.y[:, -1]) / scale))
+    return np.array(errs)
+
+
+@pytest.mark.parametrize("model,params,y0,T", [
+    (O.MODEL_BARKLEY, (0.75, 0.02, 0.02), (0.6, 0.1), 0.5),
+    (O.MODEL_FHN, (0.3, 0.7, 0.5), (1.5, -0.3), 3.0),
+    (O.MODEL_ZFK, (0.13,), (0.4,), 3.0),
+])
+def test_first_order_convergence_simple_models(model, params, y0, T):
+    e = _converge(model, list(params), np.array(y0, float), T, [1e-3, 5e-4, 2.5e-4])
+    order = np.log2(e[:-1] / e[1:])
+    assert np.all(order > 0.85) and np.all(order < 1.15), (e, order)
+
+
+def test_first_order_convergence_crn_upstroke():
+    y0 = np.array(WL.CRN_INITIAL, float)
+    e = _converge(O.MODEL_CRN, [], y0, 5.0, [4e-3, 2e-3, 1e-3], stim_amp=20.0, stim_ms=2.0)
+    order = np.log2(e[:-1] / e[1:])
+    assert np.all(order > 0.8) and np.all(order < 1.25), (e, order)
+
+
+def _roots(f, lo, hi, n=4001):
+    x = np.linspace(lo, hi, n)
+    fx = np.array([f(v) for v in x])
+    r = []
+    for i in range(n - 1):
+        if fx[i] == 0.0:
+            r.append(x[i])
+        elif fx[i] * fx[i + 1] < 0:
+            a, b = x[i], x[i + 1]
+            for _ in range(80):
+                m = 0.5 * (a + b)
+                if f(a) * f(m) <= 0:
+                    b = m
+                else:
+                    a = m
+            r.append(0.5 * (a + b))
+    return np.array(r)
+
+
+def test_barkley_special_cases():
+    a, b, eps = 0.75, 0.02, 0.02
+    p = [a, b, eps]
+    for v in (0.0, 0.3, 0.55):
+        r = _roots(lambda u: O.model_eval(O.MODEL_BARKLEY, p, [u, v])[0][0], -0.5, 1.5)
+        np.testing.assert_allclose(np.sort(r), np.sort([0.0, (v + b) / a, 1.0]), atol=1e-10)
+        # cubic with leading coefficient -1/eps
+        us = np.linspace(-1, 2, 9)
+        c = np.polyfit(us, [O.model_eval(O.MODEL_BARKLEY, p, [u, v])[0][0] for u in us], 3)
+        assert abs(c[0] + 1.0 / eps) < 1e-8 / eps
+    # u fixed at 0 or 1: v relaxes to u; forward Euler gives the geometric sequence
+    k = 0.01
+    for u in (0.0, 1.0):
+        s = cell(O.MODEL_BARKLEY, p, [u, 0.3], k)
+        s.step(50)
+        assert abs(s.state[0, 0, 0, 0] - u) == 0.0
+        assert abs(s.state[1, 0, 0, 0] - (u + (0.3 - u) * (1 - k) ** 50)) < 1e-14
+
+
+def test_fhn_special_cases():
+    eps, bet, gam = 0.3, 0.7, 0.5
+    p = [eps, bet, gam]
+    r = _roots(lambda u: O.model_eval(O.MODEL_FHN, p, [u, 0.0])[0][0], -3, 3)
+    np.testing.assert_allclose(np.sort(r), [-np.sqrt(3), 0.0, np.sqrt(3)], atol=1e-10)
+    r0 = O.model_eval(O.MODEL_FHN, p, [0.4, 0.0])[0]
+    r1 = O.model_eval(O.MODEL_FHN, p, [0.4, 1.0])[0]
+    assert abs((r1[0] - r0[0]) + 1.0 / eps) < 1e-12          # du'/dv = -1/eps
+    assert abs((r1[1] - r0[1]) + eps * gam) < 1e-12          # dv'/dv = -eps gamma
+    assert abs(O.model_eval(O.MODEL_FHN, p, [-bet, 0.0])[0][1]) < 1e-15
+    assert abs(O.model_eval(O.MODEL_FHN, p, [1.0 - bet, 0.0])[0][1] - eps) < 1e-14
+
+
+def test_zfk_roots():
+    al = 0.13
+    r = _roots(lambda V: O.model_eval(O.MODEL_ZFK, [al], [V])[0][0], -0.5, 1.5)
+    np.testing.assert_allclose(r, [0.0, al, 1.0], atol=1e-10)
+
+
+def test_crn_resting_state_is_steady():
+    y0 = np.array(WL.CRN_INITIAL, float)
+    rate, inf, tau = O.model_eval(O.MODEL_CRN, [], y0)
+    assert abs(rate[0]) < 2e-3                          # net ionic current ~ 0 at rest
+    for i in (6, 7, 8, 9, 10, 11, 12, 15, 16, 17):      # fast gates sit at steady state
+        assert abs(y0[i] - inf[i]) < 0.02 * max(inf[i], 1e-3) + 1e-4, (WL.CRN_NAMES[i], y0[i], inf[i])
+    s = cell(O.MODEL_CRN, [], y0, 0.01)
+    s.step(10000)                                       # 100 ms without stimulus
+    assert abs(s.state[0, 0, 0, 0] - y0[0]) < 0.05
+
+
+def test_crn_action_potential_shape():
+    """2 ms, 20 pA/pF stimulus (the model publication's protocol): overshoot, APD90 and
+    calcium transient in the ranges that publication reports."""
+    y0 = np.array(WL.CRN_INITIAL, float)
+    s = cell(O.MODEL_CRN, [], y0, 0.01, [O.Stimulus(ONE, 20.0, 0, 200)])
+    s.start_recording(-40.0)
+    V, Ca = [], []
+    for _ in range(4000):
+        s.step(10)
+        V.append(s.state[0, 0, 0, 0])
+        Ca.append(s.state[3, 0, 0, 0])
+    V, Ca = np.array(V), np.array(Ca)
+    assert 15.0 < V.max() < 35.0
+    assert 270.0 < s.rec.apd[0] < 340.0
+    assert 0.5e-3 < Ca.max() < 1.2e-3
+    assert -82.0 < V[-1] < -77.0
+    assert s.rec.status[0] == 3 and 0.5 < s.rec.at[0] < 2.5
+
+
+@pytest.mark.parametrize("Vs", [-47.13, -14.1, 3.3328, 19.9, -10.0, 7.9])
+def test_crn_removable_singularities_continuous(Vs):
+    y = crn_state(Vs)
+    r0, i0, t0 = O.model_eval(O.MODEL_CRN, [], y)
+    for d in (1e-7, 1e-5):
+        ym, yp = crn_state(Vs - d), crn_state(Vs + d)
+        rm, im, tm = O.model_eval(O.MODEL_CRN, [], ym)
+        rp, ip, tp = O.model_eval(O.MODEL_CRN, [], yp)
+        np.testing.assert_allclose(t0[6:], 0.5 * (tm[6:] + tp[6:]), rtol=1e-7)
+        assert np.all(np.isfinite(t0)) and np.all(np.isfinite(r0))
+
+
+def test_stimulus_windows_brute_force():
+    dt, A = 0.5, 1.25
+    st = O.Stimulus(ONE, A, n0=3, length=2, period=5, count=3)
+    s = cell(O.MODEL_NONE, [], [0.0], dt, [st])
+    expected = 0.0
+    for n in range(30):
+        on = any(3 + 5 * c <= n < 3 + 5 * c + 2 for c in range(3))
+        expected += dt * A * on
+        s.step(1)
+        assert s.state[0, 0, 0, 0] == pytest.approx(expected, abs=1e-14)
+    s2 = cell(O.MODEL_NONE, [], [0.0], dt, [O.Stimulus(ONE, A, 4, 3, 0, 1)])
+    s2.step(20)
+    assert s2.state[0, 0, 0, 0] == pytest.approx(3 * dt * A, abs=1e-14)
+
+
+def test_recording_piecewise_linear():
+    """V rises at slope 2 for 1 time unit, then falls at slope 1: AT, peak and APD90 are
+    known exactly (threshold 0.5, rest 0)."""
+    dt = 0.1
+    st = [O.Stimulus(ONE, 2.0, 0, 10), O.Stimulus(ONE, -1.0, 10, 100)]
+    s = cell(O.MODEL_NONE, [], [0.0], dt, st)
+    s.start_recording(0.5)
+    s.step(60)
+    r = s.rec
+    assert r.status[0] == 3
+    assert r.at[0] == pytest.approx(0.25, abs=1e-12)
+    assert r.vmax[0] == pytest.approx(2.0, abs=1e-12)
+    assert r.apd[0] == pytest.approx(2.8 - 0.25, abs=1e-12)
+
+
+def test_threads_bitwise_equal_serial():
+    g = WL.crn_cup(32, 32, 16, seed=5)
+    outs = []
+    for nt in (1, 4):
+        s = O.Sim(g["mask"], 1.0, g["fibre"], 0.3, 0.03, O.MODEL_CRN, [], 0.01, nthreads=nt)
+        s.state[:] = g["state"]
+        s.stimuli.append(O.Stimulus(g["stim"], 40.0, 0, 200))
+        s.step(30)
+        outs.append(s.state.copy())
+    assert np.array_equal(outs[0], outs[1])
