@@ -1,0 +1,206 @@
+#!/usr/bin/env python3
+"""Benchmark of the monodomain step on one MI355X.
+
+A "step" is one pass of the whole hot path over the 3D atrial workload: the
+fused anisotropic 19-point no-flux stencil + Courtemanche-Ramirez-Nattel
+kinetics (Euler + Rush-Larsen) + stimulus + activation-time/APD90 recording,
+FP32, on a 128x128x64 ellipsoidal-cup tissue at 35% active (367,000 tissue
+voxels), dt 0.01 ms.  Inputs are resident in HBM before timing starts; the
+timed region is K steps bracketed by synchronisations, timed with HIP events
+on the stream the kernels are launched on.
+
+Prints ONE JSON line (see the keys below).  --gpus N>1 is refused: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-updates/s (FP32 plain vs surrogate) at ≤1dt activation-time error; %HBM roof"
+HBM_PEAK_GBS = 8000.0
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+STEP_SOURCES = [os.path.join(ROOT, "paper_1605_06015_amd", "csrc", f)
+                for f in ("step_kernels.hip", "kinetics.h", "bbx_internal.h")]
+
+# Algorithmic HBM bytes per tissue-voxel update of the fused CRN step in FP32:
+# 21 state values read + 21 written (4 B each) + geometry (box index 4, neighbour
+# bits 4, unit fibre 12, tensor-gradient face coefficients 12) + status byte 1.
+CRN_BYTES_PER_VOXEL = 21 * 4 * 2 + 32 + 1
+# Pure-diffusion stencil, FP32, dense anisotropic box: V read + V written + fibre +
+# face coefficients (no index / bit arrays on a dense box).
+STENCIL_BYTES_PER_VOXEL = 4 + 4 + 12 + 12
+
+
+def source_hash(paths=STEP_SOURCES) -> str:
+    h = hashlib.sha256()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(name: str, bytes_alg: float):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were taken
+    on the current kernel sources; else None."""
+    path = os.path.join(PROFILE_DIR, name)
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def time_steps(grid, stream, steps, warmup):
+    import torch
+    grid.step(warmup)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    grid.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3  # seconds
+
+
+def crn_workload(precision, stream):
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.CRN_3D
+    g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
+    grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], precision, stream)
+    grid.model(B.BBX_MODEL_CRN, [], c["dt"])
+    for v in range(21):
+        grid.set(v, g["state"][v])
+    grid.stimulus(g["stim"], c["stim_amp"], 0.0, c["stim_ms"])
+    grid.record(c["theta"])
+    return grid, g
+
+
+def cpu_baseline(seconds_target=12.0):
+    """The FP64 oracle on the same workload, timed on this host's cores over a bounded
+    number of steps (per-step time by differencing two runs)."""
+    from oracle import oracle as O
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.CRN_3D
+    g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except Exception:
+        ncpu = os.cpu_count() or 1
+    nthreads = max(1, min(16, ncpu))
+    s = O.Sim(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], O.MODEL_CRN, [], c["dt"],
+              nthreads=nthreads)
+    s.state[:] = g["state"]
+    s.stimuli.append(O.Stimulus(g["stim"], c["stim_amp"], 0, int(round(c["stim_ms"] / c["dt"]))))
+    t0 = time.perf_counter()
+    s.step(2)
+    t1 = time.perf_counter()
+    per = max((t1 - t0) / 2, 1e-4)
+    n1 = 2
+    n2 = n1 + max(4, int(seconds_target / per))
+    t2 = time.perf_counter()
+    s.step(n2 - n1)
+    t3 = time.perf_counter()
+    per_step = (t3 - t2) / (n2 - n1)
+    nact = int(g["mask"].sum())
+    return {"value": nact / per_step, "unit": "voxel-updates/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"CRN 128x128x64 cup ({nact} tissue voxels), FP64 oracle, {n2 - n1} steps "
+                      f"after 2 warm-up steps, {t3 - t2:.1f} s, OpenMP over voxels"}
+
+
+def stencil_roofline(stream, steps=100, warmup=10):
+    """Pure-diffusion FP32 stencil on a dense 512x512x384 box with fibres rotating
+    through z (the HBM roofline workload: V is 403 MB, beyond the Infinity Cache)."""
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    nx, ny, nz = 512, 512, 384
+    mask, fib = WL.full_box_rotating(nx, ny, nz)
+    grid = B.Grid(mask, 0.2, fib, 0.3, 0.03, B.BBX_FP32, stream)
+    del fib
+    grid.model(B.BBX_MODEL_NONE, [], 0.01)
+    grid.set(0, np.linspace(-80, 20, mask.size).reshape(mask.shape))
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, steps, warmup)
+    nact = grid.nact
+    grid.close()
+    per_launch = sec / steps
+    gbs = STENCIL_BYTES_PER_VOXEL * nact / per_launch / 1e9
+    return {"workload": "pure diffusion, dense 512x512x384, 19-point, rotating fibres, FP32",
+            "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": STENCIL_BYTES_PER_VOXEL,
+            "us_per_launch": round(per_launch * 1e6, 2),
+            "voxel_updates_per_s": nact / per_launch}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the stencil roofline run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+
+    grid, g = crn_workload(B.BBX_FP32, stream)
+    grid.nan_check(0)
+    nact = grid.nact
+    sec = time_steps(grid, stream, args.steps, args.warmup)
+    flag = grid.read(B.BBX_READ_NAN_FLAG)[0]
+    if flag:
+        print("bench.py: non-finite state", file=sys.stderr)
+        sys.exit(1)
+    ms_per_step = sec / args.steps * 1e3
+    value = nact * args.steps / sec
+    per_launch = sec / args.steps
+    achieved = CRN_BYTES_PER_VOXEL * nact / per_launch / 1e9
+    traffic = measured_traffic("step_crn_cup128_fp32_traffic.json", CRN_BYTES_PER_VOXEL * nact)
+    out = {
+        "metric": METRIC, "value": value, "unit": "voxel-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "CRN atrial 3D, 128x128x64 ellipsoidal cup, 35% active "
+                               f"({nact} tissue voxels), 19-point anisotropic no-flux stencil, "
+                               "rotating fibres, dt 0.01 ms, apex stimulus, AT/APD90 recording, "
+                               "FP32 plain ionic", "tissue_voxels": nact, "dt_ms": 0.01},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "kernel": "k_step<float, Crn, aniso>",
+                     "bytes_per_voxel": CRN_BYTES_PER_VOXEL,
+                     "us_per_launch": round(per_launch * 1e6, 2)},
+    }
+    grid.close()
+    if not args.no_extras:
+        out["stencil_roofline"] = stencil_roofline(stream)
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,795 @@
+// Host side of libbbx: argument validation, one-off geometry preprocessing in
+// FP64, device allocation, per-step launch sequencing and readout.  Every
+// entry point catches everything: no C++ exception crosses the C ABI.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/bbx.h"
+#include "bbx_internal.h"
+
+using namespace bbx;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(e == hipErrorOutOfMemory ? BBX_ENOMEM : BBX_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                      \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+int model_nvar(int m)
+{
+    switch (m) {
+    case BBX_MODEL_NONE: return 1;
+    case BBX_MODEL_BARKLEY: return 2;
+    case BBX_MODEL_ZFK: return 1;
+    case BBX_MODEL_FHN: return 2;
+    case BBX_MODEL_CRN: return 21;
+    default: return -1;
+    }
+}
+
+int model_nparams(int m)
+{
+    switch (m) {
+    case BBX_MODEL_NONE: return 0;
+    case BBX_MODEL_BARKLEY: return 3;
+    case BBX_MODEL_ZFK: return 1;
+    case BBX_MODEL_FHN: return 3;
+    case BBX_MODEL_CRN: return 0;
+    default: return -1;
+    }
+}
+
+// Nearest integer, halves away from zero (the rounding of stimulus windows).
+int64_t steps_of(double t, double dt) { return (int64_t)llround(t / dt); }
+
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+};
+
+}  // namespace
+
+struct StimDef {
+    double amp, t0, dur, period;
+    int count;
+};
+
+struct bbx_grid {
+    int nx = 0, ny = 0, nz = 0;
+    int64_t nbox = 0, nact = 0, pitch = 0;
+    double h = 0, Dpar = 0, Dperp = 0;
+    int prec = 0, es = 4;
+    int aniso = 0, dense = 0;
+    hipStream_t stream = nullptr;
+    double wsum_max = 0;  // max_p sum_q |W^p_q| including the centre
+
+    int32_t *d_idx = nullptr;
+    uint32_t *d_nbr = nullptr;
+    void *d_fib = nullptr, *d_gt = nullptr;
+    void *d_V[2] = {nullptr, nullptr};
+    int cur = 0;
+    void *d_st = nullptr;
+    int st_alloc = 0;  // variables allocated in d_st
+
+    int model = -1, nvar = 1, scheme = 0;
+    double dt = 0, prm[kMaxParams] = {};
+
+    std::vector<StimDef> stims;
+    std::vector<uint32_t> h_stimbits;
+    uint32_t *d_stimbits = nullptr;
+    void *d_stimamp = nullptr;
+
+    int rec = 0;
+    double theta = NAN;
+    uint8_t *d_status = nullptr;
+    void *d_at = nullptr, *d_vmax = nullptr, *d_apd = nullptr, *d_vrep = nullptr;
+
+    int64_t n = 0, nan_every = 1000;
+    double *d_parts = nullptr, *d_red = nullptr;
+    int *d_flag = nullptr;
+    int nparts = 1024;
+    size_t bytes = 0;
+};
+
+namespace {
+
+template <typename P>
+hipError_t dalloc(bbx_grid *g, P **p, size_t bytes)
+{
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, bytes ? bytes : 1);
+    if (e == hipSuccess) {
+        *p = (P *)q;
+        g->bytes += bytes;
+    }
+    return e;
+}
+
+void dfree(void *p)
+{
+    if (p) (void)hipFree(p);
+}
+
+void free_all(bbx_grid *g)
+{
+    void *ps[] = {g->d_idx, g->d_nbr, g->d_fib, g->d_gt, g->d_V[0], g->d_V[1], g->d_st,
+                  g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
+                  g->d_vrep, g->d_parts, g->d_red, g->d_flag};
+    for (void *p : ps) dfree(p);
+}
+
+// Unit fibre at a box voxel (caller checked it is tissue and normalisable).
+inline void unit_fibre(const double *fib, int64_t idx, double f[3])
+{
+    const double *v = fib + 3 * idx;
+    const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    f[0] = v[0] / n;
+    f[1] = v[1] / n;
+    f[2] = v[2] / n;
+}
+
+inline void tensor(const double f[3], double Dpar, double Dperp, double D[3][3])
+{
+    for (int j = 0; j < 3; j++)
+        for (int k = 0; k < 3; k++) D[j][k] = (j == k ? Dperp : 0.0) + (Dpar - Dperp) * f[j] * f[k];
+}
+
+template <typename T>
+StepArgs<T> make_args(const bbx_grid *g)
+{
+    StepArgs<T> a;
+    memset(&a, 0, sizeof a);
+    a.nx = g->nx;
+    a.ny = g->ny;
+    a.nz = g->nz;
+    a.dense = g->dense;
+    a.nact = g->nact;
+    a.pitch = g->pitch;
+    a.idx = g->d_idx;
+    a.nbr = g->d_nbr;
+    a.fib = (const T *)g->d_fib;
+    a.gt = (const T *)g->d_gt;
+    a.Dpar = (T)g->Dpar;
+    a.Dperp = (T)g->Dperp;
+    a.ih2 = (T)(1.0 / (g->h * g->h));
+    a.st = (T *)g->d_st;
+    for (int i = 0; i < kMaxParams; i++) a.prm[i] = (T)g->prm[i];
+    a.dt = (T)g->dt;
+    a.split = g->scheme == BBX_SCHEME_SPLIT;
+    a.nstim = (int)g->stims.size();
+    a.stimbits = g->d_stimbits;
+    a.stim_amp = (const T *)g->d_stimamp;
+    a.rec = g->rec;
+    a.theta = (T)g->theta;
+    a.status = g->d_status;
+    a.at = (T *)g->d_at;
+    a.vmax = (T *)g->d_vmax;
+    a.apd = (T *)g->d_apd;
+    a.vrep = (T *)g->d_vrep;
+    a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
+    a.per_xcd = (a.nblk + kXcd - 1) / kXcd;
+    return a;
+}
+
+uint32_t stim_mask(const bbx_grid *g, int64_t n)
+{
+    uint32_t m = 0;
+    for (size_t k = 0; k < g->stims.size(); k++) {
+        const StimDef &s = g->stims[k];
+        const int64_t n0 = steps_of(s.t0, g->dt), len = steps_of(s.dur, g->dt);
+        const int64_t per = s.period > 0 ? steps_of(s.period, g->dt) : 0;
+        if (n < n0 || len <= 0) continue;
+        const int64_t r = n - n0;
+        bool on;
+        if (per <= 0) {
+            on = r < len;
+        } else {
+            const int64_t c = r / per;
+            on = !(s.count > 0 && c >= s.count) && (r - c * per) < len;
+        }
+        if (on) m |= 1u << k;
+    }
+    return m;
+}
+
+template <typename T>
+int step_impl(bbx_grid *g, int64_t nsteps)
+{
+    StepArgs<T> a = make_args<T>(g);
+    const int nst = g->nvar - 1;
+    if (g->nan_every > 0) HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), g->stream), "hipMemsetAsync");
+    for (int64_t s = 0; s < nsteps; s++) {
+        const int64_t n = g->n + s;
+        a.Vin = (const T *)g->d_V[g->cur];
+        a.Vout = (T *)g->d_V[g->cur ^ 1];
+        a.stim_on = g->stims.empty() ? 0u : stim_mask(g, n);
+        a.tn = (T)((double)n * g->dt);
+        if (g->nact > 0) HIP_TRY(launch_step<T>(g->model, g->aniso, a, g->stream), "step launch");
+        g->cur ^= 1;
+        if (g->nan_every > 0 && (n + 1) % g->nan_every == 0)
+            HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense,
+                                        (const T *)g->d_st, nst, g->nact, g->pitch, g->d_flag,
+                                        g->stream),
+                    "finite check");
+    }
+    g->n += nsteps;
+    if (g->nan_every > 0) {
+        HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense,
+                                    (const T *)g->d_st, nst, g->nact, g->pitch, g->d_flag,
+                                    g->stream),
+                "finite check");
+        int flag = 0;
+        HIP_TRY(hipMemcpyAsync(&flag, g->d_flag, sizeof(int), hipMemcpyDeviceToHost, g->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        if (flag) return fail(BBX_ENUMERIC, "non-finite state value after step %lld",
+                              (long long)g->n);
+    }
+    return BBX_OK;
+}
+
+// Host array of T from doubles, in tissue order or box order (void = 0).
+template <typename T>
+std::vector<T> convert(const bbx_grid *g, const std::vector<int64_t> *act, const double *src,
+                       int box_order)
+{
+    std::vector<T> out(box_order ? (size_t)g->nbox : (size_t)g->nact, T(0));
+    for (int64_t t = 0; t < g->nact; t++) {
+        const int64_t b = act ? (*act)[t] : t;
+        out[box_order ? b : t] = (T)src[b];
+    }
+    return out;
+}
+
+std::vector<int64_t> tissue_list(const bbx_grid *g, const int32_t *h_idx)
+{
+    std::vector<int64_t> act((size_t)g->nact);
+    for (int64_t t = 0; t < g->nact; t++) act[t] = g->dense ? t : h_idx[t];
+    return act;
+}
+
+int download_idx(const bbx_grid *g, std::vector<int32_t> &h_idx)
+{
+    h_idx.clear();
+    if (g->dense) return BBX_OK;
+    h_idx.resize((size_t)g->nact);
+    HIP_TRY(hipMemcpyAsync(h_idx.data(), g->d_idx, g->nact * sizeof(int32_t),
+                           hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    return BBX_OK;
+}
+
+template <typename T>
+int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
+{
+    // tissue list (increasing box order)
+    std::vector<int32_t> idx;
+    idx.reserve((size_t)g->nbox);
+    for (int64_t b = 0; b < g->nbox; b++)
+        if (mask[b]) idx.push_back((int32_t)b);
+    g->nact = (int64_t)idx.size();
+    g->dense = g->nact == g->nbox;
+    g->pitch = (g->nact + 63) / 64 * 64;
+
+    auto tissue = [&](int x, int y, int z) -> bool {
+        if (x < 0 || y < 0 || z < 0 || x >= g->nx || y >= g->ny || z >= g->nz) return false;
+        return mask[(int64_t)x + (int64_t)g->nx * ((int64_t)y + (int64_t)g->ny * z)] != 0;
+    };
+
+    std::vector<uint32_t> nbr((size_t)g->nact);
+    std::vector<T> fib, gt;
+    if (g->aniso) {
+        fib.assign((size_t)(3 * g->pitch), T(0));
+        gt.assign((size_t)(3 * g->pitch), T(0));
+    }
+    const double ih2 = 1.0 / (g->h * g->h);
+    double wmax = 0;
+    for (int64_t t = 0; t < g->nact; t++) {
+        const int64_t b = idx[t];
+        const int x = (int)(b % g->nx), y = (int)((b / g->nx) % g->ny);
+        const int z = (int)(b / ((int64_t)g->nx * g->ny));
+        uint32_t bits = 0;
+        for (int k = 0; k < 18; k++) {
+            const NbOff o = nb_off(k);
+            if (tissue(x + o.dx, y + o.dy, z + o.dz)) bits |= 1u << k;
+        }
+        nbr[t] = bits;
+        double D[3][3] = {{g->Dperp, 0, 0}, {0, g->Dperp, 0}, {0, 0, g->Dperp}};
+        double c[3] = {0, 0, 0};
+        if (g->aniso) {
+            double f[3];
+            unit_fibre(fibre, b, f);
+            tensor(f, g->Dpar, g->Dperp, D);
+            // Tensor-gradient face coefficient: both face neighbours along k must be
+            // tissue; D at a void neighbour p +- q_j is replaced by D^p.
+            double Dn[3][2][3][3];
+            for (int j = 0; j < 3; j++)
+                for (int sgn = 0; sgn < 2; sgn++) {
+                    const NbOff o = nb_off(2 * j + sgn);
+                    if ((bits >> (2 * j + sgn)) & 1u) {
+                        double fn[3];
+                        unit_fibre(fibre, b + o.dx + (int64_t)g->nx * (o.dy + (int64_t)g->ny * o.dz), fn);
+                        tensor(fn, g->Dpar, g->Dperp, Dn[j][sgn]);
+                    } else {
+                        memcpy(Dn[j][sgn], D, sizeof D);
+                    }
+                }
+            for (int k = 0; k < 3; k++) {
+                if (((bits >> (2 * k)) & 3u) != 3u) continue;
+                double sdiv = 0;
+                for (int j = 0; j < 3; j++) sdiv += Dn[j][0][j][k] - Dn[j][1][j][k];
+                c[k] = 0.25 * ih2 * sdiv;
+            }
+            for (int k = 0; k < 3; k++) {
+                fib[k * g->pitch + t] = (T)f[k];
+                gt[k * g->pitch + t] = (T)c[k];
+            }
+        }
+        // Gershgorin radius of row p: |W_0| + sum |W_q| <= 2 sum |W_q|
+        double s = 0;
+        for (int k = 0; k < 18; k++) {
+            if (!((bits >> k) & 1u)) continue;
+            if (k < 6) {
+                const int ax = k / 2;
+                s += fabs(D[ax][ax] * ih2 + ((k & 1) ? -c[ax] : c[ax]));
+            } else if (g->aniso) {
+                const int plane = (k - 6) / 4;
+                const int j = plane == 2 ? 1 : 0, kk = plane == 0 ? 1 : 2;
+                s += fabs(0.5 * D[j][kk] * ih2);
+            }
+        }
+        wmax = fmax(wmax, 2.0 * s);
+    }
+    g->wsum_max = wmax;
+
+    const size_t es = sizeof(T);
+    hipError_t e = hipSuccess;
+    if (!g->dense) {
+        if ((e = dalloc(g, &g->d_idx, g->nact * sizeof(int32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = dalloc(g, &g->d_nbr, g->nact * sizeof(uint32_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
+        HIP_TRY(hipMemcpy(g->d_idx, idx.data(), g->nact * sizeof(int32_t), hipMemcpyHostToDevice), "hipMemcpy");
+        HIP_TRY(hipMemcpy(g->d_nbr, nbr.data(), g->nact * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    if (g->aniso) {
+        if ((e = dalloc(g, &g->d_fib, 3 * g->pitch * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if ((e = dalloc(g, &g->d_gt, 3 * g->pitch * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        HIP_TRY(hipMemcpy(g->d_fib, fib.data(), 3 * g->pitch * es, hipMemcpyHostToDevice), "hipMemcpy");
+        HIP_TRY(hipMemcpy(g->d_gt, gt.data(), 3 * g->pitch * es, hipMemcpyHostToDevice), "hipMemcpy");
+    }
+    for (int k = 0; k < 2; k++) {
+        if ((e = dalloc(g, &g->d_V[k], g->nbox * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        HIP_TRY(hipMemset(g->d_V[k], 0, g->nbox * es), "hipMemset");
+    }
+    if ((e = dalloc(g, &g->d_parts, g->nparts * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = dalloc(g, &g->d_red, 8 * sizeof(double))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = dalloc(g, &g->d_flag, sizeof(int))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = dalloc(g, &g->d_stimamp, kMaxStim * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    HIP_TRY(hipMemset(g->d_stimamp, 0, kMaxStim * es), "hipMemset");
+    return BBX_OK;
+}
+
+template <typename T>
+int alloc_state(bbx_grid *g, int nvar)
+{
+    const int need = nvar - 1;
+    if (need != g->st_alloc) {
+        dfree(g->d_st);
+        g->d_st = nullptr;
+        g->st_alloc = 0;
+        if (need > 0) {
+            hipError_t e = dalloc(g, &g->d_st, (size_t)need * g->pitch * sizeof(T));
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+            g->st_alloc = need;
+        }
+    }
+    if (need > 0)
+        HIP_TRY(launch_fill<T>((T *)g->d_st, T(0), (int64_t)need * g->pitch, g->stream), "fill");
+    return BBX_OK;
+}
+
+template <typename T>
+int state_set_impl(bbx_grid *g, int var, const double *vals)
+{
+    std::vector<int32_t> h_idx;
+    int rc = download_idx(g, h_idx);
+    if (rc) return rc;
+    std::vector<int64_t> act = tissue_list(g, h_idx.data());
+    if (var == 0) {
+        std::vector<T> box = convert<T>(g, &act, vals, 1);
+        HIP_TRY(hipMemcpyAsync(g->d_V[g->cur], box.data(), g->nbox * sizeof(T),
+                               hipMemcpyHostToDevice, g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    } else {
+        std::vector<T> lst = convert<T>(g, &act, vals, 0);
+        T *dst = (T *)g->d_st + (int64_t)(var - 1) * g->pitch;
+        HIP_TRY(hipMemcpyAsync(dst, lst.data(), g->nact * sizeof(T), hipMemcpyHostToDevice,
+                               g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    }
+    return BBX_OK;
+}
+
+template <typename T>
+int recording_impl(bbx_grid *g, double theta)
+{
+    const size_t es = sizeof(T);
+    if (!g->d_status) {
+        hipError_t e;
+        if ((e = dalloc(g, &g->d_status, g->nact ? g->nact : 1)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        void **ps[] = {&g->d_at, &g->d_vmax, &g->d_apd, &g->d_vrep};
+        for (void **p : ps)
+            if ((e = dalloc(g, p, g->pitch * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    }
+    const T nan = (T)NAN;
+    HIP_TRY(launch_fill<uint8_t>(g->d_status, 0, g->nact, g->stream), "fill");
+    HIP_TRY(launch_fill<T>((T *)g->d_at, nan, g->nact, g->stream), "fill");
+    HIP_TRY(launch_fill<T>((T *)g->d_vmax, nan, g->nact, g->stream), "fill");
+    HIP_TRY(launch_fill<T>((T *)g->d_apd, nan, g->nact, g->stream), "fill");
+    HIP_TRY(launch_gather<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense, g->nact,
+                             (T *)g->d_vrep, g->stream), "gather");
+    g->theta = theta;
+    g->rec = 1;
+    return BBX_OK;
+}
+
+template <typename T>
+int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *out,
+                 size_t out_bytes, int on_dev)
+{
+    const int64_t nbox = g->nbox;
+    switch (what) {
+    case BBX_READ_VAR:
+    case BBX_READ_ACT_TIME:
+    case BBX_READ_APD90:
+    case BBX_READ_VMAX: {
+        if (out_bytes < (size_t)nbox * sizeof(double)) return fail(BBX_EINVAL, "out_bytes too small");
+        const T *src;
+        int is_box = 0;
+        if (what == BBX_READ_VAR) {
+            if (var < 0 || var >= g->nvar) return fail(BBX_EINVAL, "var %d out of range", var);
+            if (var == 0) { src = (const T *)g->d_V[g->cur]; is_box = 1; }
+            else src = (const T *)g->d_st + (int64_t)(var - 1) * g->pitch;
+        } else {
+            if (!g->d_status) return fail(BBX_ESTATE, "recording was never started");
+            src = (const T *)(what == BBX_READ_ACT_TIME ? g->d_at : what == BBX_READ_APD90 ? g->d_apd : g->d_vmax);
+        }
+        if (on_dev) {
+            HIP_TRY(launch_to_box<T>(src, is_box, g->d_idx, g->dense, g->nact, nbox, (double *)out, g->stream), "to_box");
+            return BBX_OK;
+        }
+        DevBuf tmp;
+        HIP_TRY(hipMalloc(&tmp.p, nbox * sizeof(double)), "hipMalloc");
+        HIP_TRY(launch_to_box<T>(src, is_box, g->d_idx, g->dense, g->nact, nbox, (double *)tmp.p, g->stream), "to_box");
+        HIP_TRY(hipMemcpyAsync(out, tmp.p, nbox * sizeof(double), hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    case BBX_READ_STATUS: {
+        if (on_dev) return fail(BBX_ENOTSUP, "STATUS is read to host memory only");
+        if (!g->d_status) return fail(BBX_ESTATE, "recording was never started");
+        if (out_bytes < (size_t)nbox) return fail(BBX_EINVAL, "out_bytes too small");
+        std::vector<uint8_t> st((size_t)g->nact);
+        std::vector<int32_t> h_idx;
+        int rc = download_idx(g, h_idx);
+        if (rc) return rc;
+        if (g->nact) {
+            HIP_TRY(hipMemcpyAsync(st.data(), g->d_status, g->nact, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+            HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        }
+        uint8_t *o = (uint8_t *)out;
+        memset(o, 255, (size_t)nbox);
+        for (int64_t t = 0; t < g->nact; t++) o[g->dense ? t : h_idx[t]] = st[t];
+        return BBX_OK;
+    }
+    case BBX_READ_REDUCE_MAX:
+    case BBX_READ_REDUCE_SUM: {
+        if (out_bytes < sizeof(double)) return fail(BBX_EINVAL, "out_bytes too small");
+        if (var < 0 || var >= g->nvar) return fail(BBX_EINVAL, "var %d out of range", var);
+        const T *src = var == 0 ? (const T *)g->d_V[g->cur] : (const T *)g->d_st + (int64_t)(var - 1) * g->pitch;
+        DevBuf reg;
+        if (region) {
+            HIP_TRY(hipMalloc(&reg.p, nbox), "hipMalloc");
+            HIP_TRY(hipMemcpyAsync(reg.p, region, nbox, hipMemcpyHostToDevice, g->stream), "hipMemcpyAsync");
+        }
+        HIP_TRY(launch_reduce<T>(src, var == 0, g->d_idx, g->dense, g->nact, (const uint8_t *)reg.p,
+                                 what == BBX_READ_REDUCE_SUM, g->d_parts, g->nparts, g->d_red, g->stream),
+                "reduce");
+        HIP_TRY(hipMemcpyAsync(out, g->d_red, sizeof(double),
+                               on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    case BBX_READ_NAN_FLAG: {
+        if (on_dev) return fail(BBX_ENOTSUP, "NAN_FLAG is read to host memory only");
+        if (out_bytes < sizeof(int32_t)) return fail(BBX_EINVAL, "out_bytes too small");
+        HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), g->stream), "hipMemsetAsync");
+        HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense, (const T *)g->d_st,
+                                    g->nvar - 1, g->nact, g->pitch, g->d_flag, g->stream), "finite check");
+        HIP_TRY(hipMemcpyAsync(out, g->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    case BBX_READ_STEP: {
+        if (on_dev) return fail(BBX_ENOTSUP, "STEP is read to host memory only");
+        if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
+        memcpy(out, &g->n, sizeof(int64_t));
+        return BBX_OK;
+    }
+    case BBX_READ_WEIGHTS: {
+        const size_t need = (size_t)g->nact * 27 * sizeof(double);
+        if (out_bytes < need) return fail(BBX_EINVAL, "out_bytes too small");
+        StepArgs<T> a = make_args<T>(g);
+        if (on_dev) {
+            HIP_TRY(launch_weights<T>(a, g->aniso, (double *)out, g->stream), "weights");
+            return BBX_OK;
+        }
+        DevBuf tmp;
+        HIP_TRY(hipMalloc(&tmp.p, need ? need : 1), "hipMalloc");
+        HIP_TRY(launch_weights<T>(a, g->aniso, (double *)tmp.p, g->stream), "weights");
+        if (need) HIP_TRY(hipMemcpyAsync(out, tmp.p, need, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    default:
+        return fail(BBX_EINVAL, "unknown readout %d", what);
+    }
+}
+
+}  // namespace
+
+// ============================================================================ C ABI
+
+extern "C" {
+
+const char *bbx_last_error(void) { return g_err.c_str(); }
+
+int bbx_grid_create(int nx, int ny, int nz, double h, const uint8_t *mask, const double *fibre,
+                    double D_par, double D_perp, int precision, void *hip_stream, bbx_grid **out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(BBX_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (nx < 1 || ny < 1 || nz < 1) return fail(BBX_EINVAL, "box sizes must be >= 1");
+        const int64_t nbox = (int64_t)nx * ny * nz;
+        if (nbox > 2147483647LL) return fail(BBX_EINVAL, "box has more than 2^31-1 voxels");
+        if (!(h > 0) || !isfinite(h)) return fail(BBX_EINVAL, "h must be positive");
+        if (!(D_par > 0) || !(D_perp > 0) || !isfinite(D_par) || !isfinite(D_perp))
+            return fail(BBX_EINVAL, "D_par and D_perp must be positive");
+        if (precision != BBX_FP32 && precision != BBX_FP64) return fail(BBX_EINVAL, "bad precision");
+        if (!mask) return fail(BBX_EINVAL, "mask is NULL");
+        if (fibre) {
+            for (int64_t b = 0; b < nbox; b++) {
+                if (!mask[b]) continue;
+                const double *v = fibre + 3 * b;
+                const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+                if (!(n >= 1e-12) || !isfinite(n))
+                    return fail(BBX_EINVAL, "tissue voxel %lld has a non-normalisable fibre", (long long)b);
+            }
+        }
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BBX_EDEVICE, "no HIP device");
+
+        bbx_grid *g = new bbx_grid();
+        g->nx = nx; g->ny = ny; g->nz = nz; g->nbox = nbox;
+        g->h = h; g->Dpar = D_par; g->Dperp = D_perp;
+        g->prec = precision; g->es = precision == BBX_FP64 ? 8 : 4;
+        g->aniso = fibre != nullptr && D_par != D_perp;
+        g->stream = (hipStream_t)hip_stream;
+        int rc = precision == BBX_FP64 ? create_impl<double>(g, mask, fibre)
+                                       : create_impl<float>(g, mask, fibre);
+        if (rc != BBX_OK) {
+            std::string keep = g_err;
+            free_all(g);
+            delete g;
+            g_err = keep;
+            return rc;
+        }
+        g->h_stimbits.assign((size_t)g->nact, 0u);
+        *out = g;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, double dt, int scheme)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        const int nv = model_nvar(model), np = model_nparams(model);
+        if (nv < 0) return fail(BBX_EINVAL, "unknown model %d", model);
+        if (nparams != np) return fail(BBX_EINVAL, "model %d takes %d parameters, got %d", model, np, nparams);
+        if (np > 0 && !params) return fail(BBX_EINVAL, "params is NULL");
+        for (int i = 0; i < np; i++)
+            if (!isfinite(params[i])) return fail(BBX_EINVAL, "parameter %d is not finite", i);
+        if (!(dt > 0) || !isfinite(dt)) return fail(BBX_EINVAL, "dt must be positive");
+        if (scheme != BBX_SCHEME_ADDITIVE && scheme != BBX_SCHEME_SPLIT) return fail(BBX_EINVAL, "bad scheme");
+        if (g->wsum_max > 0 && dt > 2.0 / g->wsum_max)
+            return fail(BBX_EUNSTABLE, "dt %g exceeds the explicit diffusion bound %g", dt, 2.0 / g->wsum_max);
+        int rc = g->prec ? alloc_state<double>(g, nv) : alloc_state<float>(g, nv);
+        if (rc) return rc;
+        g->model = model;
+        g->nvar = nv;
+        g->dt = dt;
+        g->scheme = scheme;
+        for (int i = 0; i < kMaxParams; i++) g->prm[i] = i < np ? params[i] : 0.0;
+        g->n = 0;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_state_set(bbx_grid *g, int var, const double *box_values)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (!box_values) return fail(BBX_EINVAL, "values is NULL");
+        if (var < 0 || var >= g->nvar) return fail(BBX_EINVAL, "var %d out of range (nvar %d)", var, g->nvar);
+        if (var > 0 && g->model < 0) return fail(BBX_ESTATE, "set a model first");
+        return g->prec ? state_set_impl<double>(g, var, box_values) : state_set_impl<float>(g, var, box_values);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_stimulus_add(bbx_grid *g, const uint8_t *region, double amplitude, double t_start,
+                     double duration, double period, int count)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (!region) return fail(BBX_EINVAL, "region is NULL");
+        if (!isfinite(amplitude) || !isfinite(t_start) || !isfinite(duration) || !isfinite(period))
+            return fail(BBX_EINVAL, "stimulus numbers must be finite");
+        if (t_start < 0 || duration < 0) return fail(BBX_EINVAL, "t_start and duration must be >= 0");
+        if ((int)g->stims.size() >= kMaxStim) return fail(BBX_EINVAL, "at most %d stimuli", kMaxStim);
+        std::vector<int32_t> h_idx;
+        int rc = download_idx(g, h_idx);
+        if (rc) return rc;
+        const int k = (int)g->stims.size();
+        std::vector<uint32_t> bits = g->h_stimbits;
+        for (int64_t t = 0; t < g->nact; t++)
+            if (region[g->dense ? t : h_idx[t]]) bits[t] |= 1u << k;
+        if (!g->d_stimbits) {
+            hipError_t e = dalloc(g, &g->d_stimbits, g->nact * sizeof(uint32_t));
+            if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        }
+        if (g->nact)
+            HIP_TRY(hipMemcpy(g->d_stimbits, bits.data(), g->nact * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
+        if (g->prec) {
+            double a = amplitude;
+            HIP_TRY(hipMemcpy((double *)g->d_stimamp + k, &a, sizeof a, hipMemcpyHostToDevice), "hipMemcpy");
+        } else {
+            float a = (float)amplitude;
+            HIP_TRY(hipMemcpy((float *)g->d_stimamp + k, &a, sizeof a, hipMemcpyHostToDevice), "hipMemcpy");
+        }
+        g->h_stimbits.swap(bits);
+        g->stims.push_back({amplitude, t_start, duration, period, count});
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_stimulus_clear(bbx_grid *g)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    g->stims.clear();
+    std::fill(g->h_stimbits.begin(), g->h_stimbits.end(), 0u);
+    if (g->d_stimbits && g->nact)
+        HIP_TRY(hipMemset(g->d_stimbits, 0, g->nact * sizeof(uint32_t)), "hipMemset");
+    return BBX_OK;
+}
+
+int bbx_recording_set(bbx_grid *g, double theta)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (isnan(theta)) { g->rec = 0; return BBX_OK; }
+        if (!isfinite(theta)) return fail(BBX_EINVAL, "theta must be finite or NaN");
+        return g->prec ? recording_impl<double>(g, theta) : recording_impl<float>(g, theta);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_nan_check_set(bbx_grid *g, int64_t every)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (every < 0) return fail(BBX_EINVAL, "every must be >= 0");
+    g->nan_every = every;
+    return BBX_OK;
+}
+
+int bbx_clock_set(bbx_grid *g, int64_t step)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (step < 0) return fail(BBX_EINVAL, "step must be >= 0");
+    g->n = step;
+    return BBX_OK;
+}
+
+int bbx_step(bbx_grid *g, int64_t nsteps)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (nsteps < 0) return fail(BBX_EINVAL, "nsteps must be >= 0");
+        if (g->model < 0) return fail(BBX_ESTATE, "set a model first");
+        return g->prec ? step_impl<double>(g, nsteps) : step_impl<float>(g, nsteps);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_readout(bbx_grid *g, int what, int var, const uint8_t *region, void *out, size_t out_bytes,
+                int out_on_device)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (!out) return fail(BBX_EINVAL, "out is NULL");
+        return g->prec ? readout_impl<double>(g, what, var, region, out, out_bytes, out_on_device)
+                       : readout_impl<float>(g, what, var, region, out, out_bytes, out_on_device);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_info(const bbx_grid *g, int what, int64_t *out)
+{
+    g_err.clear();
+    if (!g || !out) return fail(BBX_EINVAL, "NULL argument");
+    switch (what) {
+    case BBX_INFO_NACTIVE: *out = g->nact; return BBX_OK;
+    case BBX_INFO_NVAR: *out = g->nvar; return BBX_OK;
+    case BBX_INFO_NBOX: *out = g->nbox; return BBX_OK;
+    case BBX_INFO_DEVICE_BYTES: *out = (int64_t)g->bytes; return BBX_OK;
+    default: return fail(BBX_EINVAL, "unknown info %d", what);
+    }
+}
+
+void bbx_grid_destroy(bbx_grid *g)
+{
+    if (!g) return;
+    (void)hipStreamSynchronize(g->stream);
+    free_all(g);
+    delete g;
+}
+
+}  // extern "C"

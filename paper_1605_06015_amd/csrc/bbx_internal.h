@@ -1,0 +1,90 @@
+// Internal declarations shared by the host side of libbbx and its kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bbx {
+
+constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kMaxStim = 32;     // stimuli per grid (bit per stimulus in a uint32)
+constexpr int kMaxParams = 8;    // model parameters
+constexpr int kXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
+
+// The 18 non-corner neighbours of the 19-point stencil, in bit order: the six
+// faces, then the edges of the xy, xz and yz planes as (+,+), (-,-), (+,-), (-,+).
+// Corner neighbours carry zero weight in the paper's scheme and are not stored.
+struct NbOff { int dx, dy, dz; };
+__host__ __device__ constexpr NbOff nb_off(int b)
+{
+    constexpr NbOff t[18] = {
+        {+1, 0, 0}, {-1, 0, 0}, {0, +1, 0}, {0, -1, 0}, {0, 0, +1}, {0, 0, -1},
+        {+1, +1, 0}, {-1, -1, 0}, {+1, -1, 0}, {-1, +1, 0},
+        {+1, 0, +1}, {-1, 0, -1}, {+1, 0, -1}, {-1, 0, +1},
+        {0, +1, +1}, {0, -1, -1}, {0, +1, -1}, {0, -1, +1},
+    };
+    return t[b];
+}
+
+// Arguments of one fused step launch (passed by value in the kernarg segment).
+template <typename T>
+struct StepArgs {
+    // geometry
+    int nx, ny, nz;
+    int dense;                 // 1: every box voxel is tissue, t == box index
+    int64_t nact, pitch;       // tissue voxels; element pitch of the SoA arrays
+    const int32_t *idx;        // [nact] box index of tissue voxel t (sparse only)
+    const uint32_t *nbr;       // [nact] neighbour-is-tissue bits (sparse only)
+    const T *fib;              // [3][pitch] unit fibre (anisotropic only)
+    const T *gt;               // [3][pitch] face coefficient of the tensor-gradient term
+    T Dpar, Dperp, ih2;
+    // state
+    const T *Vin;              // [nbox] V at step n (box layout, void entries 0)
+    T *Vout;                   // [nbox] V at step n+1
+    T *st;                     // [nvar-1][pitch] other state variables, updated in place
+    // model / scheme
+    T prm[kMaxParams];
+    T dt;
+    int split;
+    // stimulus
+    int nstim;
+    uint32_t stim_on;          // bit s: stimulus s active at this step
+    const uint32_t *stimbits;  // [nact] bit s: voxel inside stimulus s region
+    const T *stim_amp;         // [kMaxStim]
+    // activation / APD90 recording
+    int rec;
+    T theta, tn;
+    uint8_t *status;
+    T *at, *vmax, *apd;
+    T *vrep;                   // rest level until the peak is known, then the 90% level
+    // XCD-aware block mapping
+    int nblk, per_xcd;
+};
+
+// Launchers (step_kernels.hip).  Return hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s);
+
+// Auxiliary kernels (aux_kernels.hip).
+template <typename T>
+hipError_t launch_to_box(const T *src, int src_is_box, const int32_t *idx, int dense,
+                         int64_t nact, int64_t nbox, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_from_box(const double *src, T *dst, int dst_is_box, const int32_t *idx,
+                           int dense, int64_t nact, hipStream_t s);
+template <typename T>
+hipError_t launch_reduce(const T *src, int src_is_box, const int32_t *idx, int dense,
+                         int64_t nact, const uint8_t *region, int op, double *partials,
+                         int nparts, double *out, hipStream_t s);
+template <typename T>
+hipError_t launch_nonfinite(const T *V, const int32_t *idx, int dense, const T *st,
+                            int nst, int64_t nact, int64_t pitch, int *flag, hipStream_t s);
+template <typename T>
+hipError_t launch_weights(const StepArgs<T> &a, int aniso, double *W, hipStream_t s);
+template <typename T>
+hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_gather(const T *box, const int32_t *idx, int dense, int64_t nact, T *dst,
+                         hipStream_t s);
+
+}  // namespace bbx

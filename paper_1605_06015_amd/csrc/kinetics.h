@@ -1,0 +1,251 @@
+// Device-side cell kinetics for the fused step kernel.
+//
+// Each model provides  T advance(const T* prm, T V, T* g, T dt):  given the
+// voltage the kinetics see (V_n, or V* in the split scheme) and the other state
+// variables g[0..NV-2], it returns the kinetic part of dV/dt (= -I_ion, with a
+// positive stimulus depolarising) and advances g in place by one step:
+// forward Euler (eq (Euler)) for concentrations and recovery variables,
+// Rush-Larsen for gates -- y+ = y_inf + (y - y_inf) exp(-dt/tau), the exact
+// solution of y' = (y_inf - y)/tau with the voltage frozen (eqs (gate), (RL),
+// (RLcoeff), with the two coefficients in the order that makes it exact).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace bbx {
+namespace kin {
+
+__device__ __forceinline__ float ex(float x) { return expf(x); }
+__device__ __forceinline__ double ex(double x) { return exp(x); }
+__device__ __forceinline__ float lg(float x) { return logf(x); }
+__device__ __forceinline__ double lg(double x) { return log(x); }
+__device__ __forceinline__ float sq(float x) { return sqrtf(x); }
+__device__ __forceinline__ double sq(double x) { return sqrt(x); }
+__device__ __forceinline__ float em1(float x) { return expm1f(x); }
+__device__ __forceinline__ double em1(double x) { return expm1(x); }
+
+// z / (e^z - 1).  Near z = 0 the Bernoulli series 1 - z/2 + z^2/12 (next term
+// z^4/720, below 2e-15 for |z| < 1e-3) replaces the 0/0 quotient.
+template <typename T>
+__device__ __forceinline__ T bern(T z)
+{
+    if (fabs(z) < T(1e-3)) return T(1) - z * (T(0.5) - z * T(1.0 / 12.0));
+    return z / em1(z);
+}
+
+// Rush-Larsen step written with the total transition rate k = 1/tau.
+template <typename T>
+__device__ __forceinline__ T rl_rate(T y, T yinf, T k, T dt)
+{
+    return yinf + (y - yinf) * ex(-dt * k);
+}
+
+// Rush-Larsen step of a gate given opening/closing rates (eq (gate)).
+template <typename T>
+__device__ __forceinline__ T rl_ab(T y, T a, T b, T dt)
+{
+    T k = a + b;
+    return rl_rate(y, a / k, k, dt);
+}
+
+// ---------------------------------------------------------------- pure diffusion
+template <typename T>
+struct None {
+    static constexpr int NV = 1;
+    __device__ static T advance(const T *, T, T *, T) { return T(0); }
+};
+
+// ---------------------------------------------------------------- Barkley (1991)
+// u' = u (1 - u)(u - (v + b)/a) / eps,  v' = u - v.   prm = {a, b, eps}
+template <typename T>
+struct Barkley {
+    static constexpr int NV = 2;
+    __device__ static T advance(const T *p, T u, T *g, T dt)
+    {
+        T v = g[0];
+        T uth = (v + p[1]) / p[0];
+        g[0] = v + dt * (u - v);
+        return u * (T(1) - u) * (u - uth) / p[2];
+    }
+};
+
+// ---------------------------------------------------------------- ZFK / Nagumo
+// V' = V (V - alpha)(1 - V)   (eq (ZFKbidomV)).   prm = {alpha}
+template <typename T>
+struct Zfk {
+    static constexpr int NV = 1;
+    __device__ static T advance(const T *p, T V, T *, T)
+    {
+        return V * (V - p[0]) * (T(1) - V);
+    }
+};
+
+// ---------------------------------------------------------------- cubic FHN
+// u' = (u - u^3/3 - v)/eps,  v' = eps (u + beta - gamma v)   (eq (FHN)).
+template <typename T>
+struct Fhn {
+    static constexpr int NV = 2;
+    __device__ static T advance(const T *p, T u, T *g, T dt)
+    {
+        T v = g[0];
+        g[0] = v + dt * p[0] * (u + p[1] - p[2] * v);
+        return (u - u * u * u * T(1.0 / 3.0) - v) / p[0];
+    }
+};
+
+// ---------------------------------------------------------------- Courtemanche 1998
+// Courtemanche, Ramirez & Nattel, Am J Physiol 275:H301 (1998), human atrial
+// myocyte; the paper uses it for its scaling runs.  Transcribed from that
+// publication.  g = Na_i, K_i, Ca_i, Ca_up, Ca_rel, m, h, j, oa, oi, ua, ui,
+// xr, xs, d, f, fCa, u, v, w.  Currents per unit capacitance (pA/pF).
+template <typename T>
+struct Crn {
+    static constexpr int NV = 21;
+    __device__ static T advance(const T *, T V, T *g, T dt)
+    {
+        // physical constants and cell geometry
+        constexpr double kRTF = 8.3143 * 310.0 / 96.4867;  // mV
+        constexpr double kF = 96.4867;                    // C/mmol
+        constexpr double kCm = 100.0;                     // pF
+        constexpr double kVi = 13668.0, kVup = 1109.52, kVrel = 96.48;  // um^3
+        constexpr double kNao = 140.0, kKo = 5.4, kCao = 1.8;           // mM
+        const T RTF = T(kRTF), iRTF = T(1.0 / kRTF);
+
+        T Nai = g[0], Ki = g[1], Cai = g[2], Caup = g[3], Carel = g[4];
+
+        // reversal potentials
+        const T ENa = RTF * lg(T(kNao) / Nai);
+        const T EK = RTF * lg(T(kKo) / Ki);
+        const T ECa = T(0.5) * RTF * lg(T(kCao) / Cai);
+        const T dK = V - EK;
+
+        // fast sodium current, gates m, h, j
+        T m = g[5], h = g[6], j = g[7];
+        const T INa = T(7.8) * m * m * m * h * j * (V - ENa);
+        {
+            T am = T(3.2) * bern(T(-0.1) * (V + T(47.13)));
+            T bm = T(0.08) * ex(-V * T(1.0 / 11.0));
+            T ah, bh, aj, bj;
+            if (V < T(-40)) {
+                ah = T(0.135) * ex((V + T(80)) * T(-1.0 / 6.8));
+                bh = T(3.56) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.35) * V);
+                aj = (T(-127140) * ex(T(0.2444) * V) - T(3.474e-5) * ex(T(-0.04391) * V))
+                     * (V + T(37.78)) / (T(1) + ex(T(0.311) * (V + T(79.23))));
+                bj = T(0.1212) * ex(T(-0.01052) * V) / (T(1) + ex(T(-0.1378) * (V + T(40.14))));
+            } else {
+                ah = T(0);
+                bh = T(1) / (T(0.13) * (T(1) + ex((V + T(10.66)) * T(-1.0 / 11.1))));
+                aj = T(0);
+                bj = T(0.3) * ex(T(-2.535e-7) * V) / (T(1) + ex(T(-0.1) * (V + T(32))));
+            }
+            g[5] = rl_ab(m, am, bm, dt);
+            g[6] = rl_ab(h, ah, bh, dt);
+            g[7] = rl_ab(j, aj, bj, dt);
+        }
+
+        // transient outward (oa, oi) and ultrarapid (ua, ui) potassium currents;
+        // activation rates of oa and ua share one form; Q10 factor 3
+        T oa = g[8], oi = g[9], ua = g[10], ui = g[11];
+        const T Ito = T(0.1652) * oa * oa * oa * oi * dK;
+        const T gKur = T(0.005) + T(0.05) / (T(1) + ex((V - T(15)) * T(-1.0 / 13.0)));
+        const T IKur = gKur * ua * ua * ua * ui * dK;
+        {
+            T a_act = T(0.65) / (ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
+            T b_act = T(0.65) / (T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
+            T k_act = T(3) * (a_act + b_act);
+            g[8] = rl_rate(oa, T(1) / (T(1) + ex((V + T(20.47)) * T(-1.0 / 17.54))), k_act, dt);
+            g[10] = rl_rate(ua, T(1) / (T(1) + ex((V + T(30.3)) * T(-1.0 / 9.6))), k_act, dt);
+            T aoi = T(1) / (T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
+            T boi = T(1) / (T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
+            g[9] = rl_rate(oi, T(1) / (T(1) + ex((V + T(43.1)) * T(1.0 / 5.3))), T(3) * (aoi + boi), dt);
+            T aui = T(1) / (T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
+            T bui = ex((V - T(158)) * T(1.0 / 16.0));
+            g[11] = rl_rate(ui, T(1) / (T(1) + ex((V - T(99.45)) * T(1.0 / 27.48))), T(3) * (aui + bui), dt);
+        }
+
+        // rapid and slow delayed rectifiers
+        T xr = g[12], xs = g[13];
+        const T IKr = T(0.029411765) * xr * dK / (T(1) + ex((V + T(15)) * T(1.0 / 22.4)));
+        const T IKs = T(0.12941176) * xs * xs * dK;
+        {
+            T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
+            T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
+            g[12] = rl_rate(xr, T(1) / (T(1) + ex((V + T(14.1)) * T(-1.0 / 6.5))), axr + bxr, dt);
+            T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
+            T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
+            T xsinf = T(1) / sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7)));
+            g[13] = rl_rate(xs, xsinf, T(2) * (axs + bxs), dt);
+        }
+
+        // inward rectifier
+        const T IK1 = T(0.09) * dK / (T(1) + ex(T(0.07) * (V + T(80))));
+
+        // L-type calcium current, gates d, f, fCa (reversal fixed at 65 mV)
+        T d = g[14], f = g[15], fCa = g[16];
+        const T ICaL = T(0.12375) * d * f * fCa * (V - T(65));
+        {
+            T zd = (V + T(10)) * T(1.0 / 6.24);
+            // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
+            T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
+            g[14] = rl_rate(d, T(1) / (T(1) + ex((V + T(10)) * T(-1.0 / 8.0))), kd, dt);
+            T vv = V + T(10);
+            T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
+            g[15] = rl_rate(f, T(1) / (T(1) + ex((V + T(28)) * T(1.0 / 6.9))), kf, dt);
+            g[16] = rl_rate(fCa, T(1) / (T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
+        }
+
+        // pumps, exchanger and background currents
+        const T sigma = T((8.006372134620099 - 1.0) / 7.0);  // (e^{[Na]o/67.3} - 1)/7
+        const T vf = V * iRTF;
+        const T fNaK = T(1) / (T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
+        const T rNa = T(10) / Nai;
+        const T INaK = T(0.59933874) * fNaK / (T(1) + rNa * sq(rNa)) * T(kKo / (kKo + 1.5));
+        const T eg = ex(T(0.35) * vf), eg1 = ex(T(-0.65) * vf);
+        const T INaCa = T(1600.0 / ((87.5 * 87.5 * 87.5 + kNao * kNao * kNao) * (1.38 + kCao)))
+                        * (eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao) * Cai)
+                        / (T(1) + T(0.1) * eg1);
+        const T IbCa = T(0.001131) * (V - ECa);
+        const T IbNa = T(0.0006744375) * (V - ENa);
+        const T IpCa = T(0.275) * Cai / (T(0.0005) + Cai);
+
+        // sarcoplasmic reticulum fluxes (mM/ms), release gates u, v, w
+        T u = g[17], v = g[18], w = g[19];
+        const T Irel = T(30) * u * u * v * w * (Carel - Cai);
+        const T Itr = (Caup - Carel) * T(1.0 / 180.0);
+        const T Iup = T(0.005) / (T(1) + T(0.00092) / Cai);
+        const T Ileak = T(0.005 / 15.0) * Caup;
+        {
+            // release trigger from SR release and sarcolemmal Ca entry (currents in pA)
+            T Fn = T(1e-12 * kVrel) * Irel - T(5e-13 / kF * kCm) * (T(0.5) * ICaL - T(0.2) * INaCa);
+            T s1 = T(1) / (T(1) + ex(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16)));
+            g[17] = rl_rate(u, s1, T(1.0 / 8.0), dt);
+            g[18] = rl_rate(v, T(1) - T(1) / (T(1) + ex(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16))),
+                            T(1) / (T(1.91) + T(2.09) * s1), dt);
+            T zw = (V - T(7.9)) * T(0.2);
+            // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
+            T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
+            g[19] = rl_rate(w, T(1) - T(1) / (T(1) + ex((V - T(40)) * T(-1.0 / 17.0))), kw, dt);
+        }
+
+        // concentrations (forward Euler); current-to-flux factor Cm / (F Vi)
+        const T c2f = T(kCm / (kF * kVi));
+        g[0] = Nai + dt * c2f * (T(-3) * (INaK + INaCa) - IbNa - INa);
+        g[1] = Ki + dt * c2f * (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs);
+        {
+            T bt = T(0.07 * 0.0005) / ((Cai + T(0.0005)) * (Cai + T(0.0005)));
+            T bc = T(0.05 * 0.00238) / ((Cai + T(0.00238)) * (Cai + T(0.00238)));
+            T src = T(0.5) * c2f * (T(2) * INaCa - IpCa - ICaL - IbCa)
+                    + (T(kVup) * (Ileak - Iup) + T(kVrel) * Irel) * T(1.0 / kVi);
+            g[2] = Cai + dt * src / (T(1) + bt + bc);
+            g[3] = Caup + dt * (Iup - Ileak - Itr * T(kVrel / kVup));
+            T bq = T(10.0 * 0.8) / ((Carel + T(0.8)) * (Carel + T(0.8)));
+            g[4] = Carel + dt * (Itr - Irel) / (T(1) + bq);
+        }
+
+        return -(INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL);
+    }
+};
+
+}  // namespace kin
+}  // namespace bbx

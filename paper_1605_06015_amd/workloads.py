@@ -76,15 +76,16 @@ def _fibres_from_normal(nx_, ny_, nz_, e, angle_lo=-60.0, angle_hi=60.0):
 
 
 def cup_shell(nx=128, ny=128, nz=64, h=0.25, active_frac=0.35, seed=1, tol=0.005):
-    """Half-ellipsoidal cup: outer semi-axes 15.5 mm x (1 +- 0.05, seeded), base at
+    """Half-ellipsoidal cup: outer semi-axes 0.97 x half the box width (15.5 mm for the
+    32 mm box) x (1 +- 0.05, seeded), base at
     the top z face, apex at the bottom; inner scale s_in found by bisection so
     that the active fraction is active_frac +- tol.
 
     Returns dict(mask, fibre, apex (mm), s, s_in)."""
     rng = np.random.default_rng(seed)
     L = np.array([nx * h, ny * h, nz * h])
-    axes = 0.5 * min(L[0], L[1]) - 0.5
-    axes = np.array([axes, axes, min(axes, L[2] - 0.5)]) * (1.0 + rng.uniform(-0.05, 0.05, 3))
+    base = 0.97 * 0.5 * min(L[0], L[1])
+    axes = np.array([base, base, min(base, 0.97 * L[2])]) * (1.0 + rng.uniform(-0.05, 0.05, 3))
     axes = np.minimum(axes, [0.5 * L[0] - 0.25 * h, 0.5 * L[1] - 0.25 * h, L[2] - 0.25 * h])
     centre = np.array([0.5 * L[0], 0.5 * L[1], L[2]])
     s, X, Y, Z = _shell_s(nx, ny, nz, h, axes, centre)
