@@ -155,6 +155,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the stencil roofline run")
+    ap.add_argument("--profile", choices=["crn", "stencil"], default=None,
+                    help="counter-collection mode: a few steps of one workload, then one plain "
+                         "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
@@ -165,6 +168,23 @@ def main():
     from paper_1605_06015_amd import bbx as B
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.profile:
+        if args.profile == "crn":
+            grid, _ = crn_workload(B.BBX_FP32, stream)
+            grid.nan_check(0)
+            grid.step(args.warmup + args.steps)
+            grid.close()
+        else:
+            stencil_roofline(stream, steps=args.steps, warmup=args.warmup)
+        src = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": args.profile, "copy_bytes_each_way": src.numel() * 4}))
+        return
 
     grid, g = crn_workload(B.BBX_FP32, stream)
     grid.nan_check(0)

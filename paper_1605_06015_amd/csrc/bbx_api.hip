@@ -192,7 +192,13 @@ StepArgs<T> make_args(const bbx_grid *g)
     a.vmax = (T *)g->d_vmax;
     a.apd = (T *)g->d_apd;
     a.vrep = (T *)g->d_vrep;
-    a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
+    if (g->dense) {
+        a.gx = (g->nx + kTileX - 1) / kTileX;
+        a.gy = (g->ny + kTileY - 1) / kTileY;
+        a.nblk = a.gx * a.gy * g->nz;
+    } else {
+        a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
+    }
     a.per_xcd = (a.nblk + kXcd - 1) / kXcd;
     return a;
 }

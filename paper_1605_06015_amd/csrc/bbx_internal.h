@@ -57,9 +57,14 @@ struct StepArgs {
     uint8_t *status;
     T *at, *vmax, *apd;
     T *vrep;                   // rest level until the peak is known, then the 90% level
-    // XCD-aware block mapping
+    // XCD-aware block mapping; dense boxes use 64 x 4 (x, y) tiles, gx * gy per plane
     int nblk, per_xcd;
+    int gx, gy;
 };
+
+// Dense-box tile of one workgroup: kTileX x kTileY voxels of one z plane.
+constexpr int kTileX = 64;
+constexpr int kTileY = kBlock / kTileX;
 
 // Launchers (step_kernels.hip).  Return hipSuccess or the launch error.
 template <typename T>

@@ -16,22 +16,38 @@
 namespace bbx {
 namespace kin {
 
-__device__ __forceinline__ float ex(float x) { return expf(x); }
+// FP32 uses the hardware transcendental units (v_exp_f32, v_log_f32, v_rcp_f32:
+// about 1 ulp) instead of the correctly rounded library routines, which cost
+// 5-15 VALU instructions each; FP64 keeps the library routines.  The FP32
+// error budget is set against the FP64 oracle by the tolerance tests.
+__device__ __forceinline__ float ex(float x) { return __expf(x); }
 __device__ __forceinline__ double ex(double x) { return exp(x); }
-__device__ __forceinline__ float lg(float x) { return logf(x); }
+__device__ __forceinline__ float lg(float x) { return __logf(x); }
 __device__ __forceinline__ double lg(double x) { return log(x); }
-__device__ __forceinline__ float sq(float x) { return sqrtf(x); }
+__device__ __forceinline__ float sq(float x) { return __builtin_sqrtf(x); }
 __device__ __forceinline__ double sq(double x) { return sqrt(x); }
-__device__ __forceinline__ float em1(float x) { return expm1f(x); }
-__device__ __forceinline__ double em1(double x) { return expm1(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double dv(double a, double b) { return a / b; }
 
-// z / (e^z - 1).  Near z = 0 the Bernoulli series 1 - z/2 + z^2/12 (next term
-// z^4/720, below 2e-15 for |z| < 1e-3) replaces the 0/0 quotient.
-template <typename T>
-__device__ __forceinline__ T bern(T z)
+// z / (e^z - 1).  Near z = 0 the quotient is 0/0; there the Bernoulli series
+// 1 - z/2 + z^2/12 - z^4/720 + z^6/30240 replaces it (next term z^8/1209600).
+// FP64 switches at |z| < 1e-3 (series error < 1e-30) and divides by expm1;
+// FP32 switches at |z| < 0.1 (series error < 1e-14), beyond which e^z - 1
+// loses at most a few ulp to cancellation.
+__device__ __forceinline__ double bern(double z)
 {
-    if (fabs(z) < T(1e-3)) return T(1) - z * (T(0.5) - z * T(1.0 / 12.0));
-    return z / em1(z);
+    if (fabs(z) < 1e-3) return 1.0 - z * (0.5 - z * (1.0 / 12.0));
+    return z / expm1(z);
+}
+__device__ __forceinline__ float bern(float z)
+{
+    if (fabsf(z) < 0.1f) {
+        const float z2 = z * z;
+        return 1.0f - 0.5f * z + z2 * (1.0f / 12.0f - z2 * (1.0f / 720.0f - z2 * (1.0f / 30240.0f)));
+    }
+    return dv(z, __expf(z) - 1.0f);
 }
 
 // Rush-Larsen step written with the total transition rate k = 1/tau.
@@ -46,7 +62,14 @@ template <typename T>
 __device__ __forceinline__ T rl_ab(T y, T a, T b, T dt)
 {
     T k = a + b;
-    return rl_rate(y, a / k, k, dt);
+    return rl_rate(y, a * rcp(k), k, dt);
+}
+
+// Logistic 1 / (1 + e^x).
+template <typename T>
+__device__ __forceinline__ T lgs(T x)
+{
+    return rcp(T(1) + ex(x));
 }
 
 // ---------------------------------------------------------------- pure diffusion
@@ -115,9 +138,9 @@ struct Crn {
         T Nai = g[0], Ki = g[1], Cai = g[2], Caup = g[3], Carel = g[4];
 
         // reversal potentials
-        const T ENa = RTF * lg(T(kNao) / Nai);
-        const T EK = RTF * lg(T(kKo) / Ki);
-        const T ECa = T(0.5) * RTF * lg(T(kCao) / Cai);
+        const T ENa = RTF * lg(dv(T(kNao), Nai));
+        const T EK = RTF * lg(dv(T(kKo), Ki));
+        const T ECa = T(0.5) * RTF * lg(dv(T(kCao), Cai));
         const T dK = V - EK;
 
         // fast sodium current, gates m, h, j
@@ -131,13 +154,13 @@ struct Crn {
                 ah = T(0.135) * ex((V + T(80)) * T(-1.0 / 6.8));
                 bh = T(3.56) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.35) * V);
                 aj = (T(-127140) * ex(T(0.2444) * V) - T(3.474e-5) * ex(T(-0.04391) * V))
-                     * (V + T(37.78)) / (T(1) + ex(T(0.311) * (V + T(79.23))));
-                bj = T(0.1212) * ex(T(-0.01052) * V) / (T(1) + ex(T(-0.1378) * (V + T(40.14))));
+                     * (V + T(37.78)) * lgs(T(0.311) * (V + T(79.23)));
+                bj = T(0.1212) * ex(T(-0.01052) * V) * lgs(T(-0.1378) * (V + T(40.14)));
             } else {
                 ah = T(0);
-                bh = T(1) / (T(0.13) * (T(1) + ex((V + T(10.66)) * T(-1.0 / 11.1))));
+                bh = T(1.0 / 0.13) * lgs((V + T(10.66)) * T(-1.0 / 11.1));
                 aj = T(0);
-                bj = T(0.3) * ex(T(-2.535e-7) * V) / (T(1) + ex(T(-0.1) * (V + T(32))));
+                bj = T(0.3) * ex(T(-2.535e-7) * V) * lgs(T(-0.1) * (V + T(32)));
             }
             g[5] = rl_ab(m, am, bm, dt);
             g[6] = rl_ab(h, ah, bh, dt);
@@ -148,38 +171,38 @@ struct Crn {
         // activation rates of oa and ua share one form; Q10 factor 3
         T oa = g[8], oi = g[9], ua = g[10], ui = g[11];
         const T Ito = T(0.1652) * oa * oa * oa * oi * dK;
-        const T gKur = T(0.005) + T(0.05) / (T(1) + ex((V - T(15)) * T(-1.0 / 13.0)));
+        const T gKur = T(0.005) + T(0.05) * lgs((V - T(15)) * T(-1.0 / 13.0));
         const T IKur = gKur * ua * ua * ua * ui * dK;
         {
-            T a_act = T(0.65) / (ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
-            T b_act = T(0.65) / (T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
+            T a_act = T(0.65) * rcp(ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
+            T b_act = T(0.65) * rcp(T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
             T k_act = T(3) * (a_act + b_act);
-            g[8] = rl_rate(oa, T(1) / (T(1) + ex((V + T(20.47)) * T(-1.0 / 17.54))), k_act, dt);
-            g[10] = rl_rate(ua, T(1) / (T(1) + ex((V + T(30.3)) * T(-1.0 / 9.6))), k_act, dt);
-            T aoi = T(1) / (T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
-            T boi = T(1) / (T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
-            g[9] = rl_rate(oi, T(1) / (T(1) + ex((V + T(43.1)) * T(1.0 / 5.3))), T(3) * (aoi + boi), dt);
-            T aui = T(1) / (T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
+            g[8] = rl_rate(oa, lgs((V + T(20.47)) * T(-1.0 / 17.54)), k_act, dt);
+            g[10] = rl_rate(ua, lgs((V + T(30.3)) * T(-1.0 / 9.6)), k_act, dt);
+            T aoi = rcp(T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
+            T boi = rcp(T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
+            g[9] = rl_rate(oi, lgs((V + T(43.1)) * T(1.0 / 5.3)), T(3) * (aoi + boi), dt);
+            T aui = rcp(T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
             T bui = ex((V - T(158)) * T(1.0 / 16.0));
-            g[11] = rl_rate(ui, T(1) / (T(1) + ex((V - T(99.45)) * T(1.0 / 27.48))), T(3) * (aui + bui), dt);
+            g[11] = rl_rate(ui, lgs((V - T(99.45)) * T(1.0 / 27.48)), T(3) * (aui + bui), dt);
         }
 
         // rapid and slow delayed rectifiers
         T xr = g[12], xs = g[13];
-        const T IKr = T(0.029411765) * xr * dK / (T(1) + ex((V + T(15)) * T(1.0 / 22.4)));
+        const T IKr = T(0.029411765) * xr * dK * lgs((V + T(15)) * T(1.0 / 22.4));
         const T IKs = T(0.12941176) * xs * xs * dK;
         {
             T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
             T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
-            g[12] = rl_rate(xr, T(1) / (T(1) + ex((V + T(14.1)) * T(-1.0 / 6.5))), axr + bxr, dt);
+            g[12] = rl_rate(xr, lgs((V + T(14.1)) * T(-1.0 / 6.5)), axr + bxr, dt);
             T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
             T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
-            T xsinf = T(1) / sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7)));
+            T xsinf = rcp(sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7))));
             g[13] = rl_rate(xs, xsinf, T(2) * (axs + bxs), dt);
         }
 
         // inward rectifier
-        const T IK1 = T(0.09) * dK / (T(1) + ex(T(0.07) * (V + T(80))));
+        const T IK1 = T(0.09) * dK * lgs(T(0.07) * (V + T(80)));
 
         // L-type calcium current, gates d, f, fCa (reversal fixed at 65 mV)
         T d = g[14], f = g[15], fCa = g[16];
@@ -188,44 +211,44 @@ struct Crn {
             T zd = (V + T(10)) * T(1.0 / 6.24);
             // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
             T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
-            g[14] = rl_rate(d, T(1) / (T(1) + ex((V + T(10)) * T(-1.0 / 8.0))), kd, dt);
+            g[14] = rl_rate(d, lgs((V + T(10)) * T(-1.0 / 8.0)), kd, dt);
             T vv = V + T(10);
             T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
-            g[15] = rl_rate(f, T(1) / (T(1) + ex((V + T(28)) * T(1.0 / 6.9))), kf, dt);
-            g[16] = rl_rate(fCa, T(1) / (T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
+            g[15] = rl_rate(f, lgs((V + T(28)) * T(1.0 / 6.9)), kf, dt);
+            g[16] = rl_rate(fCa, rcp(T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
         }
 
         // pumps, exchanger and background currents
         const T sigma = T((8.006372134620099 - 1.0) / 7.0);  // (e^{[Na]o/67.3} - 1)/7
         const T vf = V * iRTF;
-        const T fNaK = T(1) / (T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
-        const T rNa = T(10) / Nai;
-        const T INaK = T(0.59933874) * fNaK / (T(1) + rNa * sq(rNa)) * T(kKo / (kKo + 1.5));
+        const T fNaK = rcp(T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
+        const T rNa = dv(T(10), Nai);
+        const T INaK = T(0.59933874 * kKo / (kKo + 1.5)) * fNaK * rcp(T(1) + rNa * sq(rNa));
         const T eg = ex(T(0.35) * vf), eg1 = ex(T(-0.65) * vf);
         const T INaCa = T(1600.0 / ((87.5 * 87.5 * 87.5 + kNao * kNao * kNao) * (1.38 + kCao)))
                         * (eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao) * Cai)
-                        / (T(1) + T(0.1) * eg1);
+                        * rcp(T(1) + T(0.1) * eg1);
         const T IbCa = T(0.001131) * (V - ECa);
         const T IbNa = T(0.0006744375) * (V - ENa);
-        const T IpCa = T(0.275) * Cai / (T(0.0005) + Cai);
+        const T IpCa = T(0.275) * dv(Cai, T(0.0005) + Cai);
 
         // sarcoplasmic reticulum fluxes (mM/ms), release gates u, v, w
         T u = g[17], v = g[18], w = g[19];
         const T Irel = T(30) * u * u * v * w * (Carel - Cai);
         const T Itr = (Caup - Carel) * T(1.0 / 180.0);
-        const T Iup = T(0.005) / (T(1) + T(0.00092) / Cai);
+        const T Iup = T(0.005) * dv(Cai, Cai + T(0.00092));
         const T Ileak = T(0.005 / 15.0) * Caup;
         {
             // release trigger from SR release and sarcolemmal Ca entry (currents in pA)
             T Fn = T(1e-12 * kVrel) * Irel - T(5e-13 / kF * kCm) * (T(0.5) * ICaL - T(0.2) * INaCa);
-            T s1 = T(1) / (T(1) + ex(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16)));
+            T s1 = lgs(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16));
             g[17] = rl_rate(u, s1, T(1.0 / 8.0), dt);
-            g[18] = rl_rate(v, T(1) - T(1) / (T(1) + ex(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16))),
-                            T(1) / (T(1.91) + T(2.09) * s1), dt);
+            g[18] = rl_rate(v, T(1) - lgs(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16)),
+                            rcp(T(1.91) + T(2.09) * s1), dt);
             T zw = (V - T(7.9)) * T(0.2);
             // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
             T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
-            g[19] = rl_rate(w, T(1) - T(1) / (T(1) + ex((V - T(40)) * T(-1.0 / 17.0))), kw, dt);
+            g[19] = rl_rate(w, T(1) - lgs((V - T(40)) * T(-1.0 / 17.0)), kw, dt);
         }
 
         // concentrations (forward Euler); current-to-flux factor Cm / (F Vi)
@@ -233,14 +256,16 @@ struct Crn {
         g[0] = Nai + dt * c2f * (T(-3) * (INaK + INaCa) - IbNa - INa);
         g[1] = Ki + dt * c2f * (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs);
         {
-            T bt = T(0.07 * 0.0005) / ((Cai + T(0.0005)) * (Cai + T(0.0005)));
-            T bc = T(0.05 * 0.00238) / ((Cai + T(0.00238)) * (Cai + T(0.00238)));
+            T ct = Cai + T(0.0005), cc = Cai + T(0.00238);
+            T bt = T(0.07 * 0.0005) * rcp(ct * ct);
+            T bc = T(0.05 * 0.00238) * rcp(cc * cc);
             T src = T(0.5) * c2f * (T(2) * INaCa - IpCa - ICaL - IbCa)
                     + (T(kVup) * (Ileak - Iup) + T(kVrel) * Irel) * T(1.0 / kVi);
-            g[2] = Cai + dt * src / (T(1) + bt + bc);
+            g[2] = Cai + dt * src * rcp(T(1) + bt + bc);
             g[3] = Caup + dt * (Iup - Ileak - Itr * T(kVrel / kVup));
-            T bq = T(10.0 * 0.8) / ((Carel + T(0.8)) * (Carel + T(0.8)));
-            g[4] = Carel + dt * (Itr - Irel) / (T(1) + bq);
+            T cq = Carel + T(0.8);
+            T bq = T(10.0 * 0.8) * rcp(cq * cq);
+            g[4] = Carel + dt * (Itr - Irel) * rcp(T(1) + bq);
         }
 
         return -(INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL);

@@ -24,30 +24,66 @@
 
 namespace bbx {
 
-template <typename T>
-__device__ __forceinline__ T nbdiff(const T *__restrict__ V, int64_t idx, int64_t off,
-                                    uint32_t bits, int b, T Vp)
+// V_{p+off} - V_p if neighbour bit b is set (tissue), else 0.  FULL: the whole
+// workgroup is known to be interior (every neighbour is tissue).
+template <typename T, bool FULL>
+__device__ __forceinline__ T nbd(const T *__restrict__ V, int idx, int off, uint32_t bits, int b,
+                                 T Vp)
 {
+    if (FULL) return V[idx + off] - Vp;
     return ((bits >> b) & 1u) ? V[idx + off] - Vp : T(0);
 }
 
-template <typename T, class M, bool ANISO>
+// (L V)_p in the difference form; see the header comment.
+template <typename T, bool ANISO, bool FULL>
+__device__ __forceinline__ T laplacian(const StepArgs<T> &a, const T *__restrict__ V, int t,
+                                       int idx, uint32_t bits, T Vp)
+{
+    const int sy = a.nx, sz = a.nx * a.ny;
+    const T ex_ = nbd<T, FULL>(V, idx, 1, bits, 0, Vp), wx = nbd<T, FULL>(V, idx, -1, bits, 1, Vp);
+    const T ny_ = nbd<T, FULL>(V, idx, sy, bits, 2, Vp), sy_ = nbd<T, FULL>(V, idx, -sy, bits, 3, Vp);
+    const T up = nbd<T, FULL>(V, idx, sz, bits, 4, Vp), dn = nbd<T, FULL>(V, idx, -sz, bits, 5, Vp);
+    if (!ANISO) return a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dn));
+    const T fx = a.fib[t], fy = a.fib[a.pitch + t], fz = a.fib[2 * a.pitch + t];
+    const T cx = a.gt[t], cy = a.gt[a.pitch + t], cz = a.gt[2 * a.pitch + t];
+    const T dd = a.Dpar - a.Dperp;
+    const T Dxx = a.Dperp + dd * fx * fx, Dyy = a.Dperp + dd * fy * fy;
+    const T Dzz = a.Dperp + dd * fz * fz;
+    const T Dxy = dd * fx * fy, Dxz = dd * fx * fz, Dyz = dd * fy * fz;
+    const T exy = nbd<T, FULL>(V, idx, 1 + sy, bits, 6, Vp) + nbd<T, FULL>(V, idx, -1 - sy, bits, 7, Vp)
+                  - nbd<T, FULL>(V, idx, 1 - sy, bits, 8, Vp) - nbd<T, FULL>(V, idx, -1 + sy, bits, 9, Vp);
+    const T exz = nbd<T, FULL>(V, idx, 1 + sz, bits, 10, Vp) + nbd<T, FULL>(V, idx, -1 - sz, bits, 11, Vp)
+                  - nbd<T, FULL>(V, idx, 1 - sz, bits, 12, Vp) - nbd<T, FULL>(V, idx, -1 + sz, bits, 13, Vp);
+    const T eyz = nbd<T, FULL>(V, idx, sy + sz, bits, 14, Vp) + nbd<T, FULL>(V, idx, -sy - sz, bits, 15, Vp)
+                  - nbd<T, FULL>(V, idx, sy - sz, bits, 16, Vp) - nbd<T, FULL>(V, idx, -sy + sz, bits, 17, Vp);
+    return a.ih2 * (Dxx * (ex_ + wx) + Dyy * (ny_ + sy_) + Dzz * (up + dn)
+                    + T(0.5) * (Dxy * exy + Dxz * exz + Dyz * eyz))
+           + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
+}
+
+// One workgroup = 256 tissue voxels of the list (sparse) or one 64 x 4 tile of a
+// z plane (dense box).  Logical workgroup ids are dealt so that XCD k gets the
+// k-th contiguous eighth of the domain.
+template <typename T, class M, bool ANISO, bool DENSE>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
 {
     const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
     if (lb >= a.nblk) return;
-    const int64_t t = (int64_t)lb * kBlock + threadIdx.x;
-    if (t >= a.nact) return;
 
-    const int64_t sy = a.nx, sz = (int64_t)a.nx * a.ny;
-    int64_t idx;
+    int t, idx;
     uint32_t bits;
-    if (a.dense) {
-        idx = t;
-        const int64_t r = t / a.nx;
-        const int x = (int)(t - r * a.nx);
-        const int z = (int)(r / a.ny);
-        const int y = (int)(r - (int64_t)z * a.ny);
+    bool full = false;
+    if (DENSE) {
+        // tile coordinates are workgroup-uniform (scalar unit)
+        const int bx = lb % a.gx, r = lb / a.gx;
+        const int by = r % a.gy, z = r / a.gy;
+        const int x = bx * kTileX + (int)(threadIdx.x % kTileX);
+        const int y = by * kTileY + (int)(threadIdx.x / kTileX);
+        if (x >= a.nx || y >= a.ny) return;
+        idx = x + a.nx * (y + a.ny * z);
+        t = idx;
+        full = bx > 0 && (bx + 1) * kTileX < a.nx && by > 0 && (by + 1) * kTileY < a.ny && z > 0 &&
+               z + 1 < a.nz;
         const uint32_t px = x + 1 < a.nx, mx = x > 0, py = y + 1 < a.ny, my = y > 0;
         const uint32_t pz = z + 1 < a.nz, mz = z > 0;
         bits = px | mx << 1 | py << 2 | my << 3 | pz << 4 | mz << 5;
@@ -57,38 +93,16 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
             bits |= (py & pz) << 14 | (my & mz) << 15 | (py & mz) << 16 | (my & pz) << 17;
         }
     } else {
+        t = lb * kBlock + (int)threadIdx.x;
+        if (t >= a.nact) return;
         idx = a.idx[t];
         bits = a.nbr[t];
     }
 
     const T *__restrict__ V = a.Vin;
     const T Vp = V[idx];
-    T LV;
-    if (!ANISO) {
-        T s = nbdiff(V, idx, 1, bits, 0, Vp) + nbdiff(V, idx, -1, bits, 1, Vp)
-              + nbdiff(V, idx, sy, bits, 2, Vp) + nbdiff(V, idx, -sy, bits, 3, Vp)
-              + nbdiff(V, idx, sz, bits, 4, Vp) + nbdiff(V, idx, -sz, bits, 5, Vp);
-        LV = a.Dperp * a.ih2 * s;
-    } else {
-        const T fx = a.fib[t], fy = a.fib[a.pitch + t], fz = a.fib[2 * a.pitch + t];
-        const T cx = a.gt[t], cy = a.gt[a.pitch + t], cz = a.gt[2 * a.pitch + t];
-        const T dd = a.Dpar - a.Dperp;
-        const T Dxx = a.Dperp + dd * fx * fx, Dyy = a.Dperp + dd * fy * fy;
-        const T Dzz = a.Dperp + dd * fz * fz;
-        const T Dxy = dd * fx * fy, Dxz = dd * fx * fz, Dyz = dd * fy * fz;
-        const T ex_ = nbdiff(V, idx, 1, bits, 0, Vp), wx = nbdiff(V, idx, -1, bits, 1, Vp);
-        const T ny_ = nbdiff(V, idx, sy, bits, 2, Vp), sy_ = nbdiff(V, idx, -sy, bits, 3, Vp);
-        const T up = nbdiff(V, idx, sz, bits, 4, Vp), dn = nbdiff(V, idx, -sz, bits, 5, Vp);
-        const T exy = nbdiff(V, idx, 1 + sy, bits, 6, Vp) + nbdiff(V, idx, -1 - sy, bits, 7, Vp)
-                      - nbdiff(V, idx, 1 - sy, bits, 8, Vp) - nbdiff(V, idx, -1 + sy, bits, 9, Vp);
-        const T exz = nbdiff(V, idx, 1 + sz, bits, 10, Vp) + nbdiff(V, idx, -1 - sz, bits, 11, Vp)
-                      - nbdiff(V, idx, 1 - sz, bits, 12, Vp) - nbdiff(V, idx, -1 + sz, bits, 13, Vp);
-        const T eyz = nbdiff(V, idx, sy + sz, bits, 14, Vp) + nbdiff(V, idx, -sy - sz, bits, 15, Vp)
-                      - nbdiff(V, idx, sy - sz, bits, 16, Vp) - nbdiff(V, idx, -sy + sz, bits, 17, Vp);
-        LV = a.ih2 * (Dxx * (ex_ + wx) + Dyy * (ny_ + sy_) + Dzz * (up + dn)
-                      + T(0.5) * (Dxy * exy + Dxz * exz + Dyz * eyz))
-             + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
-    }
+    const T LV = full ? laplacian<T, ANISO, true>(a, V, t, idx, bits, Vp)
+                      : laplacian<T, ANISO, false>(a, V, t, idx, bits, Vp);
 
     // stimulus current
     T Is = T(0);
@@ -139,11 +153,14 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
 template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
-    const int grid = a.per_xcd * kXcd;
-    if (aniso)
-        hipLaunchKernelGGL((k_step<T, M, true>), dim3(grid), dim3(kBlock), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_step<T, M, false>), dim3(grid), dim3(kBlock), 0, s, a);
+    const dim3 grid(a.per_xcd * kXcd), block(kBlock);
+    if (a.dense) {
+        if (aniso) hipLaunchKernelGGL((k_step<T, M, true, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step<T, M, false, true>), grid, block, 0, s, a);
+    } else {
+        if (aniso) hipLaunchKernelGGL((k_step<T, M, true, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step<T, M, false, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 
