@@ -145,7 +145,27 @@ def stencil_roofline(stream, steps=100, warmup=10):
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": STENCIL_BYTES_PER_VOXEL,
             "us_per_launch": round(per_launch * 1e6, 2),
-            "voxel_updates_per_s": nact / per_launch}
+            "voxel_updates_per_s": nact / per_launch,
+            "device_copy_GBs": round(copy_bandwidth(stream), 1)}
+
+
+def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
+    """Read+write bandwidth of a plain 1 GiB device-to-device copy (context for the
+    stencil's fraction of peak)."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    return 2 * nbytes * reps / sec / 1e9
 
 
 def main():

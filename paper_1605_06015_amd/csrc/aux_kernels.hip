@@ -207,11 +207,11 @@ __global__ void k_weights(const StepArgs<T> a, int aniso, double *W)
     double D[3][3] = {{(double)a.Dperp, 0, 0}, {0, (double)a.Dperp, 0}, {0, 0, (double)a.Dperp}};
     double c[3] = {0, 0, 0};
     if (aniso) {
-        const double f[3] = {(double)a.fib[t], (double)a.fib[a.pitch + t],
-                             (double)a.fib[2 * a.pitch + t]};
+        const T *gp = a.geo + 6 * t;
+        const double f[3] = {(double)gp[0], (double)gp[1], (double)gp[2]};
         for (int j = 0; j < 3; j++) {
             for (int k = 0; k < 3; k++) D[j][k] += ((double)a.Dpar - (double)a.Dperp) * f[j] * f[k];
-            c[j] = (double)a.gt[j * a.pitch + t];
+            c[j] = (double)gp[3 + j];
         }
     }
     double *w = W + 27 * t;

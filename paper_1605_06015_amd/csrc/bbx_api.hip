@@ -91,7 +91,7 @@ struct bbx_grid {
 
     int32_t *d_idx = nullptr;
     uint32_t *d_nbr = nullptr;
-    void *d_fib = nullptr, *d_gt = nullptr;
+    void *d_geo = nullptr;
     void *d_V[2] = {nullptr, nullptr};
     int cur = 0;
     void *d_st = nullptr;
@@ -138,7 +138,7 @@ void dfree(void *p)
 
 void free_all(bbx_grid *g)
 {
-    void *ps[] = {g->d_idx, g->d_nbr, g->d_fib, g->d_gt, g->d_V[0], g->d_V[1], g->d_st,
+    void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag};
     for (void *p : ps) dfree(p);
@@ -173,8 +173,7 @@ StepArgs<T> make_args(const bbx_grid *g)
     a.pitch = g->pitch;
     a.idx = g->d_idx;
     a.nbr = g->d_nbr;
-    a.fib = (const T *)g->d_fib;
-    a.gt = (const T *)g->d_gt;
+    a.geo = (const T *)g->d_geo;
     a.Dpar = (T)g->Dpar;
     a.Dperp = (T)g->Dperp;
     a.ih2 = (T)(1.0 / (g->h * g->h));
@@ -195,7 +194,12 @@ StepArgs<T> make_args(const bbx_grid *g)
     if (g->dense) {
         a.gx = (g->nx + kTileX - 1) / kTileX;
         a.gy = (g->ny + kTileY - 1) / kTileY;
-        a.nblk = a.gx * a.gy * g->nz;
+        // z-chunk: long enough to amortise the two extra halo planes, short enough
+        // to give every SIMD several workgroups
+        int zc = 32;
+        while (zc > 4 && (int64_t)a.gx * a.gy * ((g->nz + zc - 1) / zc) < 8192) zc /= 2;
+        a.zc = zc;
+        a.nblk = a.gx * a.gy * ((g->nz + zc - 1) / zc);
     } else {
         a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
     }
@@ -309,11 +313,8 @@ int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
     };
 
     std::vector<uint32_t> nbr((size_t)g->nact);
-    std::vector<T> fib, gt;
-    if (g->aniso) {
-        fib.assign((size_t)(3 * g->pitch), T(0));
-        gt.assign((size_t)(3 * g->pitch), T(0));
-    }
+    std::vector<T> geo;
+    if (g->aniso) geo.assign((size_t)(6 * g->nact), T(0));
     const double ih2 = 1.0 / (g->h * g->h);
     double wmax = 0;
     for (int64_t t = 0; t < g->nact; t++) {
@@ -353,8 +354,8 @@ int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
                 c[k] = 0.25 * ih2 * sdiv;
             }
             for (int k = 0; k < 3; k++) {
-                fib[k * g->pitch + t] = (T)f[k];
-                gt[k * g->pitch + t] = (T)c[k];
+                geo[6 * t + k] = (T)f[k];
+                geo[6 * t + 3 + k] = (T)c[k];
             }
         }
         // Gershgorin radius of row p: |W_0| + sum |W_q| <= 2 sum |W_q|
@@ -383,10 +384,9 @@ int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
         HIP_TRY(hipMemcpy(g->d_nbr, nbr.data(), g->nact * sizeof(uint32_t), hipMemcpyHostToDevice), "hipMemcpy");
     }
     if (g->aniso) {
-        if ((e = dalloc(g, &g->d_fib, 3 * g->pitch * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        if ((e = dalloc(g, &g->d_gt, 3 * g->pitch * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
-        HIP_TRY(hipMemcpy(g->d_fib, fib.data(), 3 * g->pitch * es, hipMemcpyHostToDevice), "hipMemcpy");
-        HIP_TRY(hipMemcpy(g->d_gt, gt.data(), 3 * g->pitch * es, hipMemcpyHostToDevice), "hipMemcpy");
+        if ((e = dalloc(g, &g->d_geo, 6 * g->nact * es)) != hipSuccess) return hip_fail(e, "hipMalloc");
+        if (g->nact)
+            HIP_TRY(hipMemcpy(g->d_geo, geo.data(), 6 * g->nact * es, hipMemcpyHostToDevice), "hipMemcpy");
     }
     for (int k = 0; k < 2; k++) {
         if ((e = dalloc(g, &g->d_V[k], g->nbox * es)) != hipSuccess) return hip_fail(e, "hipMalloc");

@@ -35,8 +35,8 @@ struct StepArgs {
     int64_t nact, pitch;       // tissue voxels; element pitch of the SoA arrays
     const int32_t *idx;        // [nact] box index of tissue voxel t (sparse only)
     const uint32_t *nbr;       // [nact] neighbour-is-tissue bits (sparse only)
-    const T *fib;              // [3][pitch] unit fibre (anisotropic only)
-    const T *gt;               // [3][pitch] face coefficient of the tensor-gradient term
+    const T *geo;              // [nact][6] per voxel: unit fibre (3), face coefficients
+                               // of the tensor-gradient term (3); anisotropic only
     T Dpar, Dperp, ih2;
     // state
     const T *Vin;              // [nbox] V at step n (box layout, void entries 0)
@@ -59,7 +59,7 @@ struct StepArgs {
     T *vrep;                   // rest level until the peak is known, then the 90% level
     // XCD-aware block mapping; dense boxes use 64 x 4 (x, y) tiles, gx * gy per plane
     int nblk, per_xcd;
-    int gx, gy;
+    int gx, gy, zc;            // dense: tiles along x, y; planes per z-chunk
 };
 
 // Dense-box tile of one workgroup: kTileX x kTileY voxels of one z plane.

@@ -12,7 +12,7 @@
 // centre weight is minus the sum of the others).  c_k, the face coefficient of
 // the tensor-gradient part Wtilde, depends on the neighbours' fibres only and
 // is precomputed per voxel; D^p is rebuilt in registers from the fibre, so the
-// kernel streams 3+3 values per voxel instead of 18 weights.
+// kernel streams 3+3 interleaved values per voxel instead of 18 weights.
 //
 // Memory: V lives in box layout (neighbour gathers; void entries stay 0 and are
 // never selected), everything else is structure-of-arrays over the tissue list
@@ -44,8 +44,9 @@ __device__ __forceinline__ T laplacian(const StepArgs<T> &a, const T *__restrict
     const T ny_ = nbd<T, FULL>(V, idx, sy, bits, 2, Vp), sy_ = nbd<T, FULL>(V, idx, -sy, bits, 3, Vp);
     const T up = nbd<T, FULL>(V, idx, sz, bits, 4, Vp), dn = nbd<T, FULL>(V, idx, -sz, bits, 5, Vp);
     if (!ANISO) return a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dn));
-    const T fx = a.fib[t], fy = a.fib[a.pitch + t], fz = a.fib[2 * a.pitch + t];
-    const T cx = a.gt[t], cy = a.gt[a.pitch + t], cz = a.gt[2 * a.pitch + t];
+    const T *gp = a.geo + 6 * (int64_t)t;
+    const T fx = gp[0], fy = gp[1], fz = gp[2];
+    const T cx = gp[3], cy = gp[4], cz = gp[5];
     const T dd = a.Dpar - a.Dperp;
     const T Dxx = a.Dperp + dd * fx * fx, Dyy = a.Dperp + dd * fy * fy;
     const T Dzz = a.Dperp + dd * fz * fz;
@@ -61,50 +62,11 @@ __device__ __forceinline__ T laplacian(const StepArgs<T> &a, const T *__restrict
            + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
 }
 
-// One workgroup = 256 tissue voxels of the list (sparse) or one 64 x 4 tile of a
-// z plane (dense box).  Logical workgroup ids are dealt so that XCD k gets the
-// k-th contiguous eighth of the domain.
-template <typename T, class M, bool ANISO, bool DENSE>
-__global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
+// Everything after the Laplacian for one voxel: stimulus, kinetics, stores and
+// the activation / peak / APD90 recorder (per-voxel threshold-crossing test).
+template <typename T, class M>
+__device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int idx, T Vp, T LV)
 {
-    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
-    if (lb >= a.nblk) return;
-
-    int t, idx;
-    uint32_t bits;
-    bool full = false;
-    if (DENSE) {
-        // tile coordinates are workgroup-uniform (scalar unit)
-        const int bx = lb % a.gx, r = lb / a.gx;
-        const int by = r % a.gy, z = r / a.gy;
-        const int x = bx * kTileX + (int)(threadIdx.x % kTileX);
-        const int y = by * kTileY + (int)(threadIdx.x / kTileX);
-        if (x >= a.nx || y >= a.ny) return;
-        idx = x + a.nx * (y + a.ny * z);
-        t = idx;
-        full = bx > 0 && (bx + 1) * kTileX < a.nx && by > 0 && (by + 1) * kTileY < a.ny && z > 0 &&
-               z + 1 < a.nz;
-        const uint32_t px = x + 1 < a.nx, mx = x > 0, py = y + 1 < a.ny, my = y > 0;
-        const uint32_t pz = z + 1 < a.nz, mz = z > 0;
-        bits = px | mx << 1 | py << 2 | my << 3 | pz << 4 | mz << 5;
-        if (ANISO) {
-            bits |= (px & py) << 6 | (mx & my) << 7 | (px & my) << 8 | (mx & py) << 9;
-            bits |= (px & pz) << 10 | (mx & mz) << 11 | (px & mz) << 12 | (mx & pz) << 13;
-            bits |= (py & pz) << 14 | (my & mz) << 15 | (py & mz) << 16 | (my & pz) << 17;
-        }
-    } else {
-        t = lb * kBlock + (int)threadIdx.x;
-        if (t >= a.nact) return;
-        idx = a.idx[t];
-        bits = a.nbr[t];
-    }
-
-    const T *__restrict__ V = a.Vin;
-    const T Vp = V[idx];
-    const T LV = full ? laplacian<T, ANISO, true>(a, V, t, idx, bits, Vp)
-                      : laplacian<T, ANISO, false>(a, V, t, idx, bits, Vp);
-
-    // stimulus current
     T Is = T(0);
     if (a.stim_on) {
         const uint32_t sb = a.stimbits[t] & a.stim_on;
@@ -112,7 +74,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
             if ((sb >> s) & 1u) Is += a.stim_amp[s];
     }
 
-    // kinetics
     T g[M::NV > 1 ? M::NV - 1 : 1];
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) g[i] = a.st[i * a.pitch + t];
@@ -123,7 +84,6 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
     a.Vout[idx] = Vn;
 
-    // activation time / peak / APD90 (per-voxel threshold-crossing recorder)
     if (a.rec) {
         uint8_t s0 = a.status[t];
         if (s0 != 3) {
@@ -150,16 +110,149 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
     }
 }
 
+// Tissue-list path: one thread per tissue voxel, 256 consecutive list entries per
+// workgroup.  Logical workgroup ids are dealt so that XCD k gets the k-th
+// contiguous eighth of the list, keeping neighbour rows and planes in its L2.
+template <typename T, class M, bool ANISO>
+__global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
+{
+    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
+    if (lb >= a.nblk) return;
+    const int t = lb * kBlock + (int)threadIdx.x;
+    if (t >= a.nact) return;
+    const int idx = a.idx[t];
+    const uint32_t bits = a.nbr[t];
+    const T Vp = a.Vin[idx];
+    const T LV = laplacian<T, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
+    update_voxel<T, M>(a, t, idx, Vp, LV);
+}
+
+// Dense-box path (every voxel is tissue): a workgroup owns a 64 x 4 column tile
+// and marches along z through a chunk of a.zc planes.  Three planes of V, each
+// with a one-voxel halo (66 x 6), live in an LDS ring; plane z+2 is fetched into
+// registers while plane z is computed, so every V value is read from memory about
+// once and each wave keeps loads in flight across the loop.
+constexpr int kLX = kTileX + 2, kLY = kTileY + 2, kPlane = kLX * kLY;
+
+template <typename T>
+__device__ __forceinline__ T plane_val(const StepArgs<T> &a, int bx, int by, int p, int e)
+{
+    const int lx = e % kLX, ly = e / kLX;
+    const int x = bx * kTileX + lx - 1, y = by * kTileY + ly - 1;
+    if (p < 0 || p >= a.nz || x < 0 || y < 0 || x >= a.nx || y >= a.ny) return T(0);
+    return a.Vin[x + a.nx * (y + a.ny * p)];
+}
+
+template <typename T, bool FULL>
+__device__ __forceinline__ T lds_d(const T *P, int o, uint32_t bits, int b, T Vp)
+{
+    if (FULL) return P[o] - Vp;
+    return ((bits >> b) & 1u) ? P[o] - Vp : T(0);
+}
+
+template <typename T, bool ANISO, bool FULL>
+__device__ __forceinline__ T laplacian_lds(const StepArgs<T> &a, const T *Pm, const T *Pc,
+                                           const T *Pp, int c, const T *geo, uint32_t bits, T Vp)
+{
+    const T ex_ = lds_d<T, FULL>(Pc, c + 1, bits, 0, Vp), wx = lds_d<T, FULL>(Pc, c - 1, bits, 1, Vp);
+    const T ny_ = lds_d<T, FULL>(Pc, c + kLX, bits, 2, Vp), sy_ = lds_d<T, FULL>(Pc, c - kLX, bits, 3, Vp);
+    const T up = lds_d<T, FULL>(Pp, c, bits, 4, Vp), dn = lds_d<T, FULL>(Pm, c, bits, 5, Vp);
+    if (!ANISO) return a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dn));
+    const T fx = geo[0], fy = geo[1], fz = geo[2];
+    const T cx = geo[3], cy = geo[4], cz = geo[5];
+    const T dd = a.Dpar - a.Dperp;
+    const T Dxx = a.Dperp + dd * fx * fx, Dyy = a.Dperp + dd * fy * fy;
+    const T Dzz = a.Dperp + dd * fz * fz;
+    const T Dxy = dd * fx * fy, Dxz = dd * fx * fz, Dyz = dd * fy * fz;
+    const T exy = lds_d<T, FULL>(Pc, c + 1 + kLX, bits, 6, Vp) + lds_d<T, FULL>(Pc, c - 1 - kLX, bits, 7, Vp)
+                  - lds_d<T, FULL>(Pc, c + 1 - kLX, bits, 8, Vp) - lds_d<T, FULL>(Pc, c - 1 + kLX, bits, 9, Vp);
+    const T exz = lds_d<T, FULL>(Pp, c + 1, bits, 10, Vp) + lds_d<T, FULL>(Pm, c - 1, bits, 11, Vp)
+                  - lds_d<T, FULL>(Pm, c + 1, bits, 12, Vp) - lds_d<T, FULL>(Pp, c - 1, bits, 13, Vp);
+    const T eyz = lds_d<T, FULL>(Pp, c + kLX, bits, 14, Vp) + lds_d<T, FULL>(Pm, c - kLX, bits, 15, Vp)
+                  - lds_d<T, FULL>(Pm, c + kLX, bits, 16, Vp) - lds_d<T, FULL>(Pp, c - kLX, bits, 17, Vp);
+    return a.ih2 * (Dxx * (ex_ + wx) + Dyy * (ny_ + sy_) + Dzz * (up + dn)
+                    + T(0.5) * (Dxy * exy + Dxz * exz + Dyz * eyz))
+           + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
+}
+
+template <typename T, class M, bool ANISO>
+__global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
+{
+    __shared__ T ring[3][kPlane];
+    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
+    if (lb >= a.nblk) return;                       // workgroup-uniform exit
+    const int bx = lb % a.gx, r = lb / a.gx;
+    const int by = r % a.gy, bz = r / a.gy;
+    const int z0 = bz * a.zc, z1 = min(a.nz, z0 + a.zc);
+    const int tx = (int)(threadIdx.x % kTileX), ty = (int)(threadIdx.x / kTileX);
+    const int x = bx * kTileX + tx, y = by * kTileY + ty;
+    const bool own = x < a.nx && y < a.ny;
+    const int e0 = (int)threadIdx.x, e1 = e0 + kBlock;    // this thread's plane elements
+    const bool has1 = e1 < kPlane;
+    const int c = (ty + 1) * kLX + tx + 1;                 // own position in a plane
+    const bool xy_in = bx > 0 && (bx + 1) * kTileX < a.nx && by > 0 && (by + 1) * kTileY < a.ny;
+    const uint32_t px = x + 1 < a.nx, mx = x > 0, py = y + 1 < a.ny, my = y > 0;
+
+    // planes z0-1, z0, z0+1 -> ring slots 0, 1, 2 (slot of plane p: (p - z0 + 1) % 3)
+    for (int k = 0; k < 3; k++) {
+        ring[k][e0] = plane_val(a, bx, by, z0 - 1 + k, e0);
+        if (has1) ring[k][e1] = plane_val(a, bx, by, z0 - 1 + k, e1);
+    }
+    // this column's fibre and face coefficients at plane z0
+    const int64_t col = (int64_t)x + (int64_t)a.nx * y, plane = (int64_t)a.nx * a.ny;
+    T geo[6] = {};
+    if (ANISO && own)
+        for (int i = 0; i < 6; i++) geo[i] = a.geo[6 * (col + plane * z0) + i];
+    __syncthreads();
+
+    for (int z = z0; z < z1; z++) {
+        const int k = z - z0;
+        // prefetch plane z+2 of V (needed while z+1 < z1) and the geometry of z+1
+        const bool pre = z + 1 < z1;
+        T q0 = T(0), q1 = T(0);
+        T gnext[6] = {};
+        if (pre) {
+            q0 = plane_val(a, bx, by, z + 2, e0);
+            if (has1) q1 = plane_val(a, bx, by, z + 2, e1);
+            if (ANISO && own)
+                for (int i = 0; i < 6; i++) gnext[i] = a.geo[6 * (col + plane * (z + 1)) + i];
+        }
+        if (own) {
+            const T *Pm = ring[k % 3], *Pc = ring[(k + 1) % 3], *Pp = ring[(k + 2) % 3];
+            const int idx = x + a.nx * (y + a.ny * z);
+            const uint32_t pz = z + 1 < a.nz, mz = z > 0;
+            uint32_t bits = px | mx << 1 | py << 2 | my << 3 | pz << 4 | mz << 5;
+            if (ANISO) {
+                bits |= (px & py) << 6 | (mx & my) << 7 | (px & my) << 8 | (mx & py) << 9;
+                bits |= (px & pz) << 10 | (mx & mz) << 11 | (px & mz) << 12 | (mx & pz) << 13;
+                bits |= (py & pz) << 14 | (my & mz) << 15 | (py & mz) << 16 | (my & pz) << 17;
+            }
+            const T Vp = Pc[c];
+            const bool full = xy_in && z > 0 && z + 1 < a.nz;
+            const T LV = full ? laplacian_lds<T, ANISO, true>(a, Pm, Pc, Pp, c, geo, bits, Vp)
+                              : laplacian_lds<T, ANISO, false>(a, Pm, Pc, Pp, c, geo, bits, Vp);
+            update_voxel<T, M>(a, idx, idx, Vp, LV);
+        }
+        __syncthreads();                                   // slot of plane z-1 is free
+        if (pre) {
+            ring[k % 3][e0] = q0;
+            if (has1) ring[k % 3][e1] = q1;
+            for (int i = 0; i < 6; i++) geo[i] = gnext[i];
+        }
+        __syncthreads();
+    }
+}
+
 template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
     const dim3 grid(a.per_xcd * kXcd), block(kBlock);
     if (a.dense) {
-        if (aniso) hipLaunchKernelGGL((k_step<T, M, true, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step<T, M, false, true>), grid, block, 0, s, a);
+        if (aniso) hipLaunchKernelGGL((k_step_dense<T, M, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step_dense<T, M, false>), grid, block, 0, s, a);
     } else {
-        if (aniso) hipLaunchKernelGGL((k_step<T, M, true, false>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step<T, M, false, false>), grid, block, 0, s, a);
+        if (aniso) hipLaunchKernelGGL((k_step<T, M, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step<T, M, false>), grid, block, 0, s, a);
     }
     return hipGetLastError();
 }
