@@ -96,9 +96,11 @@ enum {
                                  fixed summation order: deterministic) */
     BBX_READ_NAN_FLAG = 7,    /* int32[1]: 1 if any state value is not finite */
     BBX_READ_STEP = 8,        /* int64[1]: number of steps taken (t = step * dt) */
-    BBX_READ_WEIGHTS = 9      /* double[nact*27]: the effective stencil weights W^p_q of
+    BBX_READ_WEIGHTS = 9,     /* double[nact*27]: the effective stencil weights W^p_q of
                                  every tissue voxel p (increasing box order), q = (dx,dy,dz)
                                  at (dz+1)*9 + (dy+1)*3 + (dx+1), centre = -sum of others */
+    BBX_READ_FALLBACK_COUNT = 10  /* int64[1]: voxel updates that fell back from the
+                                     surrogate to the plain kinetics since it was attached */
 };
 
 /* Info queries for bbx_info. */
@@ -174,6 +176,82 @@ int bbx_step(bbx_grid *g, int64_t nsteps);
  * out_on_device = 0: host pointer, the call synchronises the stream. */
 int bbx_readout(bbx_grid *g, int what, int var, const uint8_t *region, void *out,
                 size_t out_bytes, int out_on_device);
+
+/* ------------------------------------------------------------------------
+ * Surrogate ionic map.  A network nin -> 128 -> 128 -> nout with SiLU
+ * activations stands in for the kinetic one-step map of the explicit scheme,
+ * (V, g) -> (V + dt(-I_ion(V, g)), g+) (eq (Euler) with Rush-Larsen gates,
+ * eqs (RL), (RLcoeff)), on normalised inputs x = (s - mu_in) * in_scale and
+ * normalised increments d = ((s+ - s) - mu_out) / sigma_out.  Weights are
+ * kept in FP32 (master) and BF16 (the copies the MFMA kernels read);
+ * activations are BF16, accumulation FP32.  Parameters use the flat layout
+ * W1[128][nin], b1[128], W2[128][128], b2[128], W3[nout][128], b3[nout].
+ * ---------------------------------------------------------------------- */
+typedef struct bbx_mlp bbx_mlp;
+
+/* Create a network (1 <= nin, nout <= 32) with weights drawn from a seeded
+ * counter-based generator (uniform, scaled by 1/sqrt(fan_in)), biases 0,
+ * identity normalisation and zero Adam moments.  Work is enqueued on
+ * hip_stream (NULL = null stream). */
+int bbx_mlp_create(int nin, int nout, uint64_t seed, void *hip_stream, bbx_mlp **out);
+
+/* Copy the FP32 master parameters (count = number of parameters) to the host
+ * (set = 0) or from the host (set = 1; refreshes the BF16 copies). */
+int bbx_mlp_params(bbx_mlp *m, int set, float *host, size_t count);
+
+/* Copy the normalisation [4][32] = in_mean, in_scale, out_mean, out_sigma to
+ * (set = 0) or from (set = 1) the host. */
+int bbx_mlp_norm(bbx_mlp *m, int set, float *host);
+
+/* Fit the normalisation to training pairs on the device: S [n][nin] states
+ * and S1 [n][nout] the states one step later (row-major per sample; nin must
+ * equal nout).  Sets in_mean/in_scale from the states and out_mean/out_sigma
+ * from the increments S1 - S (scale 1 where a feature is constant).  If stats
+ * is not NULL it receives double[7][32]: mean, std, min, max of the states,
+ * then mean, std, max |.| of the increments. */
+int bbx_mlp_fit_norm(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n,
+                     double *stats);
+
+/* Network outputs for n normalised inputs X [n][nin] (device) into Y [n][nout]
+ * (device): the raw network, no normalisation applied. */
+int bbx_mlp_forward(bbx_mlp *m, const float *X_dev, int64_t n, float *Y_dev);
+
+/* Mean-squared-error loss over the n samples and nout outputs of
+ * (network(X) - T), X [n][nin], T [n][nout] on the device, and its gradient
+ * with respect to the parameters, left in the network for bbx_mlp_adam and
+ * copied to grad_host (nparams floats) if not NULL.  n <= 65536. */
+int bbx_mlp_grad(bbx_mlp *m, const float *X_dev, const float *T_dev, int64_t n, float *grad_host,
+                 double *loss);
+
+/* One Adam step (bias-corrected) with the last gradient. */
+int bbx_mlp_adam(bbx_mlp *m, float lr, float beta1, float beta2, float eps);
+
+/* Train on raw pairs (S, S1 as in bbx_mlp_fit_norm, normalised with the
+ * network's current normalisation): iters minibatch Adam steps of `batch`
+ * samples (<= 65536) drawn with replacement by a counter-based generator.
+ * loss_hist (iters floats, may be NULL) receives each step's batch loss. */
+int bbx_mlp_train(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n, int64_t batch,
+                  int64_t iters, float lr, uint64_t seed, float *loss_hist);
+
+/* Free the network. */
+void bbx_mlp_destroy(bbx_mlp *m);
+
+/* Write the state of n tissue voxels drawn uniformly with replacement (seeded
+ * counter-based generator) to out [n][nvar] (device, FP32). */
+int bbx_sample_states(bbx_grid *g, int64_t n, uint64_t seed, float *out_dev);
+
+/* Apply the grid's plain kinetic one-step map (model, parameters and dt; no
+ * diffusion, no stimulus) to n states in [n][nvar] (device, FP32) -> out. */
+int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev);
+
+/* Attach a trained network as the kinetics of an FP32 grid (NULL detaches).
+ * nin = nout = the model's nvar.  Each step then evaluates the network for
+ * every tissue voxel and falls back to the plain kinetics for a voxel whose
+ * kinetic input leaves [lo, hi] (nvar floats each), whose predicted gates
+ * leave [0, 1], whose predicted |dV| exceeds dv_max, or whose prediction is
+ * not finite.  The network's weights are copied; it may be destroyed after. */
+int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi,
+                      float dv_max);
 
 /* Integer facts about a grid (BBX_INFO_*). */
 int bbx_info(const bbx_grid *g, int what, int64_t *out);

@@ -24,7 +24,7 @@ BBX_SCHEME_ADDITIVE, BBX_SCHEME_SPLIT = 0, 1
 BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN = 0, 1, 2, 3, 4
 (BBX_READ_VAR, BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX, BBX_READ_STATUS,
  BBX_READ_REDUCE_MAX, BBX_READ_REDUCE_SUM, BBX_READ_NAN_FLAG, BBX_READ_STEP,
- BBX_READ_WEIGHTS) = range(10)
+ BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT) = range(11)
 BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -43,6 +43,18 @@ SIGNATURES = {
     "bbx_info": (_I, [_P, _I, C.POINTER(_I64)]),
     "bbx_grid_destroy": (None, [_P]),
     "bbx_last_error": (C.c_char_p, []),
+    "bbx_mlp_create": (_I, [_I, _I, C.c_uint64, _P, C.POINTER(_P)]),
+    "bbx_mlp_params": (_I, [_P, _I, _P, _SZ]),
+    "bbx_mlp_norm": (_I, [_P, _I, _P]),
+    "bbx_mlp_fit_norm": (_I, [_P, _P, _P, _I64, _P]),
+    "bbx_mlp_forward": (_I, [_P, _P, _I64, _P]),
+    "bbx_mlp_grad": (_I, [_P, _P, _P, _I64, _P, _P]),
+    "bbx_mlp_adam": (_I, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "bbx_mlp_train": (_I, [_P, _P, _P, _I64, _I64, _I64, C.c_float, C.c_uint64, _P]),
+    "bbx_mlp_destroy": (None, [_P]),
+    "bbx_sample_states": (_I, [_P, _I64, C.c_uint64, _P]),
+    "bbx_ionic_map": (_I, [_P, _P, _I64, _P]),
+    "bbx_surrogate_set": (_I, [_P, _P, _P, _P, C.c_float]),
 }
 
 
@@ -217,6 +229,15 @@ class Grid:
     def clock(self, step):
         bbx_clock_set(self.handle, step)
 
+    def sample_states(self, n, seed, out):
+        bbx_sample_states(self.handle, n, seed, out)
+
+    def ionic_map(self, inp, out):
+        bbx_ionic_map(self.handle, inp, inp.shape[0], out)
+
+    def surrogate(self, mlp, lo, hi, dv_max):
+        bbx_surrogate_set(self.handle, None if mlp is None else mlp.handle, lo, hi, dv_max)
+
     def get(self, var=0):
         out = np.empty(self.shape, np.float64)
         return bbx_readout(self.handle, BBX_READ_VAR, var, None, out)
@@ -228,7 +249,7 @@ class Grid:
             out = np.empty(1, np.float64)
         elif what == BBX_READ_NAN_FLAG:
             out = np.empty(1, np.int32)
-        elif what == BBX_READ_STEP:
+        elif what in (BBX_READ_STEP, BBX_READ_FALLBACK_COUNT):
             out = np.empty(1, np.int64)
         elif what == BBX_READ_WEIGHTS:
             out = np.empty((self.nact, 27), np.float64)
@@ -236,3 +257,135 @@ class Grid:
             out = np.empty(self.shape, np.float64)
         bbx_readout(self.handle, what, var, region, out)
         return out
+
+
+# ---------------------------------------------------------------- surrogate network
+def _dptr(t):
+    """Device address of a contiguous torch tensor (or an int address)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return C.c_void_p(t)
+    if not t.is_contiguous():
+        raise ValueError("device tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def bbx_mlp_create(nin, nout, seed, hip_stream=None):
+    out = C.c_void_p()
+    _check(_lib.bbx_mlp_create(int(nin), int(nout), int(seed) & (2 ** 64 - 1),
+                               _stream_handle(hip_stream), C.byref(out)))
+    return out
+
+
+def bbx_mlp_params(m, set_, host):
+    host = np.ascontiguousarray(host, dtype=np.float32) if set_ else host
+    _check(_lib.bbx_mlp_params(m, int(set_), _ptr(host), host.size))
+    return host
+
+
+def bbx_mlp_norm(m, set_, host):
+    _check(_lib.bbx_mlp_norm(m, int(set_), _ptr(host)))
+    return host
+
+
+def bbx_mlp_fit_norm(m, S, S1, n, stats=None):
+    _check(_lib.bbx_mlp_fit_norm(m, _dptr(S), _dptr(S1), int(n), _ptr(stats)))
+    return stats
+
+
+def bbx_mlp_forward(m, X, n, Y):
+    _check(_lib.bbx_mlp_forward(m, _dptr(X), int(n), _dptr(Y)))
+
+
+def bbx_mlp_grad(m, X, T, n, grad_host=None):
+    loss = np.zeros(1, np.float64)
+    _check(_lib.bbx_mlp_grad(m, _dptr(X), _dptr(T), int(n), _ptr(grad_host), _ptr(loss)))
+    return loss[0]
+
+
+def bbx_mlp_adam(m, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(_lib.bbx_mlp_adam(m, float(lr), float(beta1), float(beta2), float(eps)))
+
+
+def bbx_mlp_train(m, S, S1, n, batch, iters, lr, seed, loss_hist=None):
+    _check(_lib.bbx_mlp_train(m, _dptr(S), _dptr(S1), int(n), int(batch), int(iters), float(lr),
+                              int(seed) & (2 ** 64 - 1), _ptr(loss_hist)))
+    return loss_hist
+
+
+def bbx_mlp_destroy(m):
+    _lib.bbx_mlp_destroy(m)
+
+
+def bbx_sample_states(g, n, seed, out):
+    _check(_lib.bbx_sample_states(g, int(n), int(seed) & (2 ** 64 - 1), _dptr(out)))
+
+
+def bbx_ionic_map(g, inp, n, out):
+    _check(_lib.bbx_ionic_map(g, _dptr(inp), int(n), _dptr(out)))
+
+
+def bbx_surrogate_set(g, m, lo=None, hi=None, dv_max=0.0):
+    """Attach network m (None detaches)."""
+    if m is None:
+        _check(_lib.bbx_surrogate_set(g, None, None, None, 0.0))
+        return
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    hi = np.ascontiguousarray(hi, dtype=np.float32)
+    _check(_lib.bbx_surrogate_set(g, m, _ptr(lo), _ptr(hi), float(dv_max)))
+
+
+class Mlp:
+    """Owning wrapper of a surrogate network nin -> 128 -> 128 -> nout."""
+
+    def __init__(self, nin, nout, seed=0, stream=None):
+        self.nin, self.nout = nin, nout
+        self.handle = bbx_mlp_create(nin, nout, seed, stream)
+
+    def close(self):
+        if self.handle is not None:
+            bbx_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def nparams(self):
+        return 128 * self.nin + 128 + 128 * 128 + 128 + self.nout * 128 + self.nout
+
+    def get_params(self):
+        return bbx_mlp_params(self.handle, 0, np.empty(self.nparams, np.float32))
+
+    def set_params(self, p):
+        bbx_mlp_params(self.handle, 1, p)
+
+    def get_norm(self):
+        return bbx_mlp_norm(self.handle, 0, np.empty((4, 32), np.float32))
+
+    def set_norm(self, norm):
+        bbx_mlp_norm(self.handle, 1, np.ascontiguousarray(norm, dtype=np.float32))
+
+    def fit_norm(self, S, S1):
+        stats = np.zeros((7, 32), np.float64)
+        return bbx_mlp_fit_norm(self.handle, S, S1, S.shape[0], stats)
+
+    def forward(self, X, Y):
+        bbx_mlp_forward(self.handle, X, X.shape[0], Y)
+
+    def grad(self, X, T, with_host=True):
+        gh = np.empty(self.nparams, np.float32) if with_host else None
+        loss = bbx_mlp_grad(self.handle, X, T, X.shape[0], gh)
+        return loss, gh
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        bbx_mlp_adam(self.handle, lr, beta1, beta2, eps)
+
+    def train(self, S, S1, batch, iters, lr, seed=0):
+        hist = np.empty(iters, np.float32)
+        bbx_mlp_train(self.handle, S, S1, S.shape[0], batch, iters, lr, seed, hist)
+        return hist

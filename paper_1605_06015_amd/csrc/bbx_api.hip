@@ -7,10 +7,12 @@
 #include <string.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/bbx.h"
 #include "bbx_internal.h"
+#include "mlp_internal.h"
 
 using namespace bbx;
 
@@ -111,6 +113,13 @@ struct bbx_grid {
     void *d_at = nullptr, *d_vmax = nullptr, *d_apd = nullptr, *d_vrep = nullptr;
 
     int64_t n = 0, nan_every = 1000;
+    // attached surrogate (FP32 grids): network copy, accepted box, fallback list
+    int sur = 0;
+    MlpDev snet = {};
+    float *d_slo = nullptr, *d_shi = nullptr;
+    float dv_max = 0;
+    int32_t *d_fb_list = nullptr, *d_fb_cnt = nullptr;
+    unsigned long long *d_fb_total = nullptr;
     double *d_parts = nullptr, *d_red = nullptr;
     int *d_flag = nullptr;
     int nparts = 1024;
@@ -140,7 +149,9 @@ void free_all(bbx_grid *g)
 {
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
-                  g->d_vrep, g->d_parts, g->d_red, g->d_flag};
+                  g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
+                  g->d_fb_list, g->d_fb_cnt, g->d_fb_total, g->snet.w1, g->snet.w2, g->snet.w3,
+                  g->snet.bias, g->snet.norm};
     for (void *p : ps) dfree(p);
 }
 
@@ -228,6 +239,20 @@ uint32_t stim_mask(const bbx_grid *g, int64_t n)
     return m;
 }
 
+SurArgs sur_args(const bbx_grid *g, int parity)
+{
+    SurArgs su;
+    su.net = g->snet;
+    su.lo = g->d_slo;
+    su.hi = g->d_shi;
+    su.dv_max = g->dv_max;
+    su.fb_list = g->d_fb_list;
+    su.fb_cnt = g->d_fb_cnt;
+    su.fb_total = g->d_fb_total;
+    su.parity = parity;
+    return su;
+}
+
 template <typename T>
 int step_impl(bbx_grid *g, int64_t nsteps)
 {
@@ -240,7 +265,21 @@ int step_impl(bbx_grid *g, int64_t nsteps)
         a.Vout = (T *)g->d_V[g->cur ^ 1];
         a.stim_on = g->stims.empty() ? 0u : stim_mask(g, n);
         a.tn = (T)((double)n * g->dt);
-        if (g->nact > 0) HIP_TRY(launch_step<T>(g->model, g->aniso, a, g->stream), "step launch");
+        if (g->nact > 0) {
+            bool done = false;
+            if constexpr (std::is_same<T, float>::value) {
+                if (g->sur) {
+                    StepArgs<float> b = a;
+                    b.nblk = (int)((g->nact + kSurBlock - 1) / kSurBlock);
+                    b.per_xcd = (b.nblk + kXcd - 1) / kXcd;
+                    const SurArgs su = sur_args(g, (int)(n & 1));
+                    HIP_TRY(launch_surrogate_step(g->model, g->aniso, b, su, g->stream), "surrogate step");
+                    HIP_TRY(launch_fallback(g->model, g->aniso, b, su, g->stream), "fallback");
+                    done = true;
+                }
+            }
+            if (!done) HIP_TRY(launch_step<T>(g->model, g->aniso, a, g->stream), "step launch");
+        }
         g->cur ^= 1;
         if (g->nan_every > 0 && (n + 1) % g->nan_every == 0)
             HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense,
@@ -542,6 +581,18 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
         HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
         return BBX_OK;
     }
+    case BBX_READ_FALLBACK_COUNT: {
+        if (on_dev) return fail(BBX_ENOTSUP, "FALLBACK_COUNT is read to host memory only");
+        if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
+        unsigned long long v = 0;
+        if (g->d_fb_total) {
+            HIP_TRY(hipMemcpyAsync(&v, g->d_fb_total, sizeof v, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+            HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        }
+        int64_t o = (int64_t)v;
+        memcpy(out, &o, sizeof o);
+        return BBX_OK;
+    }
     case BBX_READ_STEP: {
         if (on_dev) return fail(BBX_ENOTSUP, "STEP is read to host memory only");
         if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
@@ -746,6 +797,8 @@ int bbx_clock_set(bbx_grid *g, int64_t step)
     g_err.clear();
     if (!g) return fail(BBX_EINVAL, "grid is NULL");
     if (step < 0) return fail(BBX_EINVAL, "step must be >= 0");
+    // the fallback list lengths alternate with the step's parity: restart both
+    if (g->d_fb_cnt) HIP_TRY(hipMemsetAsync(g->d_fb_cnt, 0, 2 * sizeof(int32_t), g->stream), "hipMemsetAsync");
     g->n = step;
     return BBX_OK;
 }
@@ -796,6 +849,368 @@ void bbx_grid_destroy(bbx_grid *g)
     (void)hipStreamSynchronize(g->stream);
     free_all(g);
     delete g;
+}
+
+}  // extern "C"
+
+// ============================================================================ surrogate network
+
+struct bbx_mlp {
+    int nin = 0, nout = 0, np = 0;
+    hipStream_t stream = nullptr;
+    float *d_p = nullptr, *d_g = nullptr, *d_m = nullptr, *d_v = nullptr;
+    double *d_loss = nullptr, *d_stats = nullptr;
+    int64_t t = 0;           // Adam steps taken
+    MlpDev dev = {};
+    MlpScratch w = {};
+    int64_t cap = 0;         // batch capacity of the scratch (rounded to 32)
+    std::vector<void *> bufs;
+};
+
+namespace {
+
+hipError_t mlp_alloc(bbx_mlp *m, void **p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes ? bytes : 1);
+    if (e == hipSuccess) m->bufs.push_back(*p);
+    return e;
+}
+
+void mlp_free(bbx_mlp *m)
+{
+    for (void *p : m->bufs) (void)hipFree(p);
+    m->bufs.clear();
+}
+
+int mlp_scratch(bbx_mlp *m, int64_t B)
+{
+    const int64_t Bp = (B + 31) / 32 * 32;
+    if (Bp <= m->cap) return BBX_OK;
+    void *ps[] = {m->w.xb, m->w.tt, m->w.xf, m->w.h1, m->w.h2, m->w.dz1, m->w.dz2, m->w.dO, m->w.part};
+    for (void *p : ps) {
+        if (!p) continue;
+        for (size_t i = 0; i < m->bufs.size(); i++)
+            if (m->bufs[i] == p) { (void)hipFree(p); m->bufs.erase(m->bufs.begin() + i); break; }
+    }
+    m->w = MlpScratch{};
+    m->cap = 0;
+    hipError_t e;
+    const size_t bf = sizeof(__bf16);
+    if ((e = mlp_alloc(m, (void **)&m->w.xb, Bp * kP * bf)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = mlp_alloc(m, (void **)&m->w.tt, Bp * kP * sizeof(float))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = mlp_alloc(m, (void **)&m->w.xf, Bp * kP * bf)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = mlp_alloc(m, (void **)&m->w.dO, Bp * kP * bf)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    __bf16 **hs[] = {&m->w.h1, &m->w.h2, &m->w.dz1, &m->w.dz2};
+    for (__bf16 **h : hs)
+        if ((e = mlp_alloc(m, (void **)h, Bp * kH * bf)) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if ((e = mlp_alloc(m, (void **)&m->w.part, (Bp / 16) * kPart * sizeof(float))) != hipSuccess)
+        return hip_fail(e, "hipMalloc");
+    m->cap = Bp;
+    return BBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbx_mlp_create(int nin, int nout, uint64_t seed, void *hip_stream, bbx_mlp **out)
+{
+    try {
+        g_err.clear();
+        if (!out) return fail(BBX_EINVAL, "out is NULL");
+        *out = nullptr;
+        if (nin < 1 || nin > kP || nout < 1 || nout > kP)
+            return fail(BBX_EINVAL, "nin and nout must be in [1, %d]", kP);
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BBX_EDEVICE, "no HIP device");
+        bbx_mlp *m = new bbx_mlp();
+        m->nin = nin;
+        m->nout = nout;
+        m->np = mlp_nparams(nin, nout);
+        m->stream = (hipStream_t)hip_stream;
+        m->dev.nin = nin;
+        m->dev.nout = nout;
+        hipError_t e = hipSuccess;
+        const size_t pb = (size_t)m->np * sizeof(float);
+        float **fs[] = {&m->d_p, &m->d_g, &m->d_m, &m->d_v};
+        for (float **f : fs)
+            if (e == hipSuccess) e = mlp_alloc(m, (void **)f, pb);
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->d_loss, sizeof(double));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->d_stats, 2 * kP * 4 * sizeof(double));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.w1, kH * kS1 * sizeof(__bf16));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.w3t, kH * kS1 * sizeof(__bf16));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.w2, kH * kS2 * sizeof(__bf16));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.w2t, kH * kS2 * sizeof(__bf16));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.w3, kP * kS2 * sizeof(__bf16));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.bias, (2 * kH + kP) * sizeof(float));
+        if (e == hipSuccess) e = mlp_alloc(m, (void **)&m->dev.norm, 4 * kP * sizeof(float));
+        if (e != hipSuccess) {
+            mlp_free(m);
+            delete m;
+            return hip_fail(e, "hipMalloc");
+        }
+        float norm[4 * kP];
+        for (int i = 0; i < kP; i++) {
+            norm[i] = 0.f;
+            norm[kP + i] = 1.f;
+            norm[2 * kP + i] = 0.f;
+            norm[3 * kP + i] = 1.f;
+        }
+        hipStream_t st = m->stream;
+        if ((e = hipMemcpyAsync(m->dev.norm, norm, sizeof norm, hipMemcpyHostToDevice, st)) == hipSuccess &&
+            (e = hipMemsetAsync(m->d_m, 0, pb, st)) == hipSuccess &&
+            (e = hipMemsetAsync(m->d_v, 0, pb, st)) == hipSuccess &&
+            (e = hipMemsetAsync(m->d_g, 0, pb, st)) == hipSuccess &&
+            (e = mlp_init(m->d_p, nin, nout, seed, st)) == hipSuccess &&
+            (e = mlp_pack(m->d_p, m->dev, st)) == hipSuccess)
+            e = hipStreamSynchronize(st);
+        if (e != hipSuccess) {
+            mlp_free(m);
+            delete m;
+            return hip_fail(e, "network initialisation");
+        }
+        *out = m;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_mlp_params(bbx_mlp *m, int set, float *host, size_t count)
+{
+    g_err.clear();
+    if (!m || !host) return fail(BBX_EINVAL, "NULL argument");
+    if (count != (size_t)m->np) return fail(BBX_EINVAL, "the network has %d parameters", m->np);
+    if (set) {
+        for (size_t i = 0; i < count; i++)
+            if (!isfinite(host[i])) return fail(BBX_EINVAL, "parameter %zu is not finite", i);
+        HIP_TRY(hipMemcpyAsync(m->d_p, host, count * sizeof(float), hipMemcpyHostToDevice, m->stream), "hipMemcpyAsync");
+        HIP_TRY(mlp_pack(m->d_p, m->dev, m->stream), "pack");
+    } else {
+        HIP_TRY(hipMemcpyAsync(host, m->d_p, count * sizeof(float), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+    }
+    HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return BBX_OK;
+}
+
+int bbx_mlp_norm(bbx_mlp *m, int set, float *host)
+{
+    g_err.clear();
+    if (!m || !host) return fail(BBX_EINVAL, "NULL argument");
+    if (set) {
+        for (int i = 0; i < 4 * kP; i++)
+            if (!isfinite(host[i])) return fail(BBX_EINVAL, "normalisation entry %d is not finite", i);
+        for (int i = 0; i < kP; i++)
+            if (host[3 * kP + i] == 0.f) return fail(BBX_EINVAL, "out_sigma %d is zero", i);
+        HIP_TRY(hipMemcpyAsync(m->dev.norm, host, 4 * kP * sizeof(float), hipMemcpyHostToDevice, m->stream), "hipMemcpyAsync");
+    } else {
+        HIP_TRY(hipMemcpyAsync(host, m->dev.norm, 4 * kP * sizeof(float), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+    }
+    HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return BBX_OK;
+}
+
+int bbx_mlp_fit_norm(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n, double *stats)
+{
+    try {
+        g_err.clear();
+        if (!m || !S_dev || !S1_dev) return fail(BBX_EINVAL, "NULL argument");
+        if (m->nin != m->nout) return fail(BBX_EINVAL, "fitting needs nin == nout");
+        if (n < 2) return fail(BBX_EINVAL, "need at least 2 samples");
+        HIP_TRY(mlp_stats(S_dev, S1_dev, n, m->nin, m->d_stats, m->stream), "stats");
+        std::vector<double> st(2 * kP * 4);
+        HIP_TRY(hipMemcpyAsync(st.data(), m->d_stats, st.size() * sizeof(double), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        float norm[4 * kP];
+        for (int i = 0; i < kP; i++) {
+            const double mi = st[i * 4], si = st[i * 4 + 1];
+            const double mo = st[(kP + i) * 4], so = st[(kP + i) * 4 + 1];
+            norm[i] = (float)mi;
+            norm[kP + i] = (float)(si > 0 ? 1.0 / si : 1.0);
+            norm[2 * kP + i] = (float)mo;
+            norm[3 * kP + i] = (float)(so > 0 ? so : 1.0);
+        }
+        HIP_TRY(hipMemcpyAsync(m->dev.norm, norm, sizeof norm, hipMemcpyHostToDevice, m->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        if (stats) {
+            for (int i = 0; i < kP; i++) {
+                stats[0 * kP + i] = st[i * 4];
+                stats[1 * kP + i] = st[i * 4 + 1];
+                stats[2 * kP + i] = st[i * 4 + 2];
+                stats[3 * kP + i] = st[i * 4 + 3];
+                stats[4 * kP + i] = st[(kP + i) * 4];
+                stats[5 * kP + i] = st[(kP + i) * 4 + 1];
+                stats[6 * kP + i] = fmax(fabs(st[(kP + i) * 4 + 2]), fabs(st[(kP + i) * 4 + 3]));
+            }
+        }
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_mlp_forward(bbx_mlp *m, const float *X_dev, int64_t n, float *Y_dev)
+{
+    g_err.clear();
+    if (!m || !X_dev || !Y_dev) return fail(BBX_EINVAL, "NULL argument");
+    if (n < 0) return fail(BBX_EINVAL, "n must be >= 0");
+    HIP_TRY(mlp_forward(m->dev, X_dev, n, Y_dev, m->stream), "forward");
+    return BBX_OK;
+}
+
+int bbx_mlp_grad(bbx_mlp *m, const float *X_dev, const float *T_dev, int64_t n, float *grad_host,
+                 double *loss)
+{
+    try {
+        g_err.clear();
+        if (!m || !X_dev || !T_dev) return fail(BBX_EINVAL, "NULL argument");
+        if (n < 1 || n > kMaxBatch) return fail(BBX_EINVAL, "n must be in [1, %lld]", (long long)kMaxBatch);
+        int rc = mlp_scratch(m, n);
+        if (rc) return rc;
+        HIP_TRY(mlp_grad(m->dev, m->w, 0, X_dev, T_dev, n, n, 0, 0, m->d_g, m->d_loss, m->stream), "gradient");
+        if (grad_host)
+            HIP_TRY(hipMemcpyAsync(grad_host, m->d_g, m->np * sizeof(float), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+        if (loss) HIP_TRY(hipMemcpyAsync(loss, m->d_loss, sizeof(double), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_mlp_adam(bbx_mlp *m, float lr, float beta1, float beta2, float eps)
+{
+    g_err.clear();
+    if (!m) return fail(BBX_EINVAL, "NULL argument");
+    if (!(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(BBX_EINVAL, "bad Adam hyper-parameters");
+    m->t += 1;
+    HIP_TRY(mlp_adam(m->d_p, m->d_m, m->d_v, m->d_g, m->np, lr, beta1, beta2, eps, m->t, m->stream), "adam");
+    HIP_TRY(mlp_pack(m->d_p, m->dev, m->stream), "pack");
+    return BBX_OK;
+}
+
+int bbx_mlp_train(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n, int64_t batch,
+                  int64_t iters, float lr, uint64_t seed, float *loss_hist)
+{
+    try {
+        g_err.clear();
+        if (!m || !S_dev || !S1_dev) return fail(BBX_EINVAL, "NULL argument");
+        if (m->nin != m->nout) return fail(BBX_EINVAL, "training on state pairs needs nin == nout");
+        if (n < 1 || batch < 1 || batch > kMaxBatch || iters < 0)
+            return fail(BBX_EINVAL, "bad n / batch / iters");
+        if (!(lr > 0)) return fail(BBX_EINVAL, "lr must be positive");
+        int rc = mlp_scratch(m, batch);
+        if (rc) return rc;
+        DevBuf lh;
+        if (loss_hist && iters > 0) HIP_TRY(hipMalloc(&lh.p, iters * sizeof(double)), "hipMalloc");
+        for (int64_t it = 0; it < iters; it++) {
+            double *ls = lh.p ? (double *)lh.p + it : m->d_loss;
+            HIP_TRY(mlp_grad(m->dev, m->w, 1, S_dev, S1_dev, n, batch, seed, (uint64_t)it, m->d_g, ls,
+                             m->stream), "gradient");
+            m->t += 1;
+            HIP_TRY(mlp_adam(m->d_p, m->d_m, m->d_v, m->d_g, m->np, lr, 0.9f, 0.999f, 1e-8f, m->t,
+                             m->stream), "adam");
+            HIP_TRY(mlp_pack(m->d_p, m->dev, m->stream), "pack");
+        }
+        if (lh.p) {
+            std::vector<double> tmp((size_t)iters);
+            HIP_TRY(hipMemcpyAsync(tmp.data(), lh.p, iters * sizeof(double), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
+            HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+            for (int64_t i = 0; i < iters; i++) loss_hist[i] = (float)tmp[(size_t)i];
+        }
+        HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+void bbx_mlp_destroy(bbx_mlp *m)
+{
+    if (!m) return;
+    (void)hipStreamSynchronize(m->stream);
+    mlp_free(m);
+    delete m;
+}
+
+int bbx_sample_states(bbx_grid *g, int64_t n, uint64_t seed, float *out_dev)
+{
+    g_err.clear();
+    if (!g || !out_dev) return fail(BBX_EINVAL, "NULL argument");
+    if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "state sampling needs an FP32 grid");
+    if (g->model < 0) return fail(BBX_ESTATE, "set a model first");
+    if (n < 0) return fail(BBX_EINVAL, "n must be >= 0");
+    if (g->nact == 0 && n > 0) return fail(BBX_EINVAL, "the grid has no tissue");
+    StepArgs<float> a = make_args<float>(g);
+    a.Vin = (const float *)g->d_V[g->cur];
+    HIP_TRY(launch_sample(a, g->nvar, n, seed, out_dev, g->stream), "sample");
+    return BBX_OK;
+}
+
+int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev)
+{
+    g_err.clear();
+    if (!g || !in_dev || !out_dev) return fail(BBX_EINVAL, "NULL argument");
+    if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the ionic map runs on FP32 grids");
+    if (g->model < 0) return fail(BBX_ESTATE, "set a model first");
+    if (n < 0) return fail(BBX_EINVAL, "n must be >= 0");
+    StepArgs<float> a = make_args<float>(g);
+    HIP_TRY(launch_ionic_map(g->model, a, g->nvar, in_dev, n, out_dev, g->stream), "ionic map");
+    return BBX_OK;
+}
+
+int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi, float dv_max)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (!m) {
+            g->sur = 0;
+            return BBX_OK;
+        }
+        if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the surrogate runs on FP32 grids");
+        if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN)
+            return fail(BBX_ENOTSUP, "no surrogate step for model %d", g->model);
+        if (m->nin != g->nvar || m->nout != g->nvar)
+            return fail(BBX_EINVAL, "network is %d -> %d, the model has %d variables", m->nin, m->nout, g->nvar);
+        if (!lo || !hi) return fail(BBX_EINVAL, "lo / hi is NULL");
+        if (!(dv_max >= 0)) return fail(BBX_EINVAL, "dv_max must be >= 0");
+        hipError_t e = hipSuccess;
+        if (!g->snet.w1) {
+            g->snet.nin = m->nin;
+            g->snet.nout = m->nout;
+            if ((e = dalloc(g, &g->snet.w1, kH * kS1 * sizeof(__bf16))) != hipSuccess ||
+                (e = dalloc(g, &g->snet.w2, kH * kS2 * sizeof(__bf16))) != hipSuccess ||
+                (e = dalloc(g, &g->snet.w3, kP * kS2 * sizeof(__bf16))) != hipSuccess ||
+                (e = dalloc(g, &g->snet.bias, (2 * kH + kP) * sizeof(float))) != hipSuccess ||
+                (e = dalloc(g, &g->snet.norm, 4 * kP * sizeof(float))) != hipSuccess ||
+                (e = dalloc(g, &g->d_slo, kP * sizeof(float))) != hipSuccess ||
+                (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
+                (e = dalloc(g, &g->d_fb_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
+                (e = dalloc(g, &g->d_fb_cnt, 2 * sizeof(int32_t))) != hipSuccess ||
+                (e = dalloc(g, &g->d_fb_total, sizeof(unsigned long long))) != hipSuccess)
+                return hip_fail(e, "hipMalloc");
+        }
+        hipStream_t st = g->stream;
+        // the network's device copies are ordered on its own stream: finish them first
+        HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+        HIP_TRY(hipMemcpyAsync(g->snet.w1, m->dev.w1, kH * kS1 * sizeof(__bf16), hipMemcpyDeviceToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->snet.w2, m->dev.w2, kH * kS2 * sizeof(__bf16), hipMemcpyDeviceToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->snet.w3, m->dev.w3, kP * kS2 * sizeof(__bf16), hipMemcpyDeviceToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->snet.bias, m->dev.bias, (2 * kH + kP) * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->snet.norm, m->dev.norm, 4 * kP * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->d_slo, lo, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
+        HIP_TRY(hipMemcpyAsync(g->d_shi, hi, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
+        HIP_TRY(hipMemsetAsync(g->d_fb_cnt, 0, 2 * sizeof(int32_t), st), "hipMemsetAsync");
+        HIP_TRY(hipMemsetAsync(g->d_fb_total, 0, sizeof(unsigned long long), st), "hipMemsetAsync");
+        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+        g->dv_max = dv_max;
+        g->sur = 1;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
 }
 
 }  // extern "C"

@@ -1,6 +1,7 @@
 // Device-side cell kinetics for the fused step kernel.
 //
-// Each model provides  T advance(const T* prm, T V, T* g, T dt):  given the
+// Each model provides NV (state variables including V), GATE0 (variables
+// GATE0..NV-1 are gating variables) and  T advance(const T* prm, T V, T* g, T dt):  given the
 // voltage the kinetics see (V_n, or V* in the split scheme) and the other state
 // variables g[0..NV-2], it returns the kinetic part of dV/dt (= -I_ion, with a
 // positive stimulus depolarising) and advances g in place by one step:
@@ -75,7 +76,7 @@ __device__ __forceinline__ T lgs(T x)
 // ---------------------------------------------------------------- pure diffusion
 template <typename T>
 struct None {
-    static constexpr int NV = 1;
+    static constexpr int NV = 1, GATE0 = 1;
     __device__ static T advance(const T *, T, T *, T) { return T(0); }
 };
 
@@ -83,7 +84,7 @@ struct None {
 // u' = u (1 - u)(u - (v + b)/a) / eps,  v' = u - v.   prm = {a, b, eps}
 template <typename T>
 struct Barkley {
-    static constexpr int NV = 2;
+    static constexpr int NV = 2, GATE0 = 2;
     __device__ static T advance(const T *p, T u, T *g, T dt)
     {
         T v = g[0];
@@ -97,7 +98,7 @@ struct Barkley {
 // V' = V (V - alpha)(1 - V)   (eq (ZFKbidomV)).   prm = {alpha}
 template <typename T>
 struct Zfk {
-    static constexpr int NV = 1;
+    static constexpr int NV = 1, GATE0 = 1;
     __device__ static T advance(const T *p, T V, T *, T)
     {
         return V * (V - p[0]) * (T(1) - V);
@@ -108,7 +109,7 @@ struct Zfk {
 // u' = (u - u^3/3 - v)/eps,  v' = eps (u + beta - gamma v)   (eq (FHN)).
 template <typename T>
 struct Fhn {
-    static constexpr int NV = 2;
+    static constexpr int NV = 2, GATE0 = 2;
     __device__ static T advance(const T *p, T u, T *g, T dt)
     {
         T v = g[0];
@@ -124,7 +125,7 @@ struct Fhn {
 // xr, xs, d, f, fCa, u, v, w.  Currents per unit capacitance (pA/pF).
 template <typename T>
 struct Crn {
-    static constexpr int NV = 21;
+    static constexpr int NV = 21, GATE0 = 6;  // variables GATE0.. are gates in [0, 1]
     __device__ static T advance(const T *, T V, T *g, T dt)
     {
         // physical constants and cell geometry

@@ -19,96 +19,9 @@
 // (coalesced, x-fastest order).  Workgroups are remapped so that each XCD works
 // on one contiguous slab of the tissue list, keeping neighbour planes in that
 // XCD's L2.
-#include "bbx_internal.h"
-#include "kinetics.h"
+#include "step_device.h"
 
 namespace bbx {
-
-// V_{p+off} - V_p if neighbour bit b is set (tissue), else 0.  FULL: the whole
-// workgroup is known to be interior (every neighbour is tissue).
-template <typename T, bool FULL>
-__device__ __forceinline__ T nbd(const T *__restrict__ V, int idx, int off, uint32_t bits, int b,
-                                 T Vp)
-{
-    if (FULL) return V[idx + off] - Vp;
-    return ((bits >> b) & 1u) ? V[idx + off] - Vp : T(0);
-}
-
-// (L V)_p in the difference form; see the header comment.
-template <typename T, bool ANISO, bool FULL>
-__device__ __forceinline__ T laplacian(const StepArgs<T> &a, const T *__restrict__ V, int t,
-                                       int idx, uint32_t bits, T Vp)
-{
-    const int sy = a.nx, sz = a.nx * a.ny;
-    const T ex_ = nbd<T, FULL>(V, idx, 1, bits, 0, Vp), wx = nbd<T, FULL>(V, idx, -1, bits, 1, Vp);
-    const T ny_ = nbd<T, FULL>(V, idx, sy, bits, 2, Vp), sy_ = nbd<T, FULL>(V, idx, -sy, bits, 3, Vp);
-    const T up = nbd<T, FULL>(V, idx, sz, bits, 4, Vp), dn = nbd<T, FULL>(V, idx, -sz, bits, 5, Vp);
-    if (!ANISO) return a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dn));
-    const T *gp = a.geo + 6 * (int64_t)t;
-    const T fx = gp[0], fy = gp[1], fz = gp[2];
-    const T cx = gp[3], cy = gp[4], cz = gp[5];
-    const T dd = a.Dpar - a.Dperp;
-    const T Dxx = a.Dperp + dd * fx * fx, Dyy = a.Dperp + dd * fy * fy;
-    const T Dzz = a.Dperp + dd * fz * fz;
-    const T Dxy = dd * fx * fy, Dxz = dd * fx * fz, Dyz = dd * fy * fz;
-    const T exy = nbd<T, FULL>(V, idx, 1 + sy, bits, 6, Vp) + nbd<T, FULL>(V, idx, -1 - sy, bits, 7, Vp)
-                  - nbd<T, FULL>(V, idx, 1 - sy, bits, 8, Vp) - nbd<T, FULL>(V, idx, -1 + sy, bits, 9, Vp);
-    const T exz = nbd<T, FULL>(V, idx, 1 + sz, bits, 10, Vp) + nbd<T, FULL>(V, idx, -1 - sz, bits, 11, Vp)
-                  - nbd<T, FULL>(V, idx, 1 - sz, bits, 12, Vp) - nbd<T, FULL>(V, idx, -1 + sz, bits, 13, Vp);
-    const T eyz = nbd<T, FULL>(V, idx, sy + sz, bits, 14, Vp) + nbd<T, FULL>(V, idx, -sy - sz, bits, 15, Vp)
-                  - nbd<T, FULL>(V, idx, sy - sz, bits, 16, Vp) - nbd<T, FULL>(V, idx, -sy + sz, bits, 17, Vp);
-    return a.ih2 * (Dxx * (ex_ + wx) + Dyy * (ny_ + sy_) + Dzz * (up + dn)
-                    + T(0.5) * (Dxy * exy + Dxz * exz + Dyz * eyz))
-           + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
-}
-
-// Everything after the Laplacian for one voxel: stimulus, kinetics, stores and
-// the activation / peak / APD90 recorder (per-voxel threshold-crossing test).
-template <typename T, class M>
-__device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int idx, T Vp, T LV)
-{
-    T Is = T(0);
-    if (a.stim_on) {
-        const uint32_t sb = a.stimbits[t] & a.stim_on;
-        for (int s = 0; s < a.nstim; s++)
-            if ((sb >> s) & 1u) Is += a.stim_amp[s];
-    }
-
-    T g[M::NV > 1 ? M::NV - 1 : 1];
-#pragma unroll
-    for (int i = 0; i < M::NV - 1; i++) g[i] = a.st[i * a.pitch + t];
-    const T Vin = a.split ? Vp + a.dt * LV : Vp;
-    const T r = M::advance(a.prm, Vin, g, a.dt);
-    const T Vn = a.split ? Vin + a.dt * (r + Is) : Vp + a.dt * (r + Is + LV);
-#pragma unroll
-    for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
-    a.Vout[idx] = Vn;
-
-    if (a.rec) {
-        uint8_t s0 = a.status[t];
-        if (s0 != 3) {
-            uint8_t s = s0;
-            if (s == 0 && Vp < a.theta && Vn >= a.theta) {
-                a.at[t] = a.tn + a.dt * (a.theta - Vp) / (Vn - Vp);
-                s = 1;
-            }
-            if (s == 1 && Vn < Vp) {
-                a.vmax[t] = Vp;
-                const T rest = a.vrep[t];
-                a.vrep[t] = rest + T(0.1) * (Vp - rest);
-                s = 2;
-            }
-            if (s == 2) {
-                const T vr = a.vrep[t];
-                if (Vp >= vr && Vn < vr) {
-                    a.apd[t] = a.tn + a.dt * (Vp - vr) / (Vp - Vn) - a.at[t];
-                    s = 3;
-                }
-            }
-            if (s != s0) a.status[t] = s;
-        }
-    }
-}
 
 // Tissue-list path: one thread per tissue voxel, 256 consecutive list entries per
 // workgroup.  Logical workgroup ids are dealt so that XCD k gets the k-th

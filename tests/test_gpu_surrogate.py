@@ -1,0 +1,205 @@
+"""GPU tests of the surrogate network path against the FP64 oracle network and
+the plain kinetics: forward pass, gradients and Adam of the BF16-MFMA training
+kernels, the kinetic one-step map that provides training targets, and the
+per-voxel fallback of the surrogate step."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from oracle import oracle as O
+from paper_1605_06015_amd import workloads as WL
+from parity_util import Problem, gpu_state, make_gpu, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+NIN = NOUT = 21
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    torch.cuda.set_device(0)
+    return B, torch
+
+
+def normwise(a, b):
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-30)
+
+
+def test_forward_matches_oracle(env):
+    B, torch = env
+    m = B.Mlp(NIN, NOUT, seed=3)
+    theta = m.get_params().astype(np.float64)
+    X = np.random.default_rng(0).standard_normal((1000, NIN)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Yd = torch.empty((1000, NOUT), dtype=torch.float32, device="cuda")
+    m.forward(Xd, Yd)
+    torch.cuda.synchronize()
+    ref, _ = OM.forward(theta, X.astype(np.float64), NIN, 128, NOUT)
+    err = normwise(Yd.cpu().numpy(), ref)
+    print("forward BF16 vs FP64 normwise rel err", err)
+    assert err <= 2e-2
+
+
+@pytest.mark.parametrize("n", [16, 1000, 4096])
+def test_gradient_matches_oracle(env, n):
+    """BF16 operands, FP32 accumulation vs the FP64 oracle's exact gradient:
+    normwise relative error <= 3e-2 per parameter block."""
+    B, torch = env
+    m = B.Mlp(NIN, NOUT, seed=5)
+    rng = np.random.default_rng(n)
+    theta = (rng.standard_normal(m.nparams) * 0.1).astype(np.float32)
+    m.set_params(theta)
+    X = rng.standard_normal((n, NIN)).astype(np.float32)
+    T = rng.standard_normal((n, NOUT)).astype(np.float32)
+    loss, g = m.grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
+    L, gref = OM.loss_and_grad(theta.astype(np.float64), X.astype(np.float64), T.astype(np.float64),
+                               NIN, 128, NOUT)
+    assert abs(loss - L) <= 2e-2 * L
+    o = 0
+    for name, shape in OM.sizes(NIN, 128, NOUT):
+        k = int(np.prod(shape))
+        e = normwise(g[o:o + k].astype(np.float64), gref[o:o + k])
+        print(n, name, "grad normwise rel err", e)
+        assert e <= 3e-2, (name, e)
+        o += k
+
+
+def test_adam_step_matches_oracle(env):
+    B, torch = env
+    m = B.Mlp(NIN, NOUT, seed=7)
+    rng = np.random.default_rng(1)
+    theta = (rng.standard_normal(m.nparams) * 0.1).astype(np.float32)
+    m.set_params(theta)
+    X = torch.from_numpy(rng.standard_normal((512, NIN)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((512, NOUT)).astype(np.float32)).cuda()
+    th = theta.astype(np.float64)
+    mm = np.zeros_like(th)
+    vv = np.zeros_like(th)
+    for t in range(1, 4):
+        _, g = m.grad(X, T)
+        m.adam(1e-3)
+        th, mm, vv = OM.adam_step(th, mm, vv, g.astype(np.float64), t, 1e-3)
+        got = m.get_params().astype(np.float64)
+        assert np.abs(got - th).max() <= 1e-6 * max(1.0, np.abs(th).max())
+        th = got  # follow the device's FP32 rounding
+
+
+def crn_states(n, seed):
+    """CRN states spread over an action potential (from a single oracle cell)."""
+    s = O.Sim(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, O.MODEL_CRN, [], 0.01)
+    for i, v in enumerate(WL.CRN_INITIAL):
+        s.set_state(i, v)
+    s.stimuli.append(O.Stimulus(np.ones((1, 1, 1), np.uint8), 20.0, 0, 200))
+    traj = []
+    for _ in range(400):
+        s.step(100)
+        traj.append(s.state[:, 0, 0, 0].copy())
+    traj = np.array(traj)
+    rng = np.random.default_rng(seed)
+    return traj[rng.integers(0, len(traj), n)]
+
+
+def test_ionic_map_matches_oracle_single_cell_step(env):
+    B, torch = env
+    S = crn_states(256, 0)
+    g = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32)
+    g.model(B.BBX_MODEL_CRN, [], 0.01)
+    Sd = torch.from_numpy(S.astype(np.float32)).cuda()
+    Od = torch.empty_like(Sd)
+    g.ionic_map(Sd, Od)
+    torch.cuda.synchronize()
+    out = Od.cpu().numpy().astype(np.float64)
+    for k in range(0, 256, 17):
+        c = O.Sim(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, O.MODEL_CRN, [], 0.01)
+        for i in range(21):
+            c.set_state(i, float(np.float32(S[k, i])))
+        c.step(1)
+        ref = c.state[:, 0, 0, 0]
+        assert abs(out[k, 0] - ref[0]) <= 1e-3
+        np.testing.assert_allclose(out[k, 1:], ref[1:], rtol=1e-5, atol=1e-6)
+
+
+def cup_problem(nx=24, ny=24, nz=12, seed=5):
+    gg = WL.crn_cup(nx, ny, nz, seed=seed)
+    return Problem(gg["mask"], 0.25, gg["fibre"], 0.3, 0.03, O.MODEL_CRN, [], 0.01,
+                   state=gg["state"], stims=[(gg["stim"], 40.0, 0.0, 2.0, 0.0, 1)], theta=-40.0)
+
+
+def test_surrogate_all_fallback_equals_plain(env):
+    """An empty accepted box sends every voxel to the plain kinetics: the result must
+    equal the plain FP32 step and every voxel-update is counted as a fallback."""
+    B, torch = env
+    p = cup_problem()
+    plain = make_gpu(p, 0)
+    plain.step(300)
+    sur = make_gpu(p, 0)
+    m = B.Mlp(NIN, NOUT, seed=1)
+    sur.surrogate(m, np.full(NIN, 1.0), np.full(NIN, -1.0), 1e9)
+    sur.step(300)
+    a, b = gpu_state(plain, 21), gpu_state(sur, 21)
+    assert np.array_equal(a, b, equal_nan=True)
+    assert sur.read(B.BBX_READ_FALLBACK_COUNT)[0] == 300 * sur.nact
+    at_a, at_b = plain.read(B.BBX_READ_ACT_TIME), sur.read(B.BBX_READ_ACT_TIME)
+    assert np.array_equal(at_a, at_b, equal_nan=True)
+
+
+def test_surrogate_forced_partial_fallback(env):
+    """Voxels whose V leaves the accepted box fall back; the count matches the number
+    of such voxels and they get exactly the plain update."""
+    B, torch = env
+    p = cup_problem()
+    m = B.Mlp(NIN, NOUT, seed=2)
+    plain = make_gpu(p, 0)
+    plain.step(150)                    # stimulus under way: apex voxels depolarised
+    state = gpu_state(plain, 21)
+    mask = p.mask == 1
+    vcut = -75.0
+    n_out = int((state[0][mask] > vcut).sum())
+    assert 0 < n_out < mask.sum()
+    q = Problem(p.mask, p.h, p.fibre, p.Dpar, p.Dperp, p.model, [], p.dt,
+                state=np.nan_to_num(state), stims=p.stims)
+    ref = make_gpu(q, 0)
+    ref.clock(150)
+    ref.step(1)
+    sur = make_gpu(q, 0)
+    sur.clock(150)
+    lo = np.full(NIN, -1e30)
+    hi = np.full(NIN, 1e30)
+    hi[0] = vcut
+    sur.surrogate(m, lo, hi, 1e30)
+    sur.step(1)
+    assert sur.read(B.BBX_READ_FALLBACK_COUNT)[0] >= n_out
+    fell = (state[0] > vcut) & mask
+    a, b = gpu_state(ref, 21), gpu_state(sur, 21)
+    for v in range(21):
+        assert np.array_equal(a[v][fell], b[v][fell]), v
+
+
+def test_surrogate_detach_restores_plain(env):
+    B, torch = env
+    p = cup_problem(20, 20, 10)
+    g = make_gpu(p, 0)
+    m = B.Mlp(NIN, NOUT, seed=1)
+    g.surrogate(m, np.full(NIN, -1e30), np.full(NIN, 1e30), 1e30)
+    g.surrogate(None)
+    ref = make_gpu(p, 0)
+    g.step(50)
+    ref.step(50)
+    assert np.array_equal(gpu_state(g, 21), gpu_state(ref, 21), equal_nan=True)
+
+
+def test_surrogate_rejects_bad_setups(env):
+    B, torch = env
+    g = B.Grid(np.ones((2, 2, 2), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP64)
+    g.model(B.BBX_MODEL_CRN, [], 0.01)
+    m = B.Mlp(NIN, NOUT, seed=1)
+    with pytest.raises(B.BBXError) as ei:
+        g.surrogate(m, np.zeros(NIN), np.ones(NIN), 1.0)
+    assert ei.value.code == B.BBX_ENOTSUP
+    g2 = B.Grid(np.ones((2, 2, 2), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32)
+    g2.model(B.BBX_MODEL_BARKLEY, [0.75, 0.02, 0.02], 0.001)
+    with pytest.raises(B.BBXError) as ei:
+        g2.surrogate(m, np.zeros(NIN), np.ones(NIN), 1.0)
+    assert ei.value.code == B.BBX_EINVAL
