@@ -168,13 +168,70 @@ def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / sec / 1e9
 
 
+def surrogate_line(stream, t_ms=500.0, iters=20000, v_hi=-75.0):
+    """Surrogate-with-fallback on the same CRN workload: train on paced runs of the cup
+    (outside the timed region), anchor the resting state, then time a full run with the
+    plain FP32 kinetics and with the surrogate accepting tissue below v_hi mV, and
+    compare activation-time and APD90 maps."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import surrogate as SU
+    t0 = time.perf_counter()
+    S, S1 = SU.generate_pairs(runs=2, t_ms=800.0, per_sample=2048, seed=2, stream=stream)
+    t1 = time.perf_counter()
+    anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32, stream)
+    anchor.model(B.BBX_MODEL_CRN, [], 0.01)
+    tr = SU.train(S, S1, iters=iters, batch=4096, lr=1e-3, seed=0, stream=stream, anchor_grid=anchor)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del S, S1
+    c_dt = 0.01
+    nsteps = int(round(t_ms / c_dt))
+    res = {}
+    for name in ("plain", "surrogate"):
+        grid, g = crn_workload(B.BBX_FP32, stream)
+        grid.nan_check(0)
+        if name == "surrogate":
+            lo, hi, dv = SU.accepted_box(tr.stats)
+            hi[0] = v_hi                      # the network handles tissue below v_hi only
+            grid.surrogate(tr.mlp, lo, hi, dv)
+        sec = time_steps(grid, stream, nsteps, 0)
+        m = g["mask"] == 1
+        res[name] = dict(sec=sec, at=grid.read(B.BBX_READ_ACT_TIME)[m], apd=grid.read(B.BBX_READ_APD90)[m],
+                         fb=int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]), nact=grid.nact)
+        grid.close()
+    p, q = res["plain"], res["surrogate"]
+    both = np.isfinite(p["at"]) & np.isfinite(q["at"])
+    dat = np.abs(p["at"][both] - q["at"][both])
+    bapd = np.isfinite(p["apd"]) & np.isfinite(q["apd"])
+    dapd = np.abs(p["apd"][bapd] - q["apd"][bapd])
+    value = q["nact"] * nsteps / q["sec"]
+    return {"workload": f"CRN cup 128x128x64, {t_ms:.0f} ms, FP32, surrogate 21-128-128-21 SiLU "
+                        "(BF16 MFMA, FP32 accumulate) with per-voxel fallback",
+            "value": value, "unit": "voxel-updates/s", "ms_per_step": q["sec"] / nsteps * 1e3,
+            "accepted_v_below_mV": v_hi,
+            "speedup_vs_plain": p["sec"] / q["sec"],
+            "fallback_fraction": q["fb"] / (q["nact"] * nsteps),
+            "at_err_vs_plain_ms": {"max": float(dat.max()) if dat.size else None,
+                                   "mean": float(dat.mean()) if dat.size else None,
+                                   "dt": c_dt, "activated_plain": int(np.isfinite(p["at"]).sum()),
+                                   "activated_surrogate": int(np.isfinite(q["at"]).sum())},
+            "apd90_err_vs_plain_ms": {"max": float(dapd.max()) if dapd.size else None,
+                                      "mean": float(dapd.mean()) if dapd.size else None,
+                                      "n": int(bapd.sum())},
+            "training": {"pairs": tr.npairs, "iters": iters, "batch": 4096,
+                         "final_loss": float(np.mean(tr.loss[-100:])), "gen_s": round(t1 - t0, 2),
+                         "train_s": round(t2 - t1, 2)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the stencil roofline run")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the stencil roofline and surrogate runs")
     ap.add_argument("--profile", choices=["crn", "stencil"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
@@ -237,6 +294,7 @@ def main():
     grid.close()
     if not args.no_extras:
         out["stencil_roofline"] = stencil_roofline(stream)
+        out["surrogate"] = surrogate_line(stream)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

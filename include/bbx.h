@@ -200,13 +200,15 @@ int bbx_mlp_create(int nin, int nout, uint64_t seed, void *hip_stream, bbx_mlp *
 int bbx_mlp_params(bbx_mlp *m, int set, float *host, size_t count);
 
 /* Copy the normalisation [4][32] = in_mean, in_scale, out_mean, out_sigma to
- * (set = 0) or from (set = 1) the host. */
+ * (set = 0) or from (set = 1) the host; out_sigma must be >= 0. */
 int bbx_mlp_norm(bbx_mlp *m, int set, float *host);
 
 /* Fit the normalisation to training pairs on the device: S [n][nin] states
  * and S1 [n][nout] the states one step later (row-major per sample; nin must
- * equal nout).  Sets in_mean/in_scale from the states and out_mean/out_sigma
- * from the increments S1 - S (scale 1 where a feature is constant).  If stats
+ * equal nout).  Sets in_mean/in_scale from the states (in_scale 1 for a
+ * constant state) and out_mean/out_sigma from the increments S1 - S
+ * (out_sigma 0 for a constant increment, which is then predicted exactly as
+ * out_mean; e.g. K_i in FP32, whose change per step is below its rounding).  If stats
  * is not NULL it receives double[7][32]: mean, std, min, max of the states,
  * then mean, std, max |.| of the increments. */
 int bbx_mlp_fit_norm(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n,
@@ -233,6 +235,13 @@ int bbx_mlp_adam(bbx_mlp *m, float lr, float beta1, float beta2, float eps);
 int bbx_mlp_train(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n, int64_t batch,
                   int64_t iters, float lr, uint64_t seed, float *loss_hist);
 
+/* Shift the output biases so that the network maps the state s0 (nin floats,
+ * device) exactly to the increment s1 - s0 (s1 on the device): e.g. s0 = a
+ * resting state and s1 = its plain one-step image, which makes the resting
+ * state an exact fixed point of the surrogate map as it is of the plain one.
+ * Requires nin == nout. */
+int bbx_mlp_anchor(bbx_mlp *m, const float *s0_dev, const float *s1_dev);
+
 /* Free the network. */
 void bbx_mlp_destroy(bbx_mlp *m);
 
@@ -248,8 +257,10 @@ int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev);
  * nin = nout = the model's nvar.  Each step then evaluates the network for
  * every tissue voxel and falls back to the plain kinetics for a voxel whose
  * kinetic input leaves [lo, hi] (nvar floats each), whose predicted gates
- * leave [0, 1], whose predicted |dV| exceeds dv_max, or whose prediction is
- * not finite.  The network's weights are copied; it may be destroyed after. */
+ * leave [-1e-3, 1 + 1e-3] (accepted gates are clamped to [0, 1]), whose
+ * predicted |dV| exceeds dv_max, or whose prediction is not finite.  Supported
+ * models: Barkley, FHN, CRN.  The network's weights are copied; it may be
+ * destroyed after. */
 int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi,
                       float dv_max);
 

@@ -51,6 +51,7 @@ SIGNATURES = {
     "bbx_mlp_grad": (_I, [_P, _P, _P, _I64, _P, _P]),
     "bbx_mlp_adam": (_I, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "bbx_mlp_train": (_I, [_P, _P, _P, _I64, _I64, _I64, C.c_float, C.c_uint64, _P]),
+    "bbx_mlp_anchor": (_I, [_P, _P, _P]),
     "bbx_mlp_destroy": (None, [_P]),
     "bbx_sample_states": (_I, [_P, _I64, C.c_uint64, _P]),
     "bbx_ionic_map": (_I, [_P, _P, _I64, _P]),
@@ -235,7 +236,8 @@ class Grid:
     def ionic_map(self, inp, out):
         bbx_ionic_map(self.handle, inp, inp.shape[0], out)
 
-    def surrogate(self, mlp, lo, hi, dv_max):
+    def surrogate(self, mlp, lo=None, hi=None, dv_max=0.0):
+        """Attach a trained Mlp with its accepted input box (None detaches)."""
         bbx_surrogate_set(self.handle, None if mlp is None else mlp.handle, lo, hi, dv_max)
 
     def get(self, var=0):
@@ -314,6 +316,10 @@ def bbx_mlp_train(m, S, S1, n, batch, iters, lr, seed, loss_hist=None):
     return loss_hist
 
 
+def bbx_mlp_anchor(m, s0, s1):
+    _check(_lib.bbx_mlp_anchor(m, _dptr(s0), _dptr(s1)))
+
+
 def bbx_mlp_destroy(m):
     _lib.bbx_mlp_destroy(m)
 
@@ -384,6 +390,9 @@ class Mlp:
 
     def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         bbx_mlp_adam(self.handle, lr, beta1, beta2, eps)
+
+    def anchor(self, s0, s1):
+        bbx_mlp_anchor(self.handle, s0, s1)
 
     def train(self, S, S1, batch, iters, lr, seed=0):
         hist = np.empty(iters, np.float32)

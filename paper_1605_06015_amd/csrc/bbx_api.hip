@@ -1001,7 +1001,7 @@ int bbx_mlp_norm(bbx_mlp *m, int set, float *host)
         for (int i = 0; i < 4 * kP; i++)
             if (!isfinite(host[i])) return fail(BBX_EINVAL, "normalisation entry %d is not finite", i);
         for (int i = 0; i < kP; i++)
-            if (host[3 * kP + i] == 0.f) return fail(BBX_EINVAL, "out_sigma %d is zero", i);
+            if (host[3 * kP + i] < 0.f) return fail(BBX_EINVAL, "out_sigma %d is negative", i);
         HIP_TRY(hipMemcpyAsync(m->dev.norm, host, 4 * kP * sizeof(float), hipMemcpyHostToDevice, m->stream), "hipMemcpyAsync");
     } else {
         HIP_TRY(hipMemcpyAsync(host, m->dev.norm, 4 * kP * sizeof(float), hipMemcpyDeviceToHost, m->stream), "hipMemcpyAsync");
@@ -1028,7 +1028,7 @@ int bbx_mlp_fit_norm(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_
             norm[i] = (float)mi;
             norm[kP + i] = (float)(si > 0 ? 1.0 / si : 1.0);
             norm[2 * kP + i] = (float)mo;
-            norm[3 * kP + i] = (float)(so > 0 ? so : 1.0);
+            norm[3 * kP + i] = (float)so;   // 0: a constant increment, predicted exactly
         }
         HIP_TRY(hipMemcpyAsync(m->dev.norm, norm, sizeof norm, hipMemcpyHostToDevice, m->stream), "hipMemcpyAsync");
         HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
@@ -1124,6 +1124,16 @@ int bbx_mlp_train(bbx_mlp *m, const float *S_dev, const float *S1_dev, int64_t n
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
     }
+}
+
+int bbx_mlp_anchor(bbx_mlp *m, const float *s0_dev, const float *s1_dev)
+{
+    g_err.clear();
+    if (!m || !s0_dev || !s1_dev) return fail(BBX_EINVAL, "NULL argument");
+    if (m->nin != m->nout) return fail(BBX_EINVAL, "anchoring needs nin == nout");
+    HIP_TRY(mlp_anchor(m->dev, s0_dev, s1_dev, m->d_p, m->stream), "anchor");
+    HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
+    return BBX_OK;
 }
 
 void bbx_mlp_destroy(bbx_mlp *m)

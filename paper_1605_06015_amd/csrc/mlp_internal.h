@@ -16,8 +16,9 @@ constexpr int kS1 = kP + 8;               // LDS row stride (BF16) of 32-wide we
 constexpr int kS2 = kH + 8;               // LDS row stride (BF16) of 128-wide weight rows
 constexpr int kPart = 2 * kH + kP + 1;    // per-tile partial sums: db1, db2, db3, loss
 constexpr int64_t kMaxBatch = 65536;      // training batch limit
-constexpr int kSurBlock = 512;            // threads per surrogate-step workgroup
+constexpr int kSurBlock = 768;            // threads per surrogate-step workgroup (12 waves)
 constexpr int kOS = kP + 1;               // row stride (floats) of the output staging
+constexpr float kGateTol = 1e-3f;         // accepted excursion of a predicted gate outside [0, 1]
 
 // Device copies of one network: BF16 weights in the MFMA layouts (see
 // mlp_kernels.hip), FP32 biases [b1 H | b2 H | b3 kP] and normalisation
@@ -57,6 +58,7 @@ hipError_t mlp_grad(const MlpDev &d, const MlpScratch &w, int mode, const float 
                     hipStream_t s);
 hipError_t mlp_adam(float *p, float *m, float *v, const float *grad, int n, float lr, float b1,
                     float b2, float eps, int64_t t, hipStream_t s);
+hipError_t mlp_anchor(const MlpDev &d, const float *s0, const float *s1, float *p, hipStream_t s);
 hipError_t mlp_stats(const float *S, const float *S1, int64_t n, int nin, double *out,
                      hipStream_t s);
 

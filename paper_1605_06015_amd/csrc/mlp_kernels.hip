@@ -132,12 +132,10 @@ __device__ __forceinline__ void fwd_tile(const MlpLds &W, bf8 x, f4v out[2], f4v
                                          f4v z2[8], bf8 h1[4], bf8 h2[4])
 {
     const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
-    const f4v zero = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int mt = 0; mt < 8; mt++) {
-        z1[mt] = mfma(ld8(W.w1 + (16 * mt + j) * kS1 + 8 * g), x, zero);
-#pragma unroll
-        for (int i = 0; i < 4; i++) z1[mt][i] += W.bias[16 * mt + 4 * g + i];
+        const f4v b = *(const f4v *)(W.bias + 16 * mt + 4 * g);   // bias as the initial sum
+        z1[mt] = mfma(ld8(W.w1 + (16 * mt + j) * kS1 + 8 * g), x, b);
     }
 #pragma unroll
     for (int ks = 0; ks < 4; ks++)
@@ -148,12 +146,10 @@ __device__ __forceinline__ void fwd_tile(const MlpLds &W, bf8 x, f4v out[2], f4v
         }
 #pragma unroll
     for (int mt = 0; mt < 8; mt++) {
-        f4v acc = zero;
+        f4v acc = *(const f4v *)(W.bias + kH + 16 * mt + 4 * g);
 #pragma unroll
         for (int ks = 0; ks < 4; ks++)
             acc = mfma(ld8(W.w2 + (16 * mt + j) * kS2 + 32 * ks + 8 * g), h1[ks], acc);
-#pragma unroll
-        for (int i = 0; i < 4; i++) acc[i] += W.bias[kH + 16 * mt + 4 * g + i];
         z2[mt] = acc;
     }
 #pragma unroll
@@ -165,12 +161,10 @@ __device__ __forceinline__ void fwd_tile(const MlpLds &W, bf8 x, f4v out[2], f4v
         }
 #pragma unroll
     for (int mt = 0; mt < 2; mt++) {
-        f4v acc = zero;
+        f4v acc = *(const f4v *)(W.bias + 2 * kH + 16 * mt + 4 * g);
 #pragma unroll
         for (int ks = 0; ks < 4; ks++)
             acc = mfma(ld8(W.w3 + (16 * mt + j) * kS2 + 32 * ks + 8 * g), h2[ks], acc);
-#pragma unroll
-        for (int i = 0; i < 4; i++) acc[i] += W.bias[2 * kH + 16 * mt + 4 * g + i];
         out[mt] = acc;
     }
 }
@@ -197,7 +191,7 @@ __device__ __forceinline__ void stage_weights(const MlpDev &d, __bf16 *w1, __bf1
 __global__ __launch_bounds__(256) void k_forward(MlpDev d, const float *X, int64_t n, float *Y)
 {
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
-    __shared__ float bias[2 * kH + kP];
+    __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
     stage_weights(d, w1, w2, w3, nullptr, nullptr, bias);
     __syncthreads();
     const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
@@ -241,8 +235,9 @@ __global__ void k_prep(MlpDev d, int mode, const float *A, const float *Bm, int6
         } else {
             const int64_t r = (int64_t)(mix64(seed ^ mix64(iter * 0x10000ull + (uint64_t)s)) % (uint64_t)n);
             if (f < d.nin) xv = (A[r * d.nin + f] - d.norm[f]) * d.norm[kP + f];
-            if (f < d.nout)
-                tv = ((Bm[r * d.nout + f] - A[r * d.nin + f]) - d.norm[2 * kP + f]) / d.norm[3 * kP + f];
+            const float sg = d.norm[3 * kP + f];
+            if (f < d.nout && sg > 0.0f)
+                tv = ((Bm[r * d.nout + f] - A[r * d.nin + f]) - d.norm[2 * kP + f]) / sg;
         }
     }
     Xb[s * kP + f] = bf(xv);
@@ -260,7 +255,7 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(MlpDev d, const __bf16 *Xb, con
 {
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
     __shared__ __attribute__((aligned(16))) __bf16 w2t[kH * kS2], w3t[kH * kS1];
-    __shared__ float bias[2 * kH + kP];
+    __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
     stage_weights(d, w1, w2, w3, w2t, w3t, bias);
     __syncthreads();
     const MlpLds W{w1, w2, w3, w2t, w3t, bias};
@@ -402,20 +397,29 @@ __global__ __launch_bounds__(256) void k_wgrad(MlpDev d, int64_t Bp, const __bf1
     }
 }
 
-// Bias gradients and the loss: sum the per-tile partials in tile order.
-__global__ void k_reduce_part(MlpDev d, const float *part, int64_t ntile, float *grad,
-                              double *loss, double inv_count)
+// Bias gradients and the loss: one workgroup per column sums the per-tile
+// partials (strided per thread, then a fixed LDS tree: deterministic).
+__global__ __launch_bounds__(256) void k_reduce_part(MlpDev d, const float *part, int64_t ntile,
+                                                     float *grad, double *loss, double inv_count)
 {
-    const int c = blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= kPart) return;
+    __shared__ double sh[256];
+    const int c = blockIdx.x;
     double s = 0.0;
-    for (int64_t t = 0; t < ntile; t++) s += (double)part[t * kPart + c];
+    for (int64_t t = threadIdx.x; t < ntile; t += 256) s += (double)part[t * kPart + c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    s = sh[0];
     const POff o = poff(d.nin, d.nout);
     if (c < kH) grad[o.b1 + c] = (float)s;
     else if (c < 2 * kH) grad[o.b2 + c - kH] = (float)s;
     else if (c < 2 * kH + kP) {
         if (c - 2 * kH < d.nout) grad[o.b3 + c - 2 * kH] = (float)s;
-    } else if (c == kPart - 1) {
+    } else {
         loss[0] = s * inv_count;
     }
 }
@@ -516,8 +520,8 @@ hipError_t mlp_grad(const MlpDev &d, const MlpScratch &w, int mode, const float 
     hipLaunchKernelGGL(k_wgrad, dim3(24), dim3(256), 0, s, d, Bp, w.xf, w.h1, w.h2, w.dz1, w.dz2, w.dO,
                        grad);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_reduce_part, dim3((kPart + 255) / 256), dim3(256), 0, s, d, w.part, tiles, grad,
-                       loss, (double)inv);
+    hipLaunchKernelGGL(k_reduce_part, dim3(kPart), dim3(256), 0, s, d, w.part, tiles, grad, loss,
+                       (double)inv);
     return hipGetLastError();
 }
 
@@ -537,103 +541,166 @@ hipError_t mlp_stats(const float *S, const float *S1, int64_t n, int nin, double
     return hipGetLastError();
 }
 
+// Anchor: shift the output biases so that the network maps state s0 exactly to
+// the normalised target increment of (s0 -> s1) (one wave, sample 0 of a tile).
+__global__ __launch_bounds__(64) void k_anchor(MlpDev d, const float *s0, const float *s1, float *p)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
+    __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
+    __shared__ float outv[kP];
+    stage_weights(d, w1, w2, w3, nullptr, nullptr, bias);
+    __syncthreads();
+    const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
+    const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+    bf8 x;
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+        const int f = 8 * g + i;
+        x[i] = bf(j == 0 && f < d.nin ? (s0[f] - d.norm[f]) * d.norm[kP + f] : 0.0f);
+    }
+    f4v out[2], z1[8], z2[8];
+    bf8 h1[4], h2[4];
+    fwd_tile(W, x, out, z1, z2, h1, h2);
+    if (j == 0)
+#pragma unroll
+        for (int mt = 0; mt < 2; mt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) outv[16 * mt + 4 * g + i] = out[mt][i];
+    __syncthreads();
+    const POff o = poff(d.nin, d.nout);
+    if (l < d.nout) {
+        const float sg = d.norm[3 * kP + l];
+        const float tgt = sg > 0.0f ? ((s1[l] - s0[l]) - d.norm[2 * kP + l]) / sg : 0.0f;
+        p[o.b3 + l] += tgt - outv[l];
+    }
+}
+
+hipError_t mlp_anchor(const MlpDev &d, const float *s0, const float *s1, float *p, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_anchor, dim3(1), dim3(64), 0, s, d, s0, s1, p);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return mlp_pack(p, d, s);
+}
+
 uint64_t mlp_mix64(uint64_t z) { return mix64(z); }
 
 // ------------------------------------------------------- surrogate step
-// Fused step with the network as kinetics (FP32).  Per workgroup: 512 tissue
-// voxels (one per thread).  Each thread computes its Laplacian and stimulus,
+// Fused step with the network as kinetics (FP32).  One persistent workgroup per
+// CU stages the weights in LDS once and walks chunks of kSurBlock tissue voxels
+// (one per thread).  Each thread computes its Laplacian and stimulus,
 // the kinetic input s = (V or V* = V + dt LV, g) and its normalised form, which
 // goes to the wave's LDS staging rows; each wave then runs the network on its
 // 64 voxels as four 16-sample tiles, writes the outputs back to the staging
 // rows, and each thread applies or rejects its prediction.  Rejected voxels
 // (input outside [lo, hi], gate outside [0, 1], |dV| > dv_max, non-finite) are
 // appended to the fallback list and left untouched for the plain kernel.
+// Accepted gate predictions within kGateTol of [0, 1] are clamped into it.
 template <class M, bool ANISO>
 __global__ __launch_bounds__(kSurBlock) void k_step_mlp(const StepArgs<float> a, const SurArgs su)
 {
     constexpr int NW = kSurBlock / 64;
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
-    __shared__ float bias[2 * kH + kP];
+    __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
     __shared__ __attribute__((aligned(16))) __bf16 xin[NW][64 * kS1];   // inputs, one row per voxel
     __shared__ float oout[NW][16 * kOS];                                 // outputs of one tile
-    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
-    if (lb >= a.nblk) return;                                  // workgroup-uniform
+    // persistent workgroups: stage the weights once, then walk the voxel chunks
     stage_weights(su.net, w1, w2, w3, nullptr, nullptr, bias);
-
+    const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
     constexpr int NV = M::NV;
     const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
-    const int t = lb * kSurBlock + (int)threadIdx.x;
-    const bool valid = t < a.nact;
     const float *nrm = su.net.norm;
 
-    int idx = 0;
-    float Vp = 0.f, LV = 0.f, Is = 0.f;
-    float s[NV] = {};
-    bool ok = valid;
-    __bf16 *xrow = xin[wv] + l * kS1;
-    if (valid) {
-        uint32_t bits;
-        voxel_of(a, t, idx, bits);
-        Vp = a.Vin[idx];
-        LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-        Is = stim_current(a, t);
-        s[0] = a.split ? Vp + a.dt * LV : Vp;
+    for (int lb = blockIdx.x; lb < a.nblk; lb += gridDim.x) {
+        const int t = lb * kSurBlock + (int)threadIdx.x;
+        const bool valid = t < a.nact;
+        int idx = 0;
+        float Vp = 0.f, LV = 0.f, Is = 0.f;
+        float s[NV] = {};
+        bool ok = valid;
+        __bf16 *xrow = xin[wv] + l * kS1;
+        if (valid) {
+            uint32_t bits;
+            voxel_of(a, t, idx, bits);
+            Vp = a.Vin[idx];
+            LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
+            Is = stim_current(a, t);
+            s[0] = a.split ? Vp + a.dt * LV : Vp;
 #pragma unroll
-        for (int i = 1; i < NV; i++) s[i] = a.st[(i - 1) * a.pitch + t];
+            for (int i = 1; i < NV; i++) s[i] = a.st[(i - 1) * a.pitch + t];
 #pragma unroll
-        for (int i = 0; i < NV; i++) ok = ok && s[i] >= su.lo[i] && s[i] <= su.hi[i];
-    }
+            for (int i = 0; i < NV; i++) ok = ok && s[i] >= su.lo[i] && s[i] <= su.hi[i];
+        }
+        __syncthreads();                                       // previous chunk done with LDS
 #pragma unroll
-    for (int f = 0; f < NV; f++) xrow[f] = bf(valid ? (s[f] - nrm[f]) * nrm[kP + f] : 0.0f);
+        for (int f = 0; f < NV; f++) xrow[f] = bf(valid ? (s[f] - nrm[f]) * nrm[kP + f] : 0.0f);
 #pragma unroll
-    for (int f = NV; f < kP; f++) xrow[f] = bf(0.0f);
-    __syncthreads();                                           // weights and inputs staged
+        for (int f = NV; f < kP; f++) xrow[f] = bf(0.0f);
+        __syncthreads();                                       // weights and inputs staged
 
-    const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
-    float *os = oout[wv];
-    float d[NV];
+        float *os = oout[wv];
+        float d[NV] = {};
+        const uint64_t want = __ballot(ok);                    // voxels still accepted
 #pragma unroll 1
-    for (int T = 0; T < 4; T++) {
-        const bf8 x = ld8(xin[wv] + (16 * T + j) * kS1 + 8 * g);
-        f4v out[2], z1[8], z2[8];
-        bf8 h1[4], h2[4];
-        fwd_tile(W, x, out, z1, z2, h1, h2);
+        for (int T = 0; T < 4; T++) {
+            if (((want >> (16 * T)) & 0xFFFFull) == 0) continue;    // whole tile rejected
+            const bf8 x = ld8(xin[wv] + (16 * T + j) * kS1 + 8 * g);
+            f4v out[2], z1[8], z2[8];
+            bf8 h1[4], h2[4];
+            fwd_tile(W, x, out, z1, z2, h1, h2);
 #pragma unroll
-        for (int mt = 0; mt < 2; mt++)
+            for (int mt = 0; mt < 2; mt++)
 #pragma unroll
-            for (int i = 0; i < 4; i++) os[j * kOS + 16 * mt + 4 * g + i] = out[mt][i];
-        // wave-internal hand-over: the LDS writes above precede these reads in the
-        // wave's in-order LDS queue
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if ((l >> 4) == T)
+                for (int i = 0; i < 4; i++) os[j * kOS + 16 * mt + 4 * g + i] = out[mt][i];
+            // wave-internal hand-over: the LDS writes above precede these reads in the
+            // wave's in-order LDS queue
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if ((l >> 4) == T)
 #pragma unroll
-            for (int i = 0; i < NV; i++) d[i] = os[j * kOS + i];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    }
-    if (!valid) return;
+                for (int i = 0; i < NV; i++) d[i] = os[j * kOS + i];
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
+        if (!valid) continue;
 
 #pragma unroll
-    for (int i = 0; i < NV; i++) {
-        d[i] = d[i] * nrm[3 * kP + i] + nrm[2 * kP + i];
-        ok = ok && isfinite(d[i]);
-    }
-    ok = ok && fabsf(d[0]) <= su.dv_max;
+        for (int i = 0; i < NV; i++) {
+            d[i] = d[i] * nrm[3 * kP + i] + nrm[2 * kP + i];
+            ok = ok && isfinite(d[i]);
+        }
+        ok = ok && fabsf(d[0]) <= su.dv_max;
+        // gates: accept excursions of at most kGateTol outside [0, 1] (rounding-level
+        // errors at resting values 0 or 1) and clamp; reject anything larger
 #pragma unroll
-    for (int i = M::GATE0; i < NV; i++) ok = ok && s[i] + d[i] >= 0.0f && s[i] + d[i] <= 1.0f;
-    if (!ok) {
-        const int k = atomicAdd(&su.fb_cnt[su.parity], 1);
-        su.fb_list[k] = t;
-        return;
-    }
-    const float Vn = a.split ? s[0] + d[0] + a.dt * Is : Vp + d[0] + a.dt * (Is + LV);
+        for (int i = M::GATE0; i < NV; i++)
+            ok = ok && s[i] + d[i] >= -kGateTol && s[i] + d[i] <= 1.0f + kGateTol;
+        // compact the rejected voxels into the fallback list: one atomic per wave,
+        // slots by prefix count of the wave's ballot over its valid lanes
+        const uint64_t rej = __ballot(!ok);
+        if (rej) {
+            const int leader = __ffsll((unsigned long long)rej) - 1;
+            int base = 0;
+            if (l == leader) base = atomicAdd(&su.fb_cnt[su.parity], __popcll(rej));
+            base = __shfl(base, leader);
+            if (!ok) {
+                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(rej >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)rej, 0u));
+                su.fb_list[base + below] = t;
+                continue;
+            }
+        }
+        const float Vn = a.split ? s[0] + d[0] + a.dt * Is : Vp + d[0] + a.dt * (Is + LV);
 #pragma unroll
-    for (int i = 1; i < NV; i++) a.st[(i - 1) * a.pitch + t] = s[i] + d[i];
-    a.Vout[idx] = Vn;
-    record_voxel(a, t, Vp, Vn);
+        for (int i = 1; i < NV; i++) {
+            const float y = s[i] + d[i];
+            a.st[(i - 1) * a.pitch + t] = i >= M::GATE0 ? fminf(fmaxf(y, 0.0f), 1.0f) : y;
+        }
+        a.Vout[idx] = Vn;
+        record_voxel(a, t, Vp, Vn);
+    }
 }
 
 // Plain kinetics for the voxels the surrogate rejected this step (grid-stride
@@ -690,7 +757,11 @@ __global__ void k_ionic(const StepArgs<float> a, const float *in, int64_t n, flo
 template <class M>
 static hipError_t sur_m(int aniso, const StepArgs<float> &a, const SurArgs &su, hipStream_t s)
 {
-    const dim3 grid(a.per_xcd * kXcd), block(kSurBlock);
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const dim3 grid((unsigned)(a.nblk < ncu ? a.nblk : ncu)), block(kSurBlock);
+    if (a.nblk == 0) return hipSuccess;
     if (aniso) hipLaunchKernelGGL((k_step_mlp<M, true>), grid, block, 0, s, a, su);
     else hipLaunchKernelGGL((k_step_mlp<M, false>), grid, block, 0, s, a, su);
     return hipGetLastError();

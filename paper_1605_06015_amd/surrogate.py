@@ -1,0 +1,98 @@
+"""Training pipeline of the surrogate ionic map (sequencing of library calls).
+
+Every computation runs in libbbx kernels: the simulator produces states
+(bbx_step with periodic stimuli), bbx_sample_states draws voxel states,
+bbx_ionic_map applies the plain kinetic one-step map to them (the training
+targets), bbx_mlp_fit_norm fits the normalisation, bbx_mlp_train runs the
+BF16-MFMA forward/backward/Adam kernels, and bbx_surrogate_set attaches the
+network to a grid.  This module only orders those calls; torch provides the
+device buffers.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import bbx as B
+from . import workloads as WL
+
+
+@dataclass
+class Trained:
+    mlp: "B.Mlp"
+    stats: np.ndarray        # (7, 32): state mean/std/min/max, increment mean/std/max|.|
+    loss: np.ndarray         # per-iteration training loss
+    npairs: int
+
+
+def generate_pairs(nx=128, ny=128, nz=64, runs=3, t_ms=1200.0, every_ms=1.0, per_sample=2048,
+                   cl_range=(250.0, 1000.0), seed=2, stream=None):
+    """States of the 3D CRN cup paced from the apex at seeded cycle lengths, sampled
+    every `every_ms` at `per_sample` random tissue voxels, and their plain kinetic
+    one-step images.  Returns device tensors S, S1 of shape (N, 21) (FP32)."""
+    import torch
+    c = WL.CRN_3D
+    rng = np.random.default_rng(seed)
+    g0 = WL.crn_cup(nx, ny, nz, seed=c["seed"], active=c["active"], h=c["h"])
+    nsamp = int(round(t_ms / every_ms))
+    S = torch.empty((runs * nsamp * per_sample, 21), dtype=torch.float32, device="cuda")
+    S1 = torch.empty_like(S)
+    k = 0
+    every = int(round(every_ms / c["dt"]))
+    for r in range(runs):
+        cl = float(rng.uniform(*cl_range))
+        grid = B.Grid(g0["mask"], c["h"], g0["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
+        grid.model(B.BBX_MODEL_CRN, [], c["dt"])
+        for v in range(21):
+            grid.set(v, g0["state"][v])
+        grid.stimulus(g0["stim"], c["stim_amp"], 0.0, c["stim_ms"], period=cl, count=0)
+        grid.nan_check(0)
+        for i in range(nsamp):
+            grid.step(every)
+            sl = S[k:k + per_sample]
+            grid.sample_states(per_sample, int(rng.integers(1 << 62)), sl)
+            grid.ionic_map(sl, S1[k:k + per_sample])
+            k += per_sample
+        grid.close()
+    torch.cuda.synchronize()
+    return S[:k], S1[:k]
+
+
+def train(S, S1, iters=20000, batch=4096, lr=1e-3, seed=0, stream=None, anchor_grid=None):
+    """Fit the normalisation and train a 21 -> 128 -> 128 -> 21 network.  If
+    anchor_grid is given (a grid with the plain CRN kinetics), the network is
+    anchored so that the published resting state is an exact fixed point."""
+    import torch
+    m = B.Mlp(21, 21, seed=seed, stream=stream)
+    stats = m.fit_norm(S, S1)
+    hist = m.train(S, S1, batch, iters, lr, seed=seed + 1)
+    if anchor_grid is not None:
+        s0 = torch.tensor([WL.CRN_INITIAL], dtype=torch.float32, device="cuda")
+        s1 = torch.empty_like(s0)
+        anchor_grid.ionic_map(s0, s1)
+        torch.cuda.synchronize()
+        m.anchor(s0, s1)
+    return Trained(m, stats, hist, int(S.shape[0]))
+
+
+def accepted_box(stats, margin=0.02, dv_cap=None):
+    """Accepted kinetic inputs: the training range widened by `margin` of its width;
+    |dV| up to the training maximum (or dv_cap if smaller)."""
+    lo = stats[2, :21].copy()
+    hi = stats[3, :21].copy()
+    # a feature that barely varied in training still gets a box of 1e-3 of its size
+    w = np.maximum(hi - lo, 1e-3 * np.maximum(np.abs(lo), np.abs(hi)))
+    w = np.maximum(w, 1e-12)
+    lo -= margin * w
+    hi += margin * w
+    dv = stats[6, 0] * 1.1
+    if dv_cap is not None:
+        dv = min(dv, dv_cap)
+    return lo.astype(np.float32), hi.astype(np.float32), float(dv)
+
+
+def attach(grid, trained, margin=0.02, dv_cap=None):
+    lo, hi, dv = accepted_box(trained.stats, margin, dv_cap)
+    grid.surrogate(trained.mlp, lo, hi, dv)
+    return lo, hi, dv

@@ -203,3 +203,50 @@ def test_surrogate_rejects_bad_setups(env):
     with pytest.raises(B.BBXError) as ei:
         g2.surrogate(m, np.zeros(NIN), np.ones(NIN), 1.0)
     assert ei.value.code == B.BBX_EINVAL
+
+
+def test_training_pipeline_and_gain(env):
+    """End to end on a small cup: simulator-generated pairs -> BF16-MFMA training ->
+    anchored surrogate.  The trained network must beat both the untrained network and
+    the no-network predictor of the mean increment (normalised loss 1) by a wide
+    margin, and the attached surrogate must take over a share of the voxel updates
+    while keeping activation times close to the plain run."""
+    B, torch = env
+    from paper_1605_06015_amd import surrogate as SU
+    S, S1 = SU.generate_pairs(nx=40, ny=40, nz=20, runs=1, t_ms=400.0, per_sample=1024, seed=4)
+    anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32)
+    anchor.model(B.BBX_MODEL_CRN, [], 0.01)
+    untrained = B.Mlp(21, 21, seed=0)
+    untrained.fit_norm(S, S1)
+    tr = SU.train(S, S1, iters=3000, batch=4096, lr=1e-3, seed=0, anchor_grid=anchor)
+    final = float(np.mean(tr.loss[-50:]))
+    first = float(np.mean(tr.loss[:5]))
+    print("training loss first", first, "final", final)
+    assert final < 0.02 and final < first / 20
+    # the surrogate on a fresh cup, 60 ms
+    c = WL.CRN_3D
+    g0 = WL.crn_cup(40, 40, 20, seed=c["seed"])
+    runs = {}
+    for name in ("plain", "surrogate"):
+        g = B.Grid(g0["mask"], c["h"], g0["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32)
+        g.model(B.BBX_MODEL_CRN, [], c["dt"])
+        for v in range(21):
+            g.set(v, g0["state"][v])
+        g.stimulus(g0["stim"], 40.0, 0.0, 2.0)
+        g.record(-40.0)
+        if name == "surrogate":
+            lo, hi, dv = SU.accepted_box(tr.stats)
+            hi[0] = -75.0
+            g.surrogate(tr.mlp, lo, hi, dv)
+        g.step(6000)
+        runs[name] = (g.read(B.BBX_READ_ACT_TIME), g.read(B.BBX_READ_FALLBACK_COUNT)[0], g.nact)
+    at_p, _, nact = runs["plain"]
+    at_s, fb, _ = runs["surrogate"]
+    m = g0["mask"] == 1
+    both = np.isfinite(at_p) & np.isfinite(at_s) & m
+    assert both.sum() > 0.9 * m.sum()
+    err = np.abs(at_p[both] - at_s[both])
+    share = 1.0 - fb / (6000 * nact)
+    print("surrogate share of voxel updates", share, "AT err mean/max (ms)", err.mean(), err.max())
+    assert 0.05 < share < 1.0
+    assert err.max() < 2.0
