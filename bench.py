@@ -30,7 +30,7 @@ METRIC = "voxel-updates/s (FP32 plain vs surrogate) at ≤1dt activation-time er
 HBM_PEAK_GBS = 8000.0
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 STEP_SOURCES = [os.path.join(ROOT, "paper_1605_06015_amd", "csrc", f)
-                for f in ("step_kernels.hip", "kinetics.h", "bbx_internal.h")]
+                for f in ("step_kernels.hip", "step_device.h", "kinetics.h", "bbx_internal.h")]
 
 # Algorithmic HBM bytes per tissue-voxel update of the fused CRN step in FP32:
 # 21 state values read + 21 written (4 B each) + geometry (box index 4, neighbour
@@ -177,7 +177,7 @@ def surrogate_line(stream, t_ms=500.0, iters=20000, v_hi=-75.0):
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import surrogate as SU
     t0 = time.perf_counter()
-    S, S1 = SU.generate_pairs(runs=2, t_ms=800.0, per_sample=2048, seed=2, stream=stream)
+    S, S1 = SU.generate_pairs(runs=3, t_ms=1200.0, per_sample=2048, seed=2, stream=stream)
     t1 = time.perf_counter()
     anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32, stream)
     anchor.model(B.BBX_MODEL_CRN, [], 0.01)
@@ -232,6 +232,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the stencil roofline and surrogate runs")
+    ap.add_argument("--sur-ms", type=float, default=500.0,
+                    help="simulated time of the surrogate comparison runs (ms)")
     ap.add_argument("--profile", choices=["crn", "stencil"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
@@ -294,7 +296,7 @@ def main():
     grid.close()
     if not args.no_extras:
         out["stencil_roofline"] = stencil_roofline(stream)
-        out["surrogate"] = surrogate_line(stream)
+        out["surrogate"] = surrogate_line(stream, t_ms=args.sur_ms)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))
