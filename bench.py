@@ -77,13 +77,15 @@ def time_steps(grid, stream, steps, warmup):
     return e0.elapsed_time(e1) / 1e3  # seconds
 
 
-def crn_workload(precision, stream):
+def crn_workload(precision, stream, tab_dv=0.0):
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import workloads as WL
     c = WL.CRN_3D
     g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
     grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], precision, stream)
     grid.model(B.BBX_MODEL_CRN, [], c["dt"])
+    if tab_dv > 0:
+        grid.tabulate(tab_dv)
     for v in range(21):
         grid.set(v, g["state"][v])
     grid.stimulus(g["stim"], c["stim_amp"], 0.0, c["stim_ms"])
@@ -224,6 +226,23 @@ def surrogate_line(stream, t_ms=500.0, iters=20000, v_hi=-75.0):
                          "train_s": round(t2 - t1, 2)}}
 
 
+def tabulated_line(stream, dv, steps, warmup):
+    """The same CRN workload with the voltage-only kinetic terms read from a table of
+    spacing dv (mV), timed like the headline run."""
+    from paper_1605_06015_amd import bbx as B
+    grid, _ = crn_workload(B.BBX_FP32, stream, tab_dv=dv)
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, steps, warmup)
+    if grid.read(B.BBX_READ_NAN_FLAG)[0]:
+        raise RuntimeError("non-finite state in the tabulated run")
+    nact = grid.nact
+    grid.close()
+    return {"workload": f"CRN cup 128x128x64, FP32, Rush-Larsen/current voltage terms tabulated "
+                        f"(dv {dv} mV, [-120, 80] mV, linear interpolation)",
+            "value": nact * steps / sec, "unit": "voxel-updates/s",
+            "ms_per_step": sec / steps * 1e3}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -234,7 +253,9 @@ def main():
                     help="skip the stencil roofline and surrogate runs")
     ap.add_argument("--sur-ms", type=float, default=500.0,
                     help="simulated time of the surrogate comparison runs (ms)")
-    ap.add_argument("--profile", choices=["crn", "stencil"], default=None,
+    ap.add_argument("--tab", type=float, default=0.05,
+                    help="table spacing (mV) of the tabulated CRN comparison line (0: skip)")
+    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -249,8 +270,9 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.profile:
-        if args.profile == "crn":
-            grid, _ = crn_workload(B.BBX_FP32, stream)
+        if args.profile in ("crn", "crn_tab"):
+            grid, _ = crn_workload(B.BBX_FP32, stream,
+                                   tab_dv=args.tab if args.profile == "crn_tab" else 0.0)
             grid.nan_check(0)
             grid.step(args.warmup + args.steps)
             grid.close()
@@ -295,6 +317,9 @@ def main():
     }
     grid.close()
     if not args.no_extras:
+        if args.tab > 0:
+            out["tabulated"] = tabulated_line(stream, args.tab, args.steps, args.warmup)
+            out["tabulated"]["speedup_vs_plain"] = round(ms_per_step / out["tabulated"]["ms_per_step"], 3)
         out["stencil_roofline"] = stencil_roofline(stream)
         out["surrogate"] = surrogate_line(stream, t_ms=args.sur_ms)
     if not args.no_cpu:

@@ -162,6 +162,16 @@ int bbx_recording_set(bbx_grid *g, double theta);
  * BBX_ENUMERIC if a value was not finite. */
 int bbx_nan_check_set(bbx_grid *g, int64_t every);
 
+/* Rush-Larsen tabulation ("Exponential solvers": the rate coefficients of
+ * gates that depend on V alone are precomputed on a grid of V at start time):
+ * dv > 0 makes an FP32 CRN grid read every voltage-only kinetic term (for the
+ * twelve voltage-gated gates y_inf and e^{-dt/tau}; six voltage factors of
+ * currents) from a table over [-120, 80] mV with spacing dv, evaluated in FP64
+ * and interpolated linearly (V outside the range is clamped).  The table is
+ * rebuilt by bbx_model_set.  dv = 0 returns to direct evaluation.  Other
+ * models or FP64 grids: BBX_ENOTSUP. */
+int bbx_tabulation_set(bbx_grid *g, double dv);
+
 /* Set the step counter (t = step * dt), e.g. when resuming from a checkpoint
  * read with BBX_READ_VAR / BBX_READ_STEP; step >= 0. */
 int bbx_clock_set(bbx_grid *g, int64_t step);

@@ -38,6 +38,7 @@ SIGNATURES = {
     "bbx_recording_set": (_I, [_P, _D]),
     "bbx_nan_check_set": (_I, [_P, _I64]),
     "bbx_clock_set": (_I, [_P, _I64]),
+    "bbx_tabulation_set": (_I, [_P, _D]),
     "bbx_step": (_I, [_P, _I64]),
     "bbx_readout": (_I, [_P, _I, _I, _P, _P, _SZ, _I]),
     "bbx_info": (_I, [_P, _I, C.POINTER(_I64)]),
@@ -148,6 +149,10 @@ def bbx_nan_check_set(g, every):
     _check(_lib.bbx_nan_check_set(g, int(every)))
 
 
+def bbx_tabulation_set(g, dv):
+    _check(_lib.bbx_tabulation_set(g, float(dv)))
+
+
 def bbx_clock_set(g, step):
     _check(_lib.bbx_clock_set(g, int(step)))
 
@@ -229,6 +234,9 @@ class Grid:
 
     def clock(self, step):
         bbx_clock_set(self.handle, step)
+
+    def tabulate(self, dv):
+        bbx_tabulation_set(self.handle, dv)
 
     def sample_states(self, n, seed, out):
         bbx_sample_states(self.handle, n, seed, out)

@@ -2,6 +2,7 @@
 // with a fixed summation order, the finite-value check, and the effective
 // stencil weights (for inspection against the paper's weight formulas).
 #include "bbx_internal.h"
+#include "kinetics.h"
 
 namespace bbx {
 
@@ -243,6 +244,29 @@ hipError_t launch_weights(const StepArgs<T> &a, int aniso, double *W, hipStream_
 {
     if (a.nact <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_weights<T>, dim3(blocks_for(a.nact)), dim3(kBlock), 0, s, a, aniso, W);
+    return hipGetLastError();
+}
+
+// Table of the CRN voltage-only terms for time step dt, evaluated in FP64 at
+// V_k = vmin + k dv (k < n) and stored in FP32 after a header {vmin, 1/dv, n}.
+__global__ void k_crn_table(double vmin, double dv, int n, double dt, float *tab)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k == 0) {
+        tab[0] = (float)vmin;
+        tab[1] = (float)(1.0 / dv);
+        tab[2] = (float)n;
+        for (int q = 3; q < kin::CRN_V; q++) tab[q] = 0.0f;
+    }
+    if (k >= n) return;
+    double c[kin::CRN_V];
+    kin::crn_vterms<double>(vmin + k * dv, dt, c);
+    for (int q = 0; q < kin::CRN_V; q++) tab[kin::CRN_V * (1 + k) + q] = (float)c[q];
+}
+
+hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_crn_table, dim3((n + 255) / 256), dim3(256), 0, s, vmin, dv, n, dt, tab);
     return hipGetLastError();
 }
 

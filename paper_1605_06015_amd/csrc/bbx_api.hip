@@ -113,6 +113,9 @@ struct bbx_grid {
     void *d_at = nullptr, *d_vmax = nullptr, *d_apd = nullptr, *d_vrep = nullptr;
 
     int64_t n = 0, nan_every = 1000;
+    double tab_dv = 0;                 // > 0: CRN voltage-only terms from a table
+    float *d_tab = nullptr;
+    int tab_n = 0;
     // attached surrogate (FP32 grids): network copy, accepted box, fallback list
     int sur = 0;
     MlpDev snet = {};
@@ -150,7 +153,7 @@ void free_all(bbx_grid *g)
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
-                  g->d_fb_list, g->d_fb_cnt, g->d_fb_total, g->snet.w1, g->snet.w2, g->snet.w3,
+                  g->d_fb_list, g->d_fb_cnt, g->d_fb_total, g->d_tab, g->snet.w1, g->snet.w2, g->snet.w3,
                   g->snet.bias, g->snet.norm};
     for (void *p : ps) dfree(p);
 }
@@ -192,6 +195,7 @@ StepArgs<T> make_args(const bbx_grid *g)
     for (int i = 0; i < kMaxParams; i++) a.prm[i] = (T)g->prm[i];
     a.dt = (T)g->dt;
     a.split = g->scheme == BBX_SCHEME_SPLIT;
+    a.tab = (g->tab_dv > 0 && g->model == BBX_MODEL_CRN && g->prec == BBX_FP32) ? g->d_tab : nullptr;
     a.nstim = (int)g->stims.size();
     a.stimbits = g->d_stimbits;
     a.stim_amp = (const T *)g->d_stimamp;
@@ -237,6 +241,23 @@ uint32_t stim_mask(const bbx_grid *g, int64_t n)
         if (on) m |= 1u << k;
     }
     return m;
+}
+
+// (Re)build the CRN voltage table for the current dt (FP32 CRN grids with tabulation on).
+int build_table(bbx_grid *g)
+{
+    if (!(g->tab_dv > 0) || g->model != BBX_MODEL_CRN || g->prec != BBX_FP32) return BBX_OK;
+    const int n = (int)ceil((kTabVmax - kTabVmin) / g->tab_dv) + 1;
+    if (n != g->tab_n) {
+        dfree(g->d_tab);
+        g->d_tab = nullptr;
+        g->tab_n = 0;
+        hipError_t e = dalloc(g, &g->d_tab, (size_t)(n + 1) * kTabWidth * sizeof(float));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        g->tab_n = n;
+    }
+    HIP_TRY(launch_crn_table(kTabVmin, g->tab_dv, n, g->dt, g->d_tab, g->stream), "table");
+    return BBX_OK;
 }
 
 SurArgs sur_args(const bbx_grid *g, int parity)
@@ -700,7 +721,7 @@ int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, dou
         g->scheme = scheme;
         for (int i = 0; i < kMaxParams; i++) g->prm[i] = i < np ? params[i] : 0.0;
         g->n = 0;
-        return BBX_OK;
+        return build_table(g);
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
     }
@@ -790,6 +811,20 @@ int bbx_nan_check_set(bbx_grid *g, int64_t every)
     if (every < 0) return fail(BBX_EINVAL, "every must be >= 0");
     g->nan_every = every;
     return BBX_OK;
+}
+
+int bbx_tabulation_set(bbx_grid *g, double dv)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (!(dv >= 0) || !isfinite(dv)) return fail(BBX_EINVAL, "dv must be >= 0");
+    if (dv > 0) {
+        if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "tabulation is an FP32 variant");
+        if (g->model != BBX_MODEL_CRN) return fail(BBX_ENOTSUP, "tabulation is provided for the CRN model");
+        if (dv < 1e-4 || (kTabVmax - kTabVmin) / dv > 1e7) return fail(BBX_EINVAL, "dv out of range");
+    }
+    g->tab_dv = dv;
+    return build_table(g);
 }
 
 int bbx_clock_set(bbx_grid *g, int64_t step)

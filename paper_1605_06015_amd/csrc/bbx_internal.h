@@ -46,6 +46,7 @@ struct StepArgs {
     T prm[kMaxParams];
     T dt;
     int split;
+    const float *tab;          // tabulated voltage-only kinetic terms (FP32 CRN) or null
     // stimulus
     int nstim;
     uint32_t stim_on;          // bit s: stimulus s active at this step
@@ -88,6 +89,9 @@ template <typename T>
 hipError_t launch_weights(const StepArgs<T> &a, int aniso, double *W, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t s);
+hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab, hipStream_t s);
+constexpr double kTabVmin = -120.0, kTabVmax = 80.0;   // tabulated voltage range (mV)
+constexpr int kTabWidth = 32;                           // floats per table node
 template <typename T>
 hipError_t launch_gather(const T *box, const int32_t *idx, int dense, int64_t nact, T *dst,
                          hipStream_t s);

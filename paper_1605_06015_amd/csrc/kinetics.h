@@ -1,7 +1,8 @@
 // Device-side cell kinetics for the fused step kernel.
 //
 // Each model provides NV (state variables including V), GATE0 (variables
-// GATE0..NV-1 are gating variables) and  T advance(const T* prm, T V, T* g, T dt):  given the
+// GATE0..NV-1 are gating variables) and
+//   T advance(const T* prm, T V, T* g, T dt, const float* tab):  given the
 // voltage the kinetics see (V_n, or V* in the split scheme) and the other state
 // variables g[0..NV-2], it returns the kinetic part of dV/dt (= -I_ion, with a
 // positive stimulus depolarising) and advances g in place by one step:
@@ -9,6 +10,7 @@
 // Rush-Larsen for gates -- y+ = y_inf + (y - y_inf) exp(-dt/tau), the exact
 // solution of y' = (y_inf - y)/tau with the voltage frozen (eqs (gate), (RL),
 // (RLcoeff), with the two coefficients in the order that makes it exact).
+// `tab` is the optional table of voltage-only terms (CrnTab), else unused.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -77,7 +79,7 @@ __device__ __forceinline__ T lgs(T x)
 template <typename T>
 struct None {
     static constexpr int NV = 1, GATE0 = 1;
-    __device__ static T advance(const T *, T, T *, T) { return T(0); }
+    __device__ static T advance(const T *, T, T *, T, const float *) { return T(0); }
 };
 
 // ---------------------------------------------------------------- Barkley (1991)
@@ -85,7 +87,7 @@ struct None {
 template <typename T>
 struct Barkley {
     static constexpr int NV = 2, GATE0 = 2;
-    __device__ static T advance(const T *p, T u, T *g, T dt)
+    __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
     {
         T v = g[0];
         T uth = (v + p[1]) / p[0];
@@ -99,7 +101,7 @@ struct Barkley {
 template <typename T>
 struct Zfk {
     static constexpr int NV = 1, GATE0 = 1;
-    __device__ static T advance(const T *p, T V, T *, T)
+    __device__ static T advance(const T *p, T V, T *, T, const float *)
     {
         return V * (V - p[0]) * (T(1) - V);
     }
@@ -110,7 +112,7 @@ struct Zfk {
 template <typename T>
 struct Fhn {
     static constexpr int NV = 2, GATE0 = 2;
-    __device__ static T advance(const T *p, T u, T *g, T dt)
+    __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
     {
         T v = g[0];
         g[0] = v + dt * p[0] * (u + p[1] - p[2] * v);
@@ -123,153 +125,255 @@ struct Fhn {
 // myocyte; the paper uses it for its scaling runs.  Transcribed from that
 // publication.  g = Na_i, K_i, Ca_i, Ca_up, Ca_rel, m, h, j, oa, oi, ua, ui,
 // xr, xs, d, f, fCa, u, v, w.  Currents per unit capacitance (pA/pF).
+//
+// The kinetics split into terms that depend on V alone (CRN_V entries: for the
+// twelve voltage-gated gates the steady state y_inf and the one-step
+// Rush-Larsen factor e^{-dt/tau}; six voltage factors of currents) and the
+// rest.  The voltage-only terms are either evaluated directly (Crn) or read
+// from a table over V built once per time step size (CrnTab: the start-time
+// tabulation of the paper's `rushlarsen` device, "Exponential solvers").
+enum {
+    CV_M, CV_MA, CV_H, CV_HA, CV_J, CV_JA, CV_OA, CV_OAA, CV_OI, CV_OIA, CV_UA, CV_UAA,
+    CV_UI, CV_UIA, CV_XR, CV_XRA, CV_XS, CV_XSA, CV_D, CV_DA, CV_F, CV_FA, CV_W, CV_WA,
+    CV_K1, CV_KR, CV_GKUR, CV_FNAK, CV_EG, CV_EG1, CRN_V = 32  // 30 used, padded to 32
+};
+
+namespace crn {
+constexpr double kRTF = 8.3143 * 310.0 / 96.4867;  // mV
+constexpr double kF = 96.4867;                    // C/mmol
+constexpr double kCm = 100.0;                     // pF
+constexpr double kVi = 13668.0, kVup = 1109.52, kVrel = 96.48;  // um^3
+constexpr double kNao = 140.0, kKo = 5.4, kCao = 1.8;           // mM
+constexpr double kNaCa = 1600.0 / ((87.5 * 87.5 * 87.5 + kNao * kNao * kNao) * (1.38 + kCao));
+}  // namespace crn
+
+// Voltage-only terms at V for time step dt.
+template <typename T>
+__device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
+{
+    using namespace crn;
+    // fast sodium current gates m, h, j from opening/closing rates
+    {
+        T am = T(3.2) * bern(T(-0.1) * (V + T(47.13)));
+        T bm = T(0.08) * ex(-V * T(1.0 / 11.0));
+        T ah, bh, aj, bj;
+        if (V < T(-40)) {
+            ah = T(0.135) * ex((V + T(80)) * T(-1.0 / 6.8));
+            bh = T(3.56) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.35) * V);
+            aj = (T(-127140) * ex(T(0.2444) * V) - T(3.474e-5) * ex(T(-0.04391) * V))
+                 * (V + T(37.78)) * lgs(T(0.311) * (V + T(79.23)));
+            bj = T(0.1212) * ex(T(-0.01052) * V) * lgs(T(-0.1378) * (V + T(40.14)));
+        } else {
+            ah = T(0);
+            bh = T(1.0 / 0.13) * lgs((V + T(10.66)) * T(-1.0 / 11.1));
+            aj = T(0);
+            bj = T(0.3) * ex(T(-2.535e-7) * V) * lgs(T(-0.1) * (V + T(32)));
+        }
+        T k = am + bm;
+        c[CV_M] = am * rcp(k);
+        c[CV_MA] = ex(-dt * k);
+        k = ah + bh;
+        c[CV_H] = ah * rcp(k);
+        c[CV_HA] = ex(-dt * k);
+        k = aj + bj;
+        c[CV_J] = aj * rcp(k);
+        c[CV_JA] = ex(-dt * k);
+    }
+    // transient outward (oa, oi) and ultrarapid (ua, ui) potassium gates; the
+    // activation rates of oa and ua share one form; Q10 factor 3
+    {
+        T a_act = T(0.65) * rcp(ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
+        T b_act = T(0.65) * rcp(T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
+        const T ea = ex(-dt * T(3) * (a_act + b_act));
+        c[CV_OA] = lgs((V + T(20.47)) * T(-1.0 / 17.54));
+        c[CV_OAA] = ea;
+        c[CV_UA] = lgs((V + T(30.3)) * T(-1.0 / 9.6));
+        c[CV_UAA] = ea;
+        T aoi = rcp(T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
+        T boi = rcp(T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
+        c[CV_OI] = lgs((V + T(43.1)) * T(1.0 / 5.3));
+        c[CV_OIA] = ex(-dt * T(3) * (aoi + boi));
+        T aui = rcp(T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
+        T bui = ex((V - T(158)) * T(1.0 / 16.0));
+        c[CV_UI] = lgs((V - T(99.45)) * T(1.0 / 27.48));
+        c[CV_UIA] = ex(-dt * T(3) * (aui + bui));
+    }
+    // rapid and slow delayed rectifier gates
+    {
+        T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
+        T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
+        c[CV_XR] = lgs((V + T(14.1)) * T(-1.0 / 6.5));
+        c[CV_XRA] = ex(-dt * (axr + bxr));
+        T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
+        T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
+        c[CV_XS] = rcp(sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7))));
+        c[CV_XSA] = ex(-dt * T(2) * (axs + bxs));
+    }
+    // L-type calcium gates d, f
+    {
+        T zd = (V + T(10)) * T(1.0 / 6.24);
+        // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
+        T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
+        c[CV_D] = lgs((V + T(10)) * T(-1.0 / 8.0));
+        c[CV_DA] = ex(-dt * kd);
+        T vv = V + T(10);
+        T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
+        c[CV_F] = lgs((V + T(28)) * T(1.0 / 6.9));
+        c[CV_FA] = ex(-dt * kf);
+    }
+    // release gate w
+    {
+        T zw = (V - T(7.9)) * T(0.2);
+        // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
+        T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
+        c[CV_W] = T(1) - lgs((V - T(40)) * T(-1.0 / 17.0));
+        c[CV_WA] = ex(-dt * kw);
+    }
+    // voltage factors of currents
+    {
+        const T vf = V * T(1.0 / kRTF);
+        c[CV_K1] = lgs(T(0.07) * (V + T(80)));
+        c[CV_KR] = lgs((V + T(15)) * T(1.0 / 22.4));
+        c[CV_GKUR] = T(0.005) + T(0.05) * lgs((V - T(15)) * T(-1.0 / 13.0));
+        const T sigma = T((8.006372134620099 - 1.0) / 7.0);  // (e^{[Na]o/67.3} - 1)/7
+        c[CV_FNAK] = rcp(T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
+        const T eg = ex(T(0.35) * vf), eg1 = ex(T(-0.65) * vf);
+        const T den = T(kNaCa) * rcp(T(1) + T(0.1) * eg1);
+        c[CV_EG] = eg * den;
+        c[CV_EG1] = eg1 * den;
+    }
+    c[30] = c[31] = T(0);
+}
+
+// Everything that is not univariate in V, given the voltage-only terms c.
+template <typename T>
+__device__ __forceinline__ T crn_rest(T V, T *g, T dt, const T *c)
+{
+    using namespace crn;
+    const T RTF = T(kRTF);
+    T Nai = g[0], Ki = g[1], Cai = g[2], Caup = g[3], Carel = g[4];
+
+    // reversal potentials
+    const T ENa = RTF * lg(dv(T(kNao), Nai));
+    const T EK = RTF * lg(dv(T(kKo), Ki));
+    const T ECa = T(0.5) * RTF * lg(dv(T(kCao), Cai));
+    const T dK = V - EK;
+
+    // currents from the state at step n, then the Rush-Larsen gate updates
+    T m = g[5], h = g[6], j = g[7];
+    const T INa = T(7.8) * m * m * m * h * j * (V - ENa);
+    g[5] = c[CV_M] + (m - c[CV_M]) * c[CV_MA];
+    g[6] = c[CV_H] + (h - c[CV_H]) * c[CV_HA];
+    g[7] = c[CV_J] + (j - c[CV_J]) * c[CV_JA];
+
+    T oa = g[8], oi = g[9], ua = g[10], ui = g[11];
+    const T Ito = T(0.1652) * oa * oa * oa * oi * dK;
+    const T IKur = c[CV_GKUR] * ua * ua * ua * ui * dK;
+    g[8] = c[CV_OA] + (oa - c[CV_OA]) * c[CV_OAA];
+    g[9] = c[CV_OI] + (oi - c[CV_OI]) * c[CV_OIA];
+    g[10] = c[CV_UA] + (ua - c[CV_UA]) * c[CV_UAA];
+    g[11] = c[CV_UI] + (ui - c[CV_UI]) * c[CV_UIA];
+
+    T xr = g[12], xs = g[13];
+    const T IKr = T(0.029411765) * xr * dK * c[CV_KR];
+    const T IKs = T(0.12941176) * xs * xs * dK;
+    g[12] = c[CV_XR] + (xr - c[CV_XR]) * c[CV_XRA];
+    g[13] = c[CV_XS] + (xs - c[CV_XS]) * c[CV_XSA];
+
+    const T IK1 = T(0.09) * dK * c[CV_K1];
+
+    T d = g[14], f = g[15], fCa = g[16];
+    const T ICaL = T(0.12375) * d * f * fCa * (V - T(65));
+    g[14] = c[CV_D] + (d - c[CV_D]) * c[CV_DA];
+    g[15] = c[CV_F] + (f - c[CV_F]) * c[CV_FA];
+    g[16] = rl_rate(fCa, rcp(T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
+
+    // pumps, exchanger and background currents
+    const T rNa = dv(T(10), Nai);
+    const T INaK = T(0.59933874 * kKo / (kKo + 1.5)) * c[CV_FNAK] * rcp(T(1) + rNa * sq(rNa));
+    const T INaCa = c[CV_EG] * Nai * Nai * Nai * T(kCao) - c[CV_EG1] * T(kNao * kNao * kNao) * Cai;
+    const T IbCa = T(0.001131) * (V - ECa);
+    const T IbNa = T(0.0006744375) * (V - ENa);
+    const T IpCa = T(0.275) * dv(Cai, T(0.0005) + Cai);
+
+    // sarcoplasmic reticulum fluxes (mM/ms), release gates u, v, w
+    T u = g[17], v = g[18], w = g[19];
+    const T Irel = T(30) * u * u * v * w * (Carel - Cai);
+    const T Itr = (Caup - Carel) * T(1.0 / 180.0);
+    const T Iup = T(0.005) * dv(Cai, Cai + T(0.00092));
+    const T Ileak = T(0.005 / 15.0) * Caup;
+    {
+        // release trigger from SR release and sarcolemmal Ca entry (currents in pA)
+        T Fn = T(1e-12 * kVrel) * Irel - T(5e-13 / kF * kCm) * (T(0.5) * ICaL - T(0.2) * INaCa);
+        T s1 = lgs(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16));
+        g[17] = rl_rate(u, s1, T(1.0 / 8.0), dt);
+        g[18] = rl_rate(v, T(1) - lgs(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16)),
+                        rcp(T(1.91) + T(2.09) * s1), dt);
+        g[19] = c[CV_W] + (w - c[CV_W]) * c[CV_WA];
+    }
+
+    // concentrations (forward Euler); current-to-flux factor Cm / (F Vi)
+    const T c2f = T(kCm / (kF * kVi));
+    g[0] = Nai + dt * c2f * (T(-3) * (INaK + INaCa) - IbNa - INa);
+    g[1] = Ki + dt * c2f * (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs);
+    {
+        T ct = Cai + T(0.0005), cc = Cai + T(0.00238);
+        T bt = T(0.07 * 0.0005) * rcp(ct * ct);
+        T bc = T(0.05 * 0.00238) * rcp(cc * cc);
+        T src = T(0.5) * c2f * (T(2) * INaCa - IpCa - ICaL - IbCa)
+                + (T(kVup) * (Ileak - Iup) + T(kVrel) * Irel) * T(1.0 / kVi);
+        g[2] = Cai + dt * src * rcp(T(1) + bt + bc);
+        g[3] = Caup + dt * (Iup - Ileak - Itr * T(kVrel / kVup));
+        T cq = Carel + T(0.8);
+        T bq = T(10.0 * 0.8) * rcp(cq * cq);
+        g[4] = Carel + dt * (Itr - Irel) * rcp(T(1) + bq);
+    }
+
+    return -(INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL);
+}
+
 template <typename T>
 struct Crn {
     static constexpr int NV = 21, GATE0 = 6;  // variables GATE0.. are gates in [0, 1]
-    __device__ static T advance(const T *, T V, T *g, T dt)
+    __device__ static T advance(const T *, T V, T *g, T dt, const float *)
     {
-        // physical constants and cell geometry
-        constexpr double kRTF = 8.3143 * 310.0 / 96.4867;  // mV
-        constexpr double kF = 96.4867;                    // C/mmol
-        constexpr double kCm = 100.0;                     // pF
-        constexpr double kVi = 13668.0, kVup = 1109.52, kVrel = 96.48;  // um^3
-        constexpr double kNao = 140.0, kKo = 5.4, kCao = 1.8;           // mM
-        const T RTF = T(kRTF), iRTF = T(1.0 / kRTF);
+        T c[CRN_V];
+        crn_vterms(V, dt, c);
+        return crn_rest(V, g, dt, c);
+    }
+};
 
-        T Nai = g[0], Ki = g[1], Cai = g[2], Caup = g[3], Carel = g[4];
+// Table of the voltage-only terms: header {vmin, 1/dv, n} in the first CRN_V
+// floats, then n nodes of CRN_V floats at V = vmin + k dv.  Linear
+// interpolation; V outside the table is clamped to its range.
+__device__ __forceinline__ void crn_lookup(const float *tab, float V, float *c)
+{
+    const float vmin = tab[0], inv = tab[1];
+    const int n = (int)tab[2];
+    const float x = (V - vmin) * inv;
+    int i = (int)floorf(x);
+    i = i < 0 ? 0 : (i > n - 2 ? n - 2 : i);
+    const float f = fminf(fmaxf(x - (float)i, 0.0f), 1.0f);
+    const float4 *p0 = (const float4 *)(tab + CRN_V * (1 + i));
+    const float4 *p1 = p0 + CRN_V / 4;
+#pragma unroll
+    for (int q = 0; q < CRN_V / 4; q++) {
+        const float4 a = p0[q], b = p1[q];
+        c[4 * q + 0] = a.x + f * (b.x - a.x);
+        c[4 * q + 1] = a.y + f * (b.y - a.y);
+        c[4 * q + 2] = a.z + f * (b.z - a.z);
+        c[4 * q + 3] = a.w + f * (b.w - a.w);
+    }
+}
 
-        // reversal potentials
-        const T ENa = RTF * lg(dv(T(kNao), Nai));
-        const T EK = RTF * lg(dv(T(kKo), Ki));
-        const T ECa = T(0.5) * RTF * lg(dv(T(kCao), Cai));
-        const T dK = V - EK;
-
-        // fast sodium current, gates m, h, j
-        T m = g[5], h = g[6], j = g[7];
-        const T INa = T(7.8) * m * m * m * h * j * (V - ENa);
-        {
-            T am = T(3.2) * bern(T(-0.1) * (V + T(47.13)));
-            T bm = T(0.08) * ex(-V * T(1.0 / 11.0));
-            T ah, bh, aj, bj;
-            if (V < T(-40)) {
-                ah = T(0.135) * ex((V + T(80)) * T(-1.0 / 6.8));
-                bh = T(3.56) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.35) * V);
-                aj = (T(-127140) * ex(T(0.2444) * V) - T(3.474e-5) * ex(T(-0.04391) * V))
-                     * (V + T(37.78)) * lgs(T(0.311) * (V + T(79.23)));
-                bj = T(0.1212) * ex(T(-0.01052) * V) * lgs(T(-0.1378) * (V + T(40.14)));
-            } else {
-                ah = T(0);
-                bh = T(1.0 / 0.13) * lgs((V + T(10.66)) * T(-1.0 / 11.1));
-                aj = T(0);
-                bj = T(0.3) * ex(T(-2.535e-7) * V) * lgs(T(-0.1) * (V + T(32)));
-            }
-            g[5] = rl_ab(m, am, bm, dt);
-            g[6] = rl_ab(h, ah, bh, dt);
-            g[7] = rl_ab(j, aj, bj, dt);
-        }
-
-        // transient outward (oa, oi) and ultrarapid (ua, ui) potassium currents;
-        // activation rates of oa and ua share one form; Q10 factor 3
-        T oa = g[8], oi = g[9], ua = g[10], ui = g[11];
-        const T Ito = T(0.1652) * oa * oa * oa * oi * dK;
-        const T gKur = T(0.005) + T(0.05) * lgs((V - T(15)) * T(-1.0 / 13.0));
-        const T IKur = gKur * ua * ua * ua * ui * dK;
-        {
-            T a_act = T(0.65) * rcp(ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
-            T b_act = T(0.65) * rcp(T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
-            T k_act = T(3) * (a_act + b_act);
-            g[8] = rl_rate(oa, lgs((V + T(20.47)) * T(-1.0 / 17.54)), k_act, dt);
-            g[10] = rl_rate(ua, lgs((V + T(30.3)) * T(-1.0 / 9.6)), k_act, dt);
-            T aoi = rcp(T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
-            T boi = rcp(T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
-            g[9] = rl_rate(oi, lgs((V + T(43.1)) * T(1.0 / 5.3)), T(3) * (aoi + boi), dt);
-            T aui = rcp(T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
-            T bui = ex((V - T(158)) * T(1.0 / 16.0));
-            g[11] = rl_rate(ui, lgs((V - T(99.45)) * T(1.0 / 27.48)), T(3) * (aui + bui), dt);
-        }
-
-        // rapid and slow delayed rectifiers
-        T xr = g[12], xs = g[13];
-        const T IKr = T(0.029411765) * xr * dK * lgs((V + T(15)) * T(1.0 / 22.4));
-        const T IKs = T(0.12941176) * xs * xs * dK;
-        {
-            T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
-            T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
-            g[12] = rl_rate(xr, lgs((V + T(14.1)) * T(-1.0 / 6.5)), axr + bxr, dt);
-            T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
-            T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
-            T xsinf = rcp(sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7))));
-            g[13] = rl_rate(xs, xsinf, T(2) * (axs + bxs), dt);
-        }
-
-        // inward rectifier
-        const T IK1 = T(0.09) * dK * lgs(T(0.07) * (V + T(80)));
-
-        // L-type calcium current, gates d, f, fCa (reversal fixed at 65 mV)
-        T d = g[14], f = g[15], fCa = g[16];
-        const T ICaL = T(0.12375) * d * f * fCa * (V - T(65));
-        {
-            T zd = (V + T(10)) * T(1.0 / 6.24);
-            // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
-            T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
-            g[14] = rl_rate(d, lgs((V + T(10)) * T(-1.0 / 8.0)), kd, dt);
-            T vv = V + T(10);
-            T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
-            g[15] = rl_rate(f, lgs((V + T(28)) * T(1.0 / 6.9)), kf, dt);
-            g[16] = rl_rate(fCa, rcp(T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
-        }
-
-        // pumps, exchanger and background currents
-        const T sigma = T((8.006372134620099 - 1.0) / 7.0);  // (e^{[Na]o/67.3} - 1)/7
-        const T vf = V * iRTF;
-        const T fNaK = rcp(T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
-        const T rNa = dv(T(10), Nai);
-        const T INaK = T(0.59933874 * kKo / (kKo + 1.5)) * fNaK * rcp(T(1) + rNa * sq(rNa));
-        const T eg = ex(T(0.35) * vf), eg1 = ex(T(-0.65) * vf);
-        const T INaCa = T(1600.0 / ((87.5 * 87.5 * 87.5 + kNao * kNao * kNao) * (1.38 + kCao)))
-                        * (eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao) * Cai)
-                        * rcp(T(1) + T(0.1) * eg1);
-        const T IbCa = T(0.001131) * (V - ECa);
-        const T IbNa = T(0.0006744375) * (V - ENa);
-        const T IpCa = T(0.275) * dv(Cai, T(0.0005) + Cai);
-
-        // sarcoplasmic reticulum fluxes (mM/ms), release gates u, v, w
-        T u = g[17], v = g[18], w = g[19];
-        const T Irel = T(30) * u * u * v * w * (Carel - Cai);
-        const T Itr = (Caup - Carel) * T(1.0 / 180.0);
-        const T Iup = T(0.005) * dv(Cai, Cai + T(0.00092));
-        const T Ileak = T(0.005 / 15.0) * Caup;
-        {
-            // release trigger from SR release and sarcolemmal Ca entry (currents in pA)
-            T Fn = T(1e-12 * kVrel) * Irel - T(5e-13 / kF * kCm) * (T(0.5) * ICaL - T(0.2) * INaCa);
-            T s1 = lgs(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16));
-            g[17] = rl_rate(u, s1, T(1.0 / 8.0), dt);
-            g[18] = rl_rate(v, T(1) - lgs(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16)),
-                            rcp(T(1.91) + T(2.09) * s1), dt);
-            T zw = (V - T(7.9)) * T(0.2);
-            // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
-            T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
-            g[19] = rl_rate(w, T(1) - lgs((V - T(40)) * T(-1.0 / 17.0)), kw, dt);
-        }
-
-        // concentrations (forward Euler); current-to-flux factor Cm / (F Vi)
-        const T c2f = T(kCm / (kF * kVi));
-        g[0] = Nai + dt * c2f * (T(-3) * (INaK + INaCa) - IbNa - INa);
-        g[1] = Ki + dt * c2f * (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs);
-        {
-            T ct = Cai + T(0.0005), cc = Cai + T(0.00238);
-            T bt = T(0.07 * 0.0005) * rcp(ct * ct);
-            T bc = T(0.05 * 0.00238) * rcp(cc * cc);
-            T src = T(0.5) * c2f * (T(2) * INaCa - IpCa - ICaL - IbCa)
-                    + (T(kVup) * (Ileak - Iup) + T(kVrel) * Irel) * T(1.0 / kVi);
-            g[2] = Cai + dt * src * rcp(T(1) + bt + bc);
-            g[3] = Caup + dt * (Iup - Ileak - Itr * T(kVrel / kVup));
-            T cq = Carel + T(0.8);
-            T bq = T(10.0 * 0.8) * rcp(cq * cq);
-            g[4] = Carel + dt * (Itr - Irel) * rcp(T(1) + bq);
-        }
-
-        return -(INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL);
+// CRN with tabulated voltage-only terms (FP32 only).
+struct CrnTab {
+    static constexpr int NV = 21, GATE0 = 6;
+    __device__ static float advance(const float *, float V, float *g, float dt, const float *tab)
+    {
+        float c[CRN_V];
+        crn_lookup(tab, V, c);
+        return crn_rest(V, g, dt, c);
     }
 };
 

@@ -748,7 +748,7 @@ __global__ void k_ionic(const StepArgs<float> a, const float *in, int64_t n, flo
     const float V = in[k * NV];
 #pragma unroll
     for (int i = 1; i < NV; i++) g[i - 1] = in[k * NV + i];
-    const float r = M::advance(a.prm, V, g, a.dt);
+    const float r = M::advance(a.prm, V, g, a.dt, a.tab);
     out[k * NV] = V + a.dt * r;
 #pragma unroll
     for (int i = 1; i < NV; i++) out[k * NV + i] = g[i - 1];
@@ -795,7 +795,7 @@ hipError_t launch_fallback(int model, int aniso, const StepArgs<float> &a, const
     switch (model) {
     case 1: return fb_m<kin::Barkley<float>>(aniso, a, su, s);
     case 3: return fb_m<kin::Fhn<float>>(aniso, a, su, s);
-    case 4: return fb_m<kin::Crn<float>>(aniso, a, su, s);
+    case 4: return a.tab ? fb_m<kin::CrnTab>(aniso, a, su, s) : fb_m<kin::Crn<float>>(aniso, a, su, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -819,7 +819,10 @@ hipError_t launch_ionic_map(int model, const StepArgs<float> &a, int nvar, const
     case 1: hipLaunchKernelGGL(k_ionic<kin::Barkley<float>>, grid, block, 0, s, a, in, n, out); break;
     case 2: hipLaunchKernelGGL(k_ionic<kin::Zfk<float>>, grid, block, 0, s, a, in, n, out); break;
     case 3: hipLaunchKernelGGL(k_ionic<kin::Fhn<float>>, grid, block, 0, s, a, in, n, out); break;
-    case 4: hipLaunchKernelGGL(k_ionic<kin::Crn<float>>, grid, block, 0, s, a, in, n, out); break;
+    case 4:
+        if (a.tab) hipLaunchKernelGGL(k_ionic<kin::CrnTab>, grid, block, 0, s, a, in, n, out);
+        else hipLaunchKernelGGL(k_ionic<kin::Crn<float>>, grid, block, 0, s, a, in, n, out);
+        break;
     default: return hipErrorInvalidValue;
     }
     (void)nvar;

@@ -119,7 +119,7 @@ __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int id
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) g[i] = a.st[i * a.pitch + t];
     const T Vin = a.split ? Vp + a.dt * LV : Vp;
-    const T r = M::advance(a.prm, Vin, g, a.dt);
+    const T r = M::advance(a.prm, Vin, g, a.dt, a.tab);
     const T Vn = a.split ? Vin + a.dt * (r + Is) : Vp + a.dt * (r + Is + LV);
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];

@@ -19,6 +19,8 @@
 // (coalesced, x-fastest order).  Workgroups are remapped so that each XCD works
 // on one contiguous slab of the tissue list, keeping neighbour planes in that
 // XCD's L2.
+#include <type_traits>
+
 #include "step_device.h"
 
 namespace bbx {
@@ -178,7 +180,10 @@ hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s
     case 1: return launch_m<T, kin::Barkley<T>>(aniso, a, s);
     case 2: return launch_m<T, kin::Zfk<T>>(aniso, a, s);
     case 3: return launch_m<T, kin::Fhn<T>>(aniso, a, s);
-    case 4: return launch_m<T, kin::Crn<T>>(aniso, a, s);
+    case 4:
+        if constexpr (std::is_same<T, float>::value)
+            if (a.tab) return launch_m<float, kin::CrnTab>(aniso, a, s);
+        return launch_m<T, kin::Crn<T>>(aniso, a, s);
     default: return hipErrorInvalidValue;
     }
 }
