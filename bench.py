@@ -243,6 +243,80 @@ def tabulated_line(stream, dv, steps, warmup):
             "ms_per_step": sec / steps * 1e3}
 
 
+# Algorithmic HBM bytes per voxel update of the FP32 FK4 ensemble step: u read +
+# written (8), three gates read + written (24), recorder status byte (1).
+ENS_BYTES_PER_VOXEL = 4 * 2 + 3 * 4 * 2 + 1
+
+
+def ensemble_workload(stream):
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.FK4_ENSEMBLE
+    w = WL.fk4_ensemble(n=c["n"], side_lo=c["side_lo"], side_hi=c["side_hi"], seed=c["seed"],
+                        h=c["h"], Dpar=c["Dpar"], aniso=c["aniso"], spread=c["spread"],
+                        s1_amp=c["s1_amp"], s1_ms=c["s1_ms"], apd_est_ms=c["apd_est_ms"],
+                        cv_est_mm_ms=c["cv_est_mm_ms"])
+    e = B.Ensemble(w["nx"], w["ny"], c["h"], w["Dpar"], w["Dperp"], w["angle"], B.BBX_MODEL_FK4,
+                   w["params"], c["dt"], B.BBX_FP32, stream)
+    for i in range(len(w["nx"])):
+        n = int(w["nx"][i]) * int(w["ny"][i])
+        for v, val in enumerate(WL.FK4_INITIAL):
+            e.set(i, v, np.full(n, val))
+    for (i, x0, x1, y0, y1, amp, t0, dur) in w["stims"]:
+        e.stimulus(i, x0, x1, y0, y1, amp, t0, dur)
+    e.record(c["theta"])
+    return e, w, c
+
+
+def ensemble_line(steps=None, chunk=1000):
+    """f1: 96 uneven 2D FK4 tissues advanced together, the whole 20,000-step (1 s) protocol
+    replayed from a captured HIP graph of `chunk` steps, tile shape autotuned; the direct
+    launch mode is timed over the first steps for comparison."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    s = torch.cuda.Stream()
+    e, w, c = ensemble_workload(s)
+    steps = steps or c["steps"]
+    best, times = e.tune(20)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    # direct launches: 200 steps from a fresh copy of the protocol start
+    d, _, _ = ensemble_workload(s)
+    d.variant(best)
+    d.step(20)
+    torch.cuda.synchronize()
+    ev[0].record(s)
+    d.step(200)
+    ev[1].record(s)
+    torch.cuda.synchronize()
+    direct_ms = ev[0].elapsed_time(ev[1]) / 200
+    d.close()
+    e.graph(chunk)
+    torch.cuda.synchronize()
+    ev[2].record(s)
+    e.step(steps)
+    ev[3].record(s)
+    torch.cuda.synchronize()
+    sec = ev[2].elapsed_time(ev[3]) / 1e3
+    if e.read(B.BBX_READ_NAN_FLAG, 0)[0]:
+        raise RuntimeError("non-finite state in the ensemble run")
+    activated = sum(int(np.isfinite(e.read(B.BBX_READ_ACT_TIME, i)).sum()) for i in range(len(w["nx"])))
+    nvox = e.nvox
+    per = sec / steps
+    gbs = ENS_BYTES_PER_VOXEL * nvox / per / 1e9
+    names = ["64x4 LDS", "32x8 LDS", "16x16 LDS", "64x4 direct"]
+    e.close()
+    return {"workload": f"{len(w['nx'])} 2D FK4 tissues, sides {int(w['nx'].min())}-{int(w['nx'].max())} "
+                        f"({nvox} voxels), per-tissue D/angle/time constants, S1-S2, "
+                        f"{steps} steps x {c['dt']} ms, FP32, graph chunk {chunk}",
+            "value": nvox * steps / sec, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
+            "total_s": sec, "tile": names[best],
+            "tune_ms_per_20_steps": {names[i]: round(float(times[i]), 3) for i in range(len(names))},
+            "direct_launch_ms_per_step": direct_ms, "graph_speedup": direct_ms / (per * 1e3),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": ENS_BYTES_PER_VOXEL},
+            "activated_voxels": activated}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -255,7 +329,9 @@ def main():
                     help="simulated time of the surrogate comparison runs (ms)")
     ap.add_argument("--tab", type=float, default=0.05,
                     help="table spacing (mV) of the tabulated CRN comparison line (0: skip)")
-    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil"], default=None,
+    ap.add_argument("--ens-steps", type=int, default=0,
+                    help="steps of the ensemble line (0: the full 20,000-step protocol)")
+    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "ensemble"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -270,7 +346,12 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.profile:
-        if args.profile in ("crn", "crn_tab"):
+        if args.profile == "ensemble":
+            e, _, _ = ensemble_workload(stream)
+            e.variant(B.BBX_ENS_TILE_64x4)
+            e.step(args.warmup + args.steps)
+            e.close()
+        elif args.profile in ("crn", "crn_tab"):
             grid, _ = crn_workload(B.BBX_FP32, stream,
                                    tab_dv=args.tab if args.profile == "crn_tab" else 0.0)
             grid.nan_check(0)
@@ -321,6 +402,7 @@ def main():
             out["tabulated"] = tabulated_line(stream, args.tab, args.steps, args.warmup)
             out["tabulated"]["speedup_vs_plain"] = round(ms_per_step / out["tabulated"]["ms_per_step"], 3)
         out["stencil_roofline"] = stencil_roofline(stream)
+        out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
         out["surrogate"] = surrogate_line(stream, t_ms=args.sur_ms)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -74,13 +74,19 @@ enum { BBX_SCHEME_ADDITIVE = 0, BBX_SCHEME_SPLIT = 1 };
  *  CRN     (21 vars)              Courtemanche-Ramirez-Nattel 1998 atrial model, no
  *                                  parameters; state order V, Na_i, K_i, Ca_i, Ca_up, Ca_rel,
  *                                  m, h, j, oa, oi, ua, ui, xr, xs, d, f, fCa, u, v, w;
- *                                  the 15 gates use Rush-Larsen, the rest forward Euler. */
+ *                                  the 15 gates use Rush-Larsen, the rest forward Euler;
+ *  FK4     (4 vars: u, v, w, s)   params {tau_fi, tau_so1, tau_si, tau_w+} (epicardial
+ *                                  0.11, 30.0181, 1.8875, 200 ms): the four-variable
+ *                                  minimal model of the Fenton-Karma family (Bueno-Orovio,
+ *                                  Cherry & Fenton 2008, epicardial set), u dimensionless;
+ *                                  v, w, s use Rush-Larsen, u forward Euler. */
 enum {
     BBX_MODEL_NONE = 0,
     BBX_MODEL_BARKLEY = 1,
     BBX_MODEL_ZFK = 2,
     BBX_MODEL_FHN = 3,
-    BBX_MODEL_CRN = 4
+    BBX_MODEL_CRN = 4,
+    BBX_MODEL_FK4 = 5
 };
 
 /* What bbx_readout returns. */
@@ -282,6 +288,103 @@ void bbx_grid_destroy(bbx_grid *g);
 
 /* Message of the calling thread's last error ("" if none). */
 const char *bbx_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Batched ensemble: many independent 2D rectangular tissues advanced together
+ * by one launch per step (the same explicit scheme as a grid: the anisotropic
+ * no-flux 9-point stencil of "Monodomain diffusion and boundary conditions"
+ * with a tissue-uniform tensor, fused with the kinetics of "Kinetics solvers",
+ * additive coupling, rectangular stimuli, activation/APD90 recording).  Each
+ * tissue has its own size, diffusion coefficients, fibre angle and model
+ * parameters; the model and dt are common.  All tissues live in one set of
+ * device arrays, tissue after tissue, each x-fastest; a step launches one
+ * workgroup per (tissue, tile) of a tile shape chosen by bbx_ensemble_tune.
+ * Steps are launched either directly or by replaying a captured HIP graph of
+ * a fixed number of steps (bbx_ensemble_graph_set).  Conventions as above;
+ * an ensemble is not thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct bbx_ensemble bbx_ensemble;
+
+/* Tile variants of the ensemble step (bbx_ensemble_variant_set / _tune):
+ * LDS-staged tiles of 64x4, 32x8 or 16x16 voxels, or 64x4 tiles that read
+ * neighbours straight from memory. */
+enum { BBX_ENS_TILE_64x4 = 0, BBX_ENS_TILE_32x8 = 1, BBX_ENS_TILE_16x16 = 2,
+       BBX_ENS_DIRECT_64x4 = 3, BBX_ENS_NVARIANT = 4 };
+
+/* Info queries for bbx_ensemble_info. */
+enum { BBX_ENS_INFO_VOXELS = 0, BBX_ENS_INFO_TILES = 1, BBX_ENS_INFO_VARIANT = 2,
+       BBX_ENS_INFO_DEVICE_BYTES = 3, BBX_ENS_INFO_GRAPH_CHUNK = 4, BBX_ENS_INFO_NVAR = 5 };
+
+/*
+ * Create an ensemble of ntissue >= 1 tissues.  Tissue i is an nx[i] x ny[i]
+ * rectangle of tissue (every voxel active; no-flux at its edges) with grid
+ * step h (mm), tensor D = Dperp[i] I + (Dpar[i] - Dperp[i]) f f^T (eq (sigma))
+ * for the in-plane unit fibre f = (cos angle[i], sin angle[i]) (radians),
+ * kinetics `model` (BBX_MODEL_NONE, _BARKLEY, _ZFK, _FHN or _FK4) with
+ * parameters params[i*nparams .. i*nparams + nparams-1] (nparams = the model's
+ * count), time step dt (ms) and precision BBX_FP32/BBX_FP64.  Every state
+ * variable starts at 0.  hip_stream: the stream all work is enqueued on; NULL
+ * makes the ensemble create (and own) a stream of its own, since graph capture
+ * needs a non-null stream.  Errors: BBX_EINVAL (sizes < 1, more than 2^31
+ * voxels in total, non-finite or negative coefficients, wrong nparams),
+ * BBX_ENOTSUP (model CRN), BBX_EUNSTABLE (dt above the Gershgorin bound of
+ * some tissue), BBX_ENOMEM / BBX_EDEVICE. */
+int bbx_ensemble_create(int ntissue, const int *nx, const int *ny, double h,
+                        const double *Dpar, const double *Dperp, const double *angle,
+                        int model, const double *params, int nparams, double dt,
+                        int precision, void *hip_stream, bbx_ensemble **out);
+
+/* Set state variable `var` of tissue `tissue` from values[nx*ny] (x fastest).
+ * Errors: BBX_EINVAL (index out of range, NULL values). */
+int bbx_ensemble_state_set(bbx_ensemble *e, int tissue, int var, const double *values);
+
+/* Add a stimulus to tissue `tissue` over the voxel rectangle x0 <= x < x1,
+ * y0 <= y < y1: amplitude added to du/dt while on, windows as in
+ * bbx_stimulus_add (whole steps, round half away from zero; period 0 = once;
+ * count 0 = unlimited).  At most 8 stimuli per tissue.  Errors: BBX_EINVAL. */
+int bbx_ensemble_stimulus_add(bbx_ensemble *e, int tissue, int x0, int x1, int y0, int y1,
+                              double amplitude, double t_start, double duration,
+                              double period, int count);
+
+/* Start activation / APD90 recording at threshold theta on every tissue (as
+ * bbx_recording_set; V_rest = each voxel's value now). */
+int bbx_ensemble_recording_set(bbx_ensemble *e, double theta);
+
+/* Launch mode of bbx_ensemble_step: chunk = 0 launches every step directly;
+ * chunk = K > 0 (even, <= 4096) captures K steps into a HIP graph on first use
+ * and replays it, launching any remainder directly.  Results are bitwise the
+ * same either way.  The graph is recaptured after any change to the ensemble.
+ * Errors: BBX_EINVAL. */
+int bbx_ensemble_graph_set(bbx_ensemble *e, int chunk);
+
+/* Select a tile variant (BBX_ENS_TILE_* / BBX_ENS_DIRECT_*).  All variants
+ * compute bitwise-identical results. */
+int bbx_ensemble_variant_set(bbx_ensemble *e, int variant);
+
+/* Autotune: time `steps` steps of every variant on a scratch copy of the
+ * current state (the ensemble's own state and clock are untouched), select
+ * the fastest and return it in *variant (may be NULL); times_ms[4] (may be
+ * NULL) receives each variant's time.  Synchronises the stream. */
+int bbx_ensemble_tune(bbx_ensemble *e, int steps, int *variant, double *times_ms);
+
+/* Advance every tissue by nsteps >= 0 steps (asynchronous). */
+int bbx_ensemble_step(bbx_ensemble *e, int64_t nsteps);
+
+/* Copy a result of tissue `tissue` to host memory out[count]: BBX_READ_VAR
+ * (var; nx*ny doubles), BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX (nx*ny
+ * doubles, NaN where not reached), BBX_READ_STATUS (nx*ny bytes),
+ * BBX_READ_NAN_FLAG (int32[1], over the whole ensemble), BBX_READ_STEP
+ * (int64[1]).  count is the number of elements of out; it must be at least
+ * what the request returns.  Synchronises the stream.  Errors: BBX_EINVAL,
+ * BBX_ESTATE (recording results before bbx_ensemble_recording_set). */
+int bbx_ensemble_readout(bbx_ensemble *e, int what, int tissue, int var, void *out, size_t count);
+
+/* Integer facts about an ensemble (BBX_ENS_INFO_*). */
+int bbx_ensemble_info(const bbx_ensemble *e, int what, int64_t *out);
+
+/* Free the ensemble, its graph, its device memory and any stream it created
+ * (synchronises its stream). */
+void bbx_ensemble_destroy(bbx_ensemble *e);
 
 #ifdef __cplusplus
 }

@@ -25,6 +25,10 @@
  *   - Courtemanche-Ramirez-Nattel 1998 cell model: transcribed from the
  *     original model publication (not part of the paper); pinned only loosely
  *     by that publication's resting state and action-potential shape.
+ *   - four-variable Fenton-Karma-type minimal model (Bueno-Orovio, Cherry &
+ *     Fenton 2008, epicardial set): transcribed from that publication; pinned
+ *     by its exact resting state, the closed-form subthreshold relaxation and
+ *     loosely by the shape of its action potential.
  */
 #include <math.h>
 #include <stdint.h>
@@ -34,7 +38,7 @@
 #include <omp.h>
 #endif
 
-enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4 };
+enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4, M_FK4 = 5 };
 enum { S_ADDITIVE = 0, S_SPLIT = 1 };
 
 #define NVAR_MAX 32
@@ -188,6 +192,7 @@ int orc_nvar(int model)
     case M_ZFK: return 1;
     case M_FHN: return 2;
     case M_CRN: return 21;
+    case M_FK4: return 4;
     default: return -1;
     }
 }
@@ -200,6 +205,7 @@ int orc_nparams(int model)
     case M_ZFK: return 1;
     case M_FHN: return 3;
     case M_CRN: return 0;
+    case M_FK4: return 4;
     default: return -1;
     }
 }
@@ -208,6 +214,7 @@ int orc_nparams(int model)
 static int is_gate(int model, int i)
 {
     if (model == M_CRN) return i >= 6;
+    if (model == M_FK4) return i >= 1;
     return 0;
 }
 
@@ -376,6 +383,50 @@ static void crn_rates(const double *y, double *rate, double *inf, double *tau)
     inf[20] = 1.0 - 1.0 / (1.0 + exp(-(V - 40.0) / 17.0));
 }
 
+/* Four-variable minimal ventricular model of Bueno-Orovio, Cherry & Fenton
+ * (J Theor Biol 2008), the "4-variable Fenton-Karma" family member cited with
+ * the Fenton-Karma model in "Cell models"; transcribed from that publication,
+ * epicardial parameter set.  State u (dimensionless), v, w, s; time in ms.
+ * Step function H(x) = 1 for x > 0, else 0.  p = (tau_fi, tau_so1, tau_si,
+ * tau_w+) are the per-tissue parameters (epicardial: 0.11, 30.0181, 1.8875,
+ * 200); every other constant is the epicardial value.  v, w and s relax
+ * linearly towards u-dependent steady states and are advanced by Rush-Larsen. */
+static void fk4_rates(const double *p, const double *y, double *rate, double *inf, double *tau)
+{
+    const double tfi = p[0], tso1 = p[1], tsi = p[2], twp = p[3];
+    const double uo = 0.0, uu = 1.55, thv = 0.3, thw = 0.13, thvm = 0.006, tho = 0.006;
+    const double tv1m = 60.0, tv2m = 1150.0, tvp = 1.4506;
+    const double tw1m = 60.0, tw2m = 15.0, kwm = 65.0, uwm = 0.03;
+    const double to1 = 400.0, to2 = 6.0, tso2 = 0.9957, kso = 2.0458, uso = 0.65;
+    const double ts1 = 2.7342, ts2 = 16.0, ks = 2.0994, us = 0.9087;
+    const double twinf = 0.07, winf_star = 0.94;
+    double u = y[0], v = y[1], w = y[2], s = y[3];
+    int Hv = u > thv, Hw = u > thw, Hvm = u > thvm, Ho = u > tho;
+
+    double tvm = Hvm ? tv2m : tv1m;
+    double twm = tw1m + (tw2m - tw1m) * (1.0 + tanh(kwm * (u - uwm))) / 2.0;
+    double tso = tso1 + (tso2 - tso1) * (1.0 + tanh(kso * (u - uso))) / 2.0;
+    double ts = Hw ? ts2 : ts1;
+    double to = Ho ? to2 : to1;
+    double vinf = u < thvm ? 1.0 : 0.0;
+    double winf = Ho ? winf_star : 1.0 - u / twinf;
+
+    double Jfi = Hv ? -v * (u - thv) * (uu - u) / tfi : 0.0;
+    double Jso = Hw ? 1.0 / tso : (u - uo) / to;
+    double Jsi = Hw ? -w * s / tsi : 0.0;
+    rate[0] = -(Jfi + Jso + Jsi);
+
+    /* v: towards v_inf with tau_v- below theta_v, towards 0 with tau_v+ above */
+    inf[1] = Hv ? 0.0 : vinf;
+    tau[1] = Hv ? tvp : tvm;
+    /* w: towards w_inf with tau_w- below theta_w, towards 0 with tau_w+ above */
+    inf[2] = Hw ? 0.0 : winf;
+    tau[2] = Hw ? twp : twm;
+    /* s: towards (1 + tanh(k_s (u - u_s)))/2 with tau_s */
+    inf[3] = (1.0 + tanh(ks * (u - us))) / 2.0;
+    tau[3] = ts;
+}
+
 static void model_eval(int model, const double *p, const double *y,
                        double *rate, double *inf, double *tau)
 {
@@ -385,6 +436,7 @@ static void model_eval(int model, const double *p, const double *y,
     case M_ZFK: zfk_rates(p, y, rate); break;
     case M_FHN: fhn_rates(p, y, rate); break;
     case M_CRN: crn_rates(y, rate, inf, tau); break;
+    case M_FK4: fk4_rates(p, y, rate, inf, tau); break;
     }
 }
 

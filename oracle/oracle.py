@@ -21,7 +21,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bbx_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-MODEL_NONE, MODEL_BARKLEY, MODEL_ZFK, MODEL_FHN, MODEL_CRN = 0, 1, 2, 3, 4
+MODEL_NONE, MODEL_BARKLEY, MODEL_ZFK, MODEL_FHN, MODEL_CRN, MODEL_FK4 = 0, 1, 2, 3, 4, 5
 SCHEME_ADDITIVE, SCHEME_SPLIT = 0, 1
 
 

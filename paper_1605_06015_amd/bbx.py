@@ -21,11 +21,15 @@ BBX_OK, BBX_EINVAL, BBX_ENOMEM, BBX_EDEVICE, BBX_ESTATE, BBX_EUNSTABLE, BBX_ENUM
     0, -1, -2, -3, -4, -5, -6, -7
 BBX_FP32, BBX_FP64 = 0, 1
 BBX_SCHEME_ADDITIVE, BBX_SCHEME_SPLIT = 0, 1
-BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN = 0, 1, 2, 3, 4
+BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, BBX_MODEL_FK4 = \
+    0, 1, 2, 3, 4, 5
 (BBX_READ_VAR, BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX, BBX_READ_STATUS,
  BBX_READ_REDUCE_MAX, BBX_READ_REDUCE_SUM, BBX_READ_NAN_FLAG, BBX_READ_STEP,
  BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT) = range(11)
 BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
+BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_NVARIANT = range(5)
+(BBX_ENS_INFO_VOXELS, BBX_ENS_INFO_TILES, BBX_ENS_INFO_VARIANT, BBX_ENS_INFO_DEVICE_BYTES,
+ BBX_ENS_INFO_GRAPH_CHUNK, BBX_ENS_INFO_NVAR) = range(6)
 
 # Every symbol the header declares, with (restype, argtypes).
 _P, _I, _D, _I64, _SZ = C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_size_t
@@ -57,6 +61,17 @@ SIGNATURES = {
     "bbx_sample_states": (_I, [_P, _I64, C.c_uint64, _P]),
     "bbx_ionic_map": (_I, [_P, _P, _I64, _P]),
     "bbx_surrogate_set": (_I, [_P, _P, _P, _P, C.c_float]),
+    "bbx_ensemble_create": (_I, [_I, _P, _P, _D, _P, _P, _P, _I, _P, _I, _D, _I, _P, C.POINTER(_P)]),
+    "bbx_ensemble_state_set": (_I, [_P, _I, _I, _P]),
+    "bbx_ensemble_stimulus_add": (_I, [_P, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I]),
+    "bbx_ensemble_recording_set": (_I, [_P, _D]),
+    "bbx_ensemble_graph_set": (_I, [_P, _I]),
+    "bbx_ensemble_variant_set": (_I, [_P, _I]),
+    "bbx_ensemble_tune": (_I, [_P, _I, C.POINTER(_I), _P]),
+    "bbx_ensemble_step": (_I, [_P, _I64]),
+    "bbx_ensemble_readout": (_I, [_P, _I, _I, _I, _P, _SZ]),
+    "bbx_ensemble_info": (_I, [_P, _I, C.POINTER(_I64)]),
+    "bbx_ensemble_destroy": (None, [_P]),
 }
 
 
@@ -406,3 +421,140 @@ class Mlp:
         hist = np.empty(iters, np.float32)
         bbx_mlp_train(self.handle, S, S1, S.shape[0], batch, iters, lr, seed, hist)
         return hist
+
+
+# ---------------------------------------------------------------- batched ensemble
+def bbx_ensemble_create(nx, ny, h, Dpar, Dperp, angle, model, params, dt, precision,
+                        hip_stream=None):
+    """params: (ntissue, nparams) array (nparams = the model's count; may be 0 columns)."""
+    nx = np.ascontiguousarray(nx, dtype=np.int32)
+    ny = np.ascontiguousarray(ny, dtype=np.int32)
+    n = nx.size
+    if ny.size != n:
+        raise ValueError("nx and ny differ in length")
+    Dp = np.ascontiguousarray(np.broadcast_to(np.asarray(Dpar, np.float64), (n,)))
+    Dq = np.ascontiguousarray(np.broadcast_to(np.asarray(Dperp, np.float64), (n,)))
+    an = np.ascontiguousarray(np.broadcast_to(np.asarray(angle, np.float64), (n,)))
+    P = np.ascontiguousarray(np.asarray(params, np.float64).reshape(n, -1))
+    out = C.c_void_p()
+    _check(_lib.bbx_ensemble_create(n, _ptr(nx), _ptr(ny), float(h), _ptr(Dp), _ptr(Dq), _ptr(an),
+                                    int(model), _ptr(P) if P.size else None, P.shape[1], float(dt),
+                                    int(precision), _stream_handle(hip_stream), C.byref(out)))
+    return out
+
+
+def bbx_ensemble_state_set(e, tissue, var, values):
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    _check(_lib.bbx_ensemble_state_set(e, int(tissue), int(var), _ptr(v)))
+
+
+def bbx_ensemble_stimulus_add(e, tissue, x0, x1, y0, y1, amplitude, t_start, duration,
+                              period=0.0, count=1):
+    _check(_lib.bbx_ensemble_stimulus_add(e, int(tissue), int(x0), int(x1), int(y0), int(y1),
+                                          float(amplitude), float(t_start), float(duration),
+                                          float(period), int(count)))
+
+
+def bbx_ensemble_recording_set(e, theta):
+    _check(_lib.bbx_ensemble_recording_set(e, float(theta)))
+
+
+def bbx_ensemble_graph_set(e, chunk):
+    _check(_lib.bbx_ensemble_graph_set(e, int(chunk)))
+
+
+def bbx_ensemble_variant_set(e, variant):
+    _check(_lib.bbx_ensemble_variant_set(e, int(variant)))
+
+
+def bbx_ensemble_tune(e, steps):
+    best = C.c_int()
+    times = np.zeros(BBX_ENS_NVARIANT, np.float64)
+    _check(_lib.bbx_ensemble_tune(e, int(steps), C.byref(best), _ptr(times)))
+    return best.value, times
+
+
+def bbx_ensemble_step(e, nsteps):
+    _check(_lib.bbx_ensemble_step(e, int(nsteps)))
+
+
+def bbx_ensemble_readout(e, what, tissue, var, out):
+    _check(_lib.bbx_ensemble_readout(e, int(what), int(tissue), int(var), _ptr(out), out.size))
+    return out
+
+
+def bbx_ensemble_info(e, what) -> int:
+    v = C.c_int64()
+    _check(_lib.bbx_ensemble_info(e, int(what), C.byref(v)))
+    return v.value
+
+
+def bbx_ensemble_destroy(e):
+    _lib.bbx_ensemble_destroy(e)
+
+
+class Ensemble:
+    """Owning wrapper of a batched ensemble of 2D rectangular tissues."""
+
+    def __init__(self, nx, ny, h, Dpar, Dperp, angle, model, params, dt, precision=BBX_FP32,
+                 stream=None):
+        self.nx = np.asarray(nx, np.int32).copy()
+        self.ny = np.asarray(ny, np.int32).copy()
+        self.handle = bbx_ensemble_create(self.nx, self.ny, h, Dpar, Dperp, angle, model, params,
+                                          dt, precision, stream)
+        self.nvar = bbx_ensemble_info(self.handle, BBX_ENS_INFO_NVAR)
+        self.nvox = bbx_ensemble_info(self.handle, BBX_ENS_INFO_VOXELS)
+
+    def close(self):
+        if self.handle:
+            bbx_ensemble_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set(self, tissue, var, values):
+        bbx_ensemble_state_set(self.handle, tissue, var, values)
+
+    def stimulus(self, tissue, x0, x1, y0, y1, amp, t0, dur, period=0.0, count=1):
+        bbx_ensemble_stimulus_add(self.handle, tissue, x0, x1, y0, y1, amp, t0, dur, period, count)
+
+    def record(self, theta):
+        bbx_ensemble_recording_set(self.handle, theta)
+
+    def graph(self, chunk):
+        bbx_ensemble_graph_set(self.handle, chunk)
+
+    def variant(self, v=None):
+        if v is not None:
+            bbx_ensemble_variant_set(self.handle, v)
+        return bbx_ensemble_info(self.handle, BBX_ENS_INFO_VARIANT)
+
+    def tune(self, steps=20):
+        return bbx_ensemble_tune(self.handle, steps)
+
+    def step(self, n=1):
+        bbx_ensemble_step(self.handle, n)
+
+    def get(self, tissue, var=0):
+        """State variable `var` of tissue `tissue` as float64 (ny, nx)."""
+        out = np.empty(int(self.nx[tissue]) * int(self.ny[tissue]), np.float64)
+        bbx_ensemble_readout(self.handle, BBX_READ_VAR, tissue, var, out)
+        return out.reshape(int(self.ny[tissue]), int(self.nx[tissue]))
+
+    def read(self, what, tissue):
+        if what == BBX_READ_STEP:
+            out = np.empty(1, np.int64)
+        elif what == BBX_READ_NAN_FLAG:
+            out = np.empty(1, np.int32)
+        elif what == BBX_READ_STATUS:
+            out = np.empty(int(self.nx[tissue]) * int(self.ny[tissue]), np.uint8)
+        else:
+            out = np.empty(int(self.nx[tissue]) * int(self.ny[tissue]), np.float64)
+        bbx_ensemble_readout(self.handle, what, tissue, 0, out)
+        if out.size > 1:
+            return out.reshape(int(self.ny[tissue]), int(self.nx[tissue]))
+        return out

@@ -51,6 +51,7 @@ int model_nvar(int m)
     case BBX_MODEL_ZFK: return 1;
     case BBX_MODEL_FHN: return 2;
     case BBX_MODEL_CRN: return 21;
+    case BBX_MODEL_FK4: return 4;
     default: return -1;
     }
 }
@@ -63,6 +64,7 @@ int model_nparams(int m)
     case BBX_MODEL_ZFK: return 1;
     case BBX_MODEL_FHN: return 3;
     case BBX_MODEL_CRN: return 0;
+    case BBX_MODEL_FK4: return 4;
     default: return -1;
     }
 }
@@ -643,6 +645,15 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
 }  // namespace
 
 // ============================================================================ C ABI
+
+// Error state shared with the other entry-point files of the library.
+int bbx::api_error(int code, const char *msg)
+{
+    g_err = msg;
+    return code;
+}
+
+void bbx::api_clear_error() { g_err.clear(); }
 
 extern "C" {
 

@@ -67,6 +67,10 @@ struct StepArgs {
 constexpr int kTileX = 64;
 constexpr int kTileY = kBlock / kTileX;
 
+// The calling thread's last-error message, shared by all entry points.
+int api_error(int code, const char *msg);
+void api_clear_error();
+
 // Launchers (step_kernels.hip).  Return hipSuccess or the launch error.
 template <typename T>
 hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s);

@@ -68,6 +68,11 @@ __device__ __forceinline__ T rl_ab(T y, T a, T b, T dt)
     return rl_rate(y, a * rcp(k), k, dt);
 }
 
+// tanh: the library routine in FP64; in FP32 1 - 2/(e^{2x} + 1) on the hardware
+// exp/rcp units (tends to +-1 correctly as e^{2x} overflows or underflows).
+__device__ __forceinline__ double th(double x) { return tanh(x); }
+__device__ __forceinline__ float th(float x) { return 1.0f - 2.0f * rcp(ex(2.0f * x) + 1.0f); }
+
 // Logistic 1 / (1 + e^x).
 template <typename T>
 __device__ __forceinline__ T lgs(T x)
@@ -117,6 +122,47 @@ struct Fhn {
         T v = g[0];
         g[0] = v + dt * p[0] * (u + p[1] - p[2] * v);
         return (u - u * u * u * T(1.0 / 3.0) - v) / p[0];
+    }
+};
+
+// ---------------------------------------------------------------- four-variable minimal model
+// Bueno-Orovio, Cherry & Fenton (2008), the four-variable member of the
+// Fenton-Karma family cited in "Cell models"; transcribed from that
+// publication, epicardial parameter set.  State u, v, w, s (u dimensionless,
+// time in ms); step function H(x) = [x > 0].
+//   du/dt = -(J_fi + J_so + J_si)
+//   J_fi = -v H(u - th_v)(u - th_v)(u_u - u)/tau_fi
+//   J_so = (u - u_o)(1 - H(u - th_w))/tau_o + H(u - th_w)/tau_so
+//   J_si = -H(u - th_w) w s / tau_si
+// v, w, s relax linearly towards u-dependent steady states (Rush-Larsen):
+//   v -> (u < th_v- ? 1 : 0) with tau_v- below th_v, -> 0 with tau_v+ above;
+//   w -> w_inf with tau_w- below th_w, -> 0 with tau_w+ above;
+//   s -> (1 + tanh(k_s (u - u_s)))/2 with tau_s.
+// prm = {tau_fi, tau_so1, tau_si, tau_w+} (epicardial 0.11, 30.0181, 1.8875, 200).
+template <typename T>
+struct Fk4 {
+    static constexpr int NV = 4, GATE0 = 1;
+    __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
+    {
+        const T thv = T(0.3), thw = T(0.13), thvm = T(0.006), tho = T(0.006);
+        const bool Hv = u > thv, Hw = u > thw, Hvm = u > thvm, Ho = u > tho;
+        const T v = g[0], w = g[1], s = g[2];
+        // currents
+        const T tso = p[1] + (T(0.9957) - p[1]) * (T(1) + th(T(2.0458) * (u - T(0.65)))) * T(0.5);
+        const T to = Ho ? T(6) : T(400);
+        const T Jfi = Hv ? dv(-v * (u - thv) * (T(1.55) - u), p[0]) : T(0);
+        const T Jso = Hw ? rcp(tso) : dv(u, to);
+        const T Jsi = Hw ? dv(-w * s, p[2]) : T(0);
+        // gates
+        const T tvm = Hvm ? T(1150) : T(60);
+        const T vinf = u < thvm ? T(1) : T(0);
+        g[0] = Hv ? rl_rate(v, T(0), rcp(T(1.4506)), dt) : rl_rate(v, vinf, rcp(tvm), dt);
+        const T twm = T(60) + (T(15) - T(60)) * (T(1) + th(T(65) * (u - T(0.03)))) * T(0.5);
+        const T winf = Ho ? T(0.94) : T(1) - dv(u, T(0.07));
+        g[1] = Hw ? rl_rate(w, T(0), rcp(p[3]), dt) : rl_rate(w, winf, rcp(twm), dt);
+        const T sinf = (T(1) + th(T(2.0994) * (u - T(0.9087)))) * T(0.5);
+        g[2] = rl_rate(s, sinf, rcp(Hw ? T(16) : T(2.7342)), dt);
+        return -(Jfi + Jso + Jsi);
     }
 };
 

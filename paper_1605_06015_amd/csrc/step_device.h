@@ -47,16 +47,16 @@ __device__ __forceinline__ T laplacian(const StepArgs<T> &a, const T *__restrict
 }
 
 // Activation / peak / APD90 recorder (per-voxel threshold-crossing test on the
-// pair V_n -> V_{n+1}).
-template <typename T>
-__device__ __forceinline__ void record_voxel(const StepArgs<T> &a, int t, T Vp, T Vn)
+// pair V_n -> V_{n+1} at time tn = n dt).  A: any argument block with the
+// recorder fields (status, theta, dt, at, vmax, vrep, apd).
+template <typename T, class A, typename I>
+__device__ __forceinline__ void record_event(const A &a, I t, T tn, T Vp, T Vn)
 {
-    if (!a.rec) return;
     uint8_t s0 = a.status[t];
     if (s0 == 3) return;
     uint8_t s = s0;
     if (s == 0 && Vp < a.theta && Vn >= a.theta) {
-        a.at[t] = a.tn + a.dt * (a.theta - Vp) / (Vn - Vp);
+        a.at[t] = tn + a.dt * (a.theta - Vp) / (Vn - Vp);
         s = 1;
     }
     if (s == 1 && Vn < Vp) {
@@ -68,11 +68,18 @@ __device__ __forceinline__ void record_voxel(const StepArgs<T> &a, int t, T Vp, 
     if (s == 2) {
         const T vr = a.vrep[t];
         if (Vp >= vr && Vn < vr) {
-            a.apd[t] = a.tn + a.dt * (Vp - vr) / (Vp - Vn) - a.at[t];
+            a.apd[t] = tn + a.dt * (Vp - vr) / (Vp - Vn) - a.at[t];
             s = 3;
         }
     }
     if (s != s0) a.status[t] = s;
+}
+
+template <typename T>
+__device__ __forceinline__ void record_voxel(const StepArgs<T> &a, int t, T Vp, T Vn)
+{
+    if (!a.rec) return;
+    record_event(a, t, a.tn, Vp, Vn);
 }
 
 // Stimulus current of tissue voxel t at this step.

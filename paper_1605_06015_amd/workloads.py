@@ -169,3 +169,46 @@ def random_fibres(shape, seed):
     rng = np.random.default_rng(seed)
     f = rng.standard_normal(tuple(shape) + (3,))
     return f / np.linalg.norm(f, axis=-1, keepdims=True)
+
+
+# ---------------------------------------------------------------- batched 2D ensemble
+# Epicardial parameters (tau_fi, tau_so1, tau_si, tau_w+) of the four-variable
+# minimal model of the Fenton-Karma family (Bueno-Orovio, Cherry & Fenton 2008)
+# and its published resting state (u, v, w) = (0, 1, 1); s starts at 0.
+FK4_EPI = (0.11, 30.0181, 1.8875, 200.0)
+FK4_INITIAL = (0.0, 1.0, 1.0, 0.0)
+# Ensemble protocol: diffusion coefficient of the model publication
+# (1.171 cm^2/s = 0.1171 mm^2/ms) along fibres, 4:1 anisotropy, h = 0.25 mm,
+# dt = 0.05 ms, 20,000 steps (1 s).
+FK4_ENSEMBLE = dict(n=96, side_lo=64, side_hi=768, h=0.25, dt=0.05, Dpar=0.1171, aniso=4.0,
+                    spread=0.2, steps=20000, seed=4, s1_amp=1.0, s1_ms=2.0, theta=0.5,
+                    apd_est_ms=270.0, cv_est_mm_ms=0.6)
+
+
+def fk4_ensemble(n=96, side_lo=64, side_hi=768, seed=4, h=0.25, Dpar=0.1171, aniso=4.0,
+                 spread=0.2, s1_amp=1.0, s1_ms=2.0, apd_est_ms=270.0, cv_est_mm_ms=0.6):
+    """n square tissues with sides evenly spaced over [side_lo, side_hi] (rounded) in a
+    seeded shuffled order; per tissue D_par scaled by U(1 - spread, 1 + spread) with
+    D_perp = D_par / aniso, a fibre angle U(0, pi), and each model time constant scaled
+    by its own U(1 - spread, 1 + spread).  S1-S2 cross-field protocol: S1 on the
+    three leftmost columns at t = 0; S2 on the lower-left quadrant once the S1 wave
+    back is estimated to have passed the middle (t = apd_est + (side/2) h / cv_est),
+    which breaks the S2 front into a spiral where the tissue is large enough.
+    Returns dict(nx, ny, Dpar, Dperp, angle, params (n, 4), stims [(tissue, x0, x1,
+    y0, y1, amp, t0_ms, dur_ms)], h)."""
+    rng = np.random.default_rng(seed)
+    sides = np.rint(np.linspace(side_lo, side_hi, n)).astype(np.int32)
+    sides = sides[rng.permutation(n)]
+    dscale = rng.uniform(1 - spread, 1 + spread, n)
+    Dp = Dpar * dscale
+    Dq = Dp / aniso
+    angle = rng.uniform(0.0, np.pi, n)
+    params = np.array(FK4_EPI) * rng.uniform(1 - spread, 1 + spread, (n, 4))
+    stims = []
+    for i, s in enumerate(sides):
+        s = int(s)
+        stims.append((i, 0, 3, 0, s, s1_amp, 0.0, s1_ms))
+        t2 = apd_est_ms + 0.5 * s * h / cv_est_mm_ms
+        stims.append((i, 0, s // 2, 0, s // 2, s1_amp, float(np.round(t2, 1)), s1_ms))
+    return dict(nx=sides.copy(), ny=sides.copy(), Dpar=Dp, Dperp=Dq, angle=angle,
+                params=params, stims=stims, h=h)

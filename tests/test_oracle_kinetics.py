@@ -259,3 +259,71 @@ def test_threads_bitwise_equal_serial():
         s.step(30)
         outs.append(s.state.copy())
     assert np.array_equal(outs[0], outs[1])
+
+
+# ------------------------------------------------ four-variable minimal (Fenton-Karma type)
+FK4_EPI = [0.11, 30.0181, 1.8875, 200.0]
+
+
+def test_fk4_rest_is_a_fixed_point():
+    """u = 0, v = w = 1, s = s_inf(0): no current flows and every gate sits at its steady
+    state, so the step map leaves the cell exactly where it is."""
+    rate, inf, tau = O.model_eval(O.MODEL_FK4, FK4_EPI, np.array([0.0, 1.0, 1.0, 0.5]))
+    assert rate[0] == 0.0 and inf[1] == 1.0 and inf[2] == 1.0
+    assert 0.0 < inf[3] < 0.05
+    y0 = [0.0, 1.0, 1.0, inf[3]]
+    s = cell(O.MODEL_FK4, FK4_EPI, y0, 0.05)
+    s.step(2000)
+    np.testing.assert_allclose(s.state[:, 0, 0, 0], y0, rtol=0, atol=1e-15)
+
+
+def test_fk4_subthreshold_relaxation_closed_form():
+    """Below every threshold (0 < u < 0.006) the only current is u / tau_o1 (tau_o1 = 400 ms)
+    and v relaxes to 1 with tau_v1- = 60 ms: forward Euler gives u_n = u_0 (1 - dt/400)^n,
+    Rush-Larsen gives v_n = 1 + (v_0 - 1) e^{-n dt/60}, exactly."""
+    dt, u0, v0 = 0.05, 0.005, 0.6
+    s = cell(O.MODEL_FK4, FK4_EPI, [u0, v0, 0.8, 0.3], dt)
+    for n in (1, 10, 100, 1000):
+        s2 = cell(O.MODEL_FK4, FK4_EPI, [u0, v0, 0.8, 0.3], dt)
+        s2.step(n)
+        u, v = s2.state[0, 0, 0, 0], s2.state[1, 0, 0, 0]
+        assert abs(u - u0 * (1 - dt / 400.0) ** n) <= 1e-15
+        assert abs(v - (1 + (v0 - 1) * np.exp(-n * dt / 60.0))) <= 1e-13
+    # w relaxes towards w_inf = 1 - u/0.07 from below 1, s towards its sigmoid: both stay in [0, 1]
+    s.step(1000)
+    assert 0.8 < s.state[2, 0, 0, 0] < 1.0 and 0.0 < s.state[3, 0, 0, 0] < 0.3
+
+
+def test_fk4_action_potential_shape():
+    """1 ms suprathreshold stimulus from rest, epicardial set: a fast upstroke close to
+    u_u = 1.55, a spike-and-dome plateau and an APD90 near the model publication's
+    epicardial value (about 270 ms), then recovery towards rest."""
+    rate, inf, tau = O.model_eval(O.MODEL_FK4, FK4_EPI, np.zeros(4))
+    s = cell(O.MODEL_FK4, FK4_EPI, [0.0, 1.0, 1.0, inf[3]], 0.05, [O.Stimulus(ONE, 0.5, 0, 20)])
+    s.start_recording(0.5)
+    u = []
+    for _ in range(8000):
+        s.step(1)
+        u.append(s.state[0, 0, 0, 0])
+    u = np.array(u)
+    assert 1.4 < u.max() < 1.55
+    assert u.argmax() * 0.05 < 3.0
+    assert s.rec.status[0] == 3
+    assert 240.0 < s.rec.apd[0] < 310.0
+    assert 0.0 <= u[-1] < 0.01
+    # the fast gate v closes during the action potential and recovers after it
+    assert s.state[1, 0, 0, 0] > 0.5
+
+
+def test_fk4_tau_parameters_act():
+    """Shorter tau_so1 / tau_si shorten or lengthen the action potential the way the
+    currents they scale should: J_so = 1/tau_so is repolarising, J_si = -w s/tau_si depolarising."""
+    def apd(p):
+        rate, inf, tau = O.model_eval(O.MODEL_FK4, p, np.zeros(4))
+        s = cell(O.MODEL_FK4, p, [0.0, 1.0, 1.0, inf[3]], 0.05, [O.Stimulus(ONE, 0.5, 0, 20)])
+        s.start_recording(0.5)
+        s.step(8000)
+        return s.rec.apd[0]
+    base = apd(FK4_EPI)
+    assert apd([0.11, 30.0181 * 0.8, 1.8875, 200.0]) < base     # stronger repolarising current
+    assert apd([0.11, 30.0181, 1.8875 * 0.8, 200.0]) > base     # stronger depolarising current
