@@ -187,8 +187,7 @@ FK4_ENSEMBLE = dict(n=96, side_lo=64, side_hi=768, h=0.25, dt=0.05, Dpar=0.1171,
 
 def fk4_ensemble(n=96, side_lo=64, side_hi=768, seed=4, h=0.25, Dpar=0.1171, aniso=4.0,
                  spread=0.2, s1_amp=1.0, s1_ms=2.0, apd_est_ms=270.0, cv_est_mm_ms=0.6):
-    """n square tissues with sides evenly spaced over [side_lo, side_hi] (rounded) in a
-    seeded shuffled order; per tissue D_par scaled by U(1 - spread, 1 + spread) with
+    """n square tissues with sides drawn uniformly from [side_lo, side_hi] (seeded); per tissue D_par scaled by U(1 - spread, 1 + spread) with
     D_perp = D_par / aniso, a fibre angle U(0, pi), and each model time constant scaled
     by its own U(1 - spread, 1 + spread).  S1-S2 cross-field protocol: S1 on the
     three leftmost columns at t = 0; S2 on the lower-left quadrant once the S1 wave
@@ -197,8 +196,7 @@ def fk4_ensemble(n=96, side_lo=64, side_hi=768, seed=4, h=0.25, Dpar=0.1171, ani
     Returns dict(nx, ny, Dpar, Dperp, angle, params (n, 4), stims [(tissue, x0, x1,
     y0, y1, amp, t0_ms, dur_ms)], h)."""
     rng = np.random.default_rng(seed)
-    sides = np.rint(np.linspace(side_lo, side_hi, n)).astype(np.int32)
-    sides = sides[rng.permutation(n)]
+    sides = rng.integers(side_lo, side_hi + 1, n).astype(np.int32)
     dscale = rng.uniform(1 - spread, 1 + spread, n)
     Dp = Dpar * dscale
     Dq = Dp / aniso
