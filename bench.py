@@ -317,6 +317,56 @@ def ensemble_line(steps=None, chunk=1000):
             "activated_voxels": activated}
 
 
+# Algorithmic HBM bytes per tissue-voxel update of the fused TP06 step in FP32: 19
+# state values read + written, geometry (index, neighbour bits, fibre, face
+# coefficients: 32 B) and the recorder status byte.
+TP06_BYTES_PER_VOXEL = 19 * 4 * 2 + 32 + 1
+
+
+def tp06_workload(stream):
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.TP06_3D
+    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_radius"])
+    grid = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
+    grid.model(B.BBX_MODEL_TP06, [], c["dt"])
+    for v, val in enumerate(WL.TP06_INITIAL):
+        grid.fill(v, val)
+    grid.stimulus(g3["s1"], c["s1_amp"], 0.0, c["s1_ms"])
+    grid.stimulus(g3["s2"], c["s2_amp"], c["s2_t"], c["s2_ms"])
+    grid.record(c["theta"])
+    grid.nan_check(0)
+    return grid, g3["electrodes"], c
+
+
+def tp06_line(stream, steps=1000, warmup=100):
+    """f2: TP06 on the 512x512x384 biventricular-like double shell (25.2 M tissue voxels),
+    FP32, S1 at the apex; timed without and with the FP64 pseudo-ECG sampled every 1 ms
+    at eight electrodes."""
+    from paper_1605_06015_amd import bbx as B
+    grid, E, c = tp06_workload(stream)
+    nact = grid.nact
+    sec = time_steps(grid, stream, steps, warmup)
+    every = int(round(c["ecg_every_ms"] / c["dt"]))
+    grid.ecg(E, every=every, max_samples=100000)
+    sec_ecg = time_steps(grid, stream, steps, 0)
+    nsamp = int(grid.ecg_series().shape[0])
+    if grid.read(B.BBX_READ_NAN_FLAG)[0]:
+        raise RuntimeError("non-finite state in the TP06 run")
+    grid.close()
+    per = sec / steps
+    gbs = TP06_BYTES_PER_VOXEL * nact / per / 1e9
+    return {"workload": f"TP06 3D, 512x512x384 double shell, 25% active ({nact} tissue voxels), "
+                        "19-point anisotropic, transmural fibres +-60 deg, h 0.2 mm, dt 0.02 ms, FP32",
+            "value": nact * steps / sec, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
+            "steps": steps, "one_second_protocol_s_est": per * round(c["t_end"] / c["dt"]),
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": TP06_BYTES_PER_VOXEL},
+            "pseudo_ecg": {"electrodes": int(len(E)), "every_steps": every, "samples": nsamp,
+                           "ms_per_sample": (sec_ecg - sec) / max(nsamp, 1) * 1e3,
+                           "overhead_frac": (sec_ecg - sec) / sec}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -331,7 +381,8 @@ def main():
                     help="table spacing (mV) of the tabulated CRN comparison line (0: skip)")
     ap.add_argument("--ens-steps", type=int, default=0,
                     help="steps of the ensemble line (0: the full 20,000-step protocol)")
-    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "ensemble"], default=None,
+    ap.add_argument("--tp06-steps", type=int, default=1000, help="timed steps of the TP06 line")
+    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "ensemble", "tp06"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -346,7 +397,11 @@ def main():
     stream = torch.cuda.current_stream()
 
     if args.profile:
-        if args.profile == "ensemble":
+        if args.profile == "tp06":
+            grid, _, _ = tp06_workload(stream)
+            grid.step(args.warmup + args.steps)
+            grid.close()
+        elif args.profile == "ensemble":
             e, _, _ = ensemble_workload(stream)
             e.variant(B.BBX_ENS_TILE_64x4)
             e.step(args.warmup + args.steps)
@@ -403,6 +458,7 @@ def main():
             out["tabulated"]["speedup_vs_plain"] = round(ms_per_step / out["tabulated"]["ms_per_step"], 3)
         out["stencil_roofline"] = stencil_roofline(stream)
         out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
+        out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
         out["surrogate"] = surrogate_line(stream, t_ms=args.sur_ms)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()

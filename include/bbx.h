@@ -79,14 +79,19 @@ enum { BBX_SCHEME_ADDITIVE = 0, BBX_SCHEME_SPLIT = 1 };
  *                                  0.11, 30.0181, 1.8875, 200 ms): the four-variable
  *                                  minimal model of the Fenton-Karma family (Bueno-Orovio,
  *                                  Cherry & Fenton 2008, epicardial set), u dimensionless;
- *                                  v, w, s use Rush-Larsen, u forward Euler. */
+ *                                  v, w, s use Rush-Larsen, u forward Euler;
+ *  TP06    (19 vars)              ten Tusscher-Panfilov 2006 ventricular model, epicardial
+ *                                  cell, no parameters; state order V, K_i, Na_i, Ca_i,
+ *                                  Ca_ss, Ca_SR, Rbar, Xr1, Xr2, Xs, m, h, j, d, f, f2, fCass,
+ *                                  s, r; the 12 gates use Rush-Larsen, the rest forward Euler. */
 enum {
     BBX_MODEL_NONE = 0,
     BBX_MODEL_BARKLEY = 1,
     BBX_MODEL_ZFK = 2,
     BBX_MODEL_FHN = 3,
     BBX_MODEL_CRN = 4,
-    BBX_MODEL_FK4 = 5
+    BBX_MODEL_FK4 = 5,
+    BBX_MODEL_TP06 = 6
 };
 
 /* What bbx_readout returns. */
@@ -105,8 +110,12 @@ enum {
     BBX_READ_WEIGHTS = 9,     /* double[nact*27]: the effective stencil weights W^p_q of
                                  every tissue voxel p (increasing box order), q = (dx,dy,dz)
                                  at (dz+1)*9 + (dy+1)*3 + (dx+1), centre = -sum of others */
-    BBX_READ_FALLBACK_COUNT = 10  /* int64[1]: voxel updates that fell back from the
+    BBX_READ_FALLBACK_COUNT = 10, /* int64[1]: voxel updates that fell back from the
                                      surrogate to the plain kinetics since it was attached */
+    BBX_READ_ECG = 11,            /* double[nelec]: pseudo-ECG of the current V at each
+                                     electrode (bbx_ecg_set), computed now */
+    BBX_READ_ECG_SERIES = 12,     /* double[count*nelec]: the sampled pseudo-ECG, sample-major */
+    BBX_READ_ECG_COUNT = 13       /* int64[1]: samples stored so far */
 };
 
 /* Info queries for bbx_info. */
@@ -142,6 +151,11 @@ int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, dou
  * entries are read.  Stream-ordered, the host array is copied before return. */
 int bbx_state_set(bbx_grid *g, int var, const double *box_values);
 
+/* Set state variable `var` to `value` on every tissue voxel (void entries of V
+ * stay 0): the uniform initial condition of a large grid without a host array.
+ * Errors as bbx_state_set, plus BBX_EINVAL for a non-finite value. */
+int bbx_state_fill(bbx_grid *g, int var, double value);
+
 /* Add a stimulus current (the external current term of eq (monodomain)):
  * amplitude (pA/pF; positive depolarises) applied to tissue voxels where
  * region[idx] != 0, during steps n with round(t_start/dt) + c*round(period/dt)
@@ -167,6 +181,23 @@ int bbx_recording_set(bbx_grid *g, double theta);
  * check on, bbx_step synchronises the stream at its end and returns
  * BBX_ENUMERIC if a value was not finite. */
 int bbx_nan_check_set(bbx_grid *g, int64_t every);
+
+/* Pseudo-ECG electrodes.  The library's pseudo-ECG of a field V at electrode
+ * position x_e (mm) is
+ *     phi(x_e) = h^3 sum_{p in tissue} (L V)_p / |x_p - x_e|,   x_p = h (x, y, z),
+ * with L the step's own discrete diffusion operator (the weights of "Monodomain
+ * diffusion and boundary conditions"): with no-flux boundaries, summation by
+ * parts makes this the volume integral of -D grad V . grad(1/r) of the
+ * classical pseudo-ECG (its constant factor left to the caller).  (L V)_p is
+ * evaluated in the grid's precision; distances and all sums are FP64, reduced
+ * in a fixed order (deterministic).  nelec (0..16) electrodes at xyz_mm[3*nelec]
+ * (copied); no electrode may sit exactly on a tissue voxel centre (EINVAL).
+ * every > 0: after each step that brings the step counter to a multiple of
+ * `every`, the ECG of the new V is stored, up to max_samples samples (read with
+ * BBX_READ_ECG_SERIES / _COUNT); every = 0: on demand only (BBX_READ_ECG).
+ * Calling it again replaces the electrodes and clears stored samples; nelec = 0
+ * turns the ECG off. */
+int bbx_ecg_set(bbx_grid *g, int nelec, const double *xyz_mm, int64_t every, int64_t max_samples);
 
 /* Rush-Larsen tabulation ("Exponential solvers": the rate coefficients of
  * gates that depend on V alone are precomputed on a grid of V at start time):
@@ -275,7 +306,7 @@ int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev);
  * kinetic input leaves [lo, hi] (nvar floats each), whose predicted gates
  * leave [-1e-3, 1 + 1e-3] (accepted gates are clamped to [0, 1]), whose
  * predicted |dV| exceeds dv_max, or whose prediction is not finite.  Supported
- * models: Barkley, FHN, CRN.  The network's weights are copied; it may be
+ * models: Barkley, FHN, CRN, TP06.  The network's weights are copied; it may be
  * destroyed after. */
 int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi,
                       float dv_max);

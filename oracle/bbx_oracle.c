@@ -29,6 +29,9 @@
  *     Fenton 2008, epicardial set): transcribed from that publication; pinned
  *     by its exact resting state, the closed-form subthreshold relaxation and
  *     loosely by the shape of its action potential.
+ *   - ten Tusscher-Panfilov 2006 ventricular model (epicardial): transcribed
+ *     from its publications; pinned only loosely by its resting state and
+ *     action-potential shape.
  */
 #include <math.h>
 #include <stdint.h>
@@ -38,7 +41,7 @@
 #include <omp.h>
 #endif
 
-enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4, M_FK4 = 5 };
+enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4, M_FK4 = 5, M_TP06 = 6 };
 enum { S_ADDITIVE = 0, S_SPLIT = 1 };
 
 #define NVAR_MAX 32
@@ -95,11 +98,14 @@ int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
                 int64_t nact, const int64_t *act, double *W)
 {
     const double ih2 = 1.0 / (h * h);
+    int bad = 0;
+    /* voxels are independent: the loop is split over threads, results unchanged */
+#pragma omp parallel for schedule(static) reduction(| : bad)
     for (int64_t a = 0; a < nact; a++) {
         int64_t idx = act[a];
         int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
         double Dp[3][3];
-        if (tensor_of(fibre, idx, Dpar, Dperp, Dp)) return -1;
+        if (tensor_of(fibre, idx, Dpar, Dperp, Dp)) { bad = 1; continue; }
 
         /* D at p+q_j and p-q_j for j = 0..2 (substituted by D^p when void). */
         double Dplus[3][3][3], Dminus[3][3][3];
@@ -111,7 +117,7 @@ int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
                 double (*dst)[3] = (s > 0) ? Dplus[j] : Dminus[j];
                 if (chi(nx, ny, nz, mask, xx, yy, zz)) {
                     int64_t nidx = (int64_t)xx + (int64_t)nx * ((int64_t)yy + (int64_t)ny * zz);
-                    if (tensor_of(fibre, nidx, Dpar, Dperp, dst)) return -1;
+                    if (tensor_of(fibre, nidx, Dpar, Dperp, dst)) bad = 1;
                 } else {
                     memcpy(dst, Dp, sizeof(Dp));
                 }
@@ -149,7 +155,7 @@ int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
                 }
         w[13] = -sum;
     }
-    return 0;
+    return bad ? -1 : 0;
 }
 
 /* (L u)_p = sum_q W^p_q u_{p+q}, written in the equivalent difference form
@@ -193,6 +199,7 @@ int orc_nvar(int model)
     case M_FHN: return 2;
     case M_CRN: return 21;
     case M_FK4: return 4;
+    case M_TP06: return 19;
     default: return -1;
     }
 }
@@ -206,6 +213,7 @@ int orc_nparams(int model)
     case M_FHN: return 3;
     case M_CRN: return 0;
     case M_FK4: return 4;
+    case M_TP06: return 0;
     default: return -1;
     }
 }
@@ -215,6 +223,7 @@ static int is_gate(int model, int i)
 {
     if (model == M_CRN) return i >= 6;
     if (model == M_FK4) return i >= 1;
+    if (model == M_TP06) return i >= 7;
     return 0;
 }
 
@@ -427,6 +436,127 @@ static void fk4_rates(const double *p, const double *y, double *rate, double *in
     tau[3] = ts;
 }
 
+/* ten Tusscher & Panfilov (2006) human ventricular model, epicardial cell, as
+ * cited in "Cell models"; transcribed from its publications (the 2004 model
+ * paper for the unchanged currents, the 2006 paper for the L-type current and
+ * the subspace calcium dynamics).  V in mV, currents in pA/pF, concentrations
+ * in mM, time in ms.  State order: V, K_i, Na_i, Ca_i, Ca_ss, Ca_SR, Rbar,
+ * Xr1, Xr2, Xs, m, h, j, d, f, f2, fCass, s, r.  The twelve gates (Xr1..r) use
+ * Rush-Larsen; concentrations and the ryanodine-receptor variable Rbar use
+ * forward Euler of their published derivatives (buffering by the rapid
+ * equilibrium factors). */
+static void tp06_rates(const double *y, double *rate, double *inf, double *tau)
+{
+    const double R = 8314.472, T = 310.0, F = 96485.3415;
+    const double RTF = R * T / F;
+    const double Cm = 0.185, Vc = 0.016404, Vsr = 0.001094, Vss = 0.00005468;
+    const double Ko = 5.4, Nao = 140.0, Cao = 2.0;
+    const double GNa = 14.838, GK1 = 5.405, Gto = 0.294, GKr = 0.153, GKs = 0.392, pKNa = 0.03;
+    const double GCaL = 3.980e-5, kNaCa = 1000.0, gam = 0.35, KmCa = 1.38, KmNai = 87.5;
+    const double ksat = 0.1, alf = 2.5, PNaK = 2.724, KmK = 1.0, KmNa = 40.0;
+    const double GpK = 0.0146, GpCa = 0.1238, KpCa = 0.0005, GbNa = 0.00029, GbCa = 0.000592;
+    const double Vmaxup = 0.006375, Kup = 0.00025, Vrel = 0.102, k1p = 0.15, k2p = 0.045;
+    const double k3 = 0.060, k4 = 0.005, EC = 1.5, maxsr = 2.5, minsr = 1.0;
+    const double Vleak = 0.00036, Vxfer = 0.0038, Bufc = 0.2, Kbufc = 0.001;
+    const double Bufsr = 10.0, Kbufsr = 0.3, Bufss = 0.4, Kbufss = 0.00025;
+
+    double V = y[0], Ki = y[1], Nai = y[2], Cai = y[3], Cass = y[4], CaSR = y[5], Rb = y[6];
+    double xr1 = y[7], xr2 = y[8], xs = y[9], m = y[10], h = y[11], j = y[12];
+    double d = y[13], f = y[14], f2 = y[15], fcass = y[16], sg = y[17], rg = y[18];
+
+    double EK = RTF * log(Ko / Ki), ENa = RTF * log(Nao / Nai);
+    double EKs = RTF * log((Ko + pKNa * Nao) / (Ki + pKNa * Nai));
+    double ECa = 0.5 * RTF * log(Cao / Cai);
+
+    double INa = GNa * m * m * m * h * j * (V - ENa);
+    /* L-type: 4 (V-15) F^2/(RT) (0.25 Ca_ss e^z - Ca_o)/(e^z - 1), z = 2 (V-15) F/(RT)
+     *       = 2 F (0.25 Ca_ss e^z - Ca_o) z/(e^z - 1) */
+    double z = 2.0 * (V - 15.0) / RTF;
+    double ICaL = GCaL * d * f * f2 * fcass * 2.0 * F * (0.25 * Cass * exp(z) - Cao) * z_over_expm1(z);
+    double Ito = Gto * rg * sg * (V - EK);
+    double IKr = GKr * sqrt(Ko / 5.4) * xr1 * xr2 * (V - EK);
+    double IKs = GKs * xs * xs * (V - EKs);
+    double aK1 = 0.1 / (1.0 + exp(0.06 * (V - EK - 200.0)));
+    double bK1 = (3.0 * exp(0.0002 * (V - EK + 100.0)) + exp(0.1 * (V - EK - 10.0)))
+                 / (1.0 + exp(-0.5 * (V - EK)));
+    double IK1 = GK1 * sqrt(Ko / 5.4) * aK1 / (aK1 + bK1) * (V - EK);
+    double eg = exp(gam * V / RTF), eg1 = exp((gam - 1.0) * V / RTF);
+    double INaCa = kNaCa * (eg * Nai * Nai * Nai * Cao - eg1 * Nao * Nao * Nao * Cai * alf)
+                   / ((KmNai * KmNai * KmNai + Nao * Nao * Nao) * (KmCa + Cao) * (1.0 + ksat * eg1));
+    double INaK = PNaK * Ko * Nai / ((Ko + KmK) * (Nai + KmNa)
+                                     * (1.0 + 0.1245 * exp(-0.1 * V / RTF) + 0.0353 * exp(-V / RTF)));
+    double IpCa = GpCa * Cai / (KpCa + Cai);
+    double IpK = GpK * (V - EK) / (1.0 + exp((25.0 - V) / 5.98));
+    double IbNa = GbNa * (V - ENa);
+    double IbCa = GbCa * (V - ECa);
+
+    /* calcium handling */
+    double kcasr = maxsr - (maxsr - minsr) / (1.0 + (EC / CaSR) * (EC / CaSR));
+    double k1 = k1p / kcasr, k2 = k2p * kcasr;
+    double O = k1 * Cass * Cass * Rb / (k3 + k1 * Cass * Cass);
+    double Irel = Vrel * O * (CaSR - Cass);
+    double Iup = Vmaxup / (1.0 + Kup * Kup / (Cai * Cai));
+    double Ileak = Vleak * (CaSR - Cai);
+    double Ixfer = Vxfer * (Cass - Cai);
+    double bc = 1.0 / (1.0 + Bufc * Kbufc / ((Cai + Kbufc) * (Cai + Kbufc)));
+    double bsr = 1.0 / (1.0 + Bufsr * Kbufsr / ((CaSR + Kbufsr) * (CaSR + Kbufsr)));
+    double bss = 1.0 / (1.0 + Bufss * Kbufss / ((Cass + Kbufss) * (Cass + Kbufss)));
+
+    rate[0] = -(INa + ICaL + Ito + IKr + IKs + IK1 + INaCa + INaK + IpCa + IpK + IbNa + IbCa);
+    rate[1] = -(IK1 + Ito + IKr + IKs - 2.0 * INaK + IpK) * Cm / (Vc * F);
+    rate[2] = -(INa + IbNa + 3.0 * INaK + 3.0 * INaCa) * Cm / (Vc * F);
+    rate[3] = bc * ((Ileak - Iup) * Vsr / Vc + Ixfer - (IbCa + IpCa - 2.0 * INaCa) * Cm / (2.0 * Vc * F));
+    rate[4] = bss * (-ICaL * Cm / (2.0 * Vss * F) + Irel * Vsr / Vss - Ixfer * Vc / Vss);
+    rate[5] = bsr * (Iup - Irel - Ileak);
+    rate[6] = -k2 * Cass * Rb + k4 * (1.0 - Rb);
+
+    /* gates: steady states and time constants */
+    inf[7] = 1.0 / (1.0 + exp((-26.0 - V) / 7.0));
+    tau[7] = 450.0 / (1.0 + exp((-45.0 - V) / 10.0)) * 6.0 / (1.0 + exp((V + 30.0) / 11.5));
+    inf[8] = 1.0 / (1.0 + exp((V + 88.0) / 24.0));
+    tau[8] = 3.0 / (1.0 + exp((-60.0 - V) / 20.0)) * 1.12 / (1.0 + exp((V - 60.0) / 20.0));
+    inf[9] = 1.0 / (1.0 + exp((-5.0 - V) / 14.0));
+    tau[9] = 1400.0 / sqrt(1.0 + exp((5.0 - V) / 6.0)) / (1.0 + exp((V - 35.0) / 15.0)) + 80.0;
+    double mi = 1.0 / (1.0 + exp((-56.86 - V) / 9.03));
+    inf[10] = mi * mi;
+    tau[10] = 1.0 / (1.0 + exp((-60.0 - V) / 5.0))
+              * (0.1 / (1.0 + exp((V + 35.0) / 5.0)) + 0.10 / (1.0 + exp((V - 50.0) / 200.0)));
+    double hi = 1.0 / (1.0 + exp((V + 71.55) / 7.43));
+    double ah, bh, aj, bj;
+    if (V >= -40.0) {
+        ah = 0.0;
+        bh = 0.77 / (0.13 * (1.0 + exp(-(V + 10.66) / 11.1)));
+        aj = 0.0;
+        bj = 0.6 * exp(0.057 * V) / (1.0 + exp(-0.1 * (V + 32.0)));
+    } else {
+        ah = 0.057 * exp(-(V + 80.0) / 6.8);
+        bh = 2.7 * exp(0.079 * V) + 3.1e5 * exp(0.3485 * V);
+        aj = (-2.5428e4 * exp(0.2444 * V) - 6.948e-6 * exp(-0.04391 * V)) * (V + 37.78)
+             / (1.0 + exp(0.311 * (V + 79.23)));
+        bj = 0.02424 * exp(-0.01052 * V) / (1.0 + exp(-0.1378 * (V + 40.14)));
+    }
+    inf[11] = hi * hi;
+    tau[11] = 1.0 / (ah + bh);
+    inf[12] = hi * hi;
+    tau[12] = 1.0 / (aj + bj);
+    inf[13] = 1.0 / (1.0 + exp((-8.0 - V) / 7.5));
+    tau[13] = (1.4 / (1.0 + exp((-35.0 - V) / 13.0)) + 0.25) * 1.4 / (1.0 + exp((V + 5.0) / 5.0))
+              + 1.0 / (1.0 + exp((50.0 - V) / 20.0));
+    inf[14] = 1.0 / (1.0 + exp((V + 20.0) / 7.0));
+    tau[14] = 1102.5 * exp(-(V + 27.0) * (V + 27.0) / 225.0) + 200.0 / (1.0 + exp((13.0 - V) / 10.0))
+              + 180.0 / (1.0 + exp((V + 30.0) / 10.0)) + 20.0;
+    inf[15] = 0.67 / (1.0 + exp((V + 35.0) / 7.0)) + 0.33;
+    tau[15] = 562.0 * exp(-(V + 27.0) * (V + 27.0) / 240.0) + 31.0 / (1.0 + exp((25.0 - V) / 10.0))
+              + 80.0 / (1.0 + exp((V + 30.0) / 10.0));
+    double cq = (Cass / 0.05) * (Cass / 0.05);
+    inf[16] = 0.6 / (1.0 + cq) + 0.4;
+    tau[16] = 80.0 / (1.0 + cq) + 2.0;
+    inf[17] = 1.0 / (1.0 + exp((V + 20.0) / 5.0));
+    tau[17] = 85.0 * exp(-(V + 45.0) * (V + 45.0) / 320.0) + 5.0 / (1.0 + exp((V - 20.0) / 5.0)) + 3.0;
+    inf[18] = 1.0 / (1.0 + exp((20.0 - V) / 6.0));
+    tau[18] = 9.5 * exp(-(V + 40.0) * (V + 40.0) / 1800.0) + 0.8;
+}
+
 static void model_eval(int model, const double *p, const double *y,
                        double *rate, double *inf, double *tau)
 {
@@ -437,6 +567,7 @@ static void model_eval(int model, const double *p, const double *y,
     case M_FHN: fhn_rates(p, y, rate); break;
     case M_CRN: crn_rates(y, rate, inf, tau); break;
     case M_FK4: fk4_rates(p, y, rate, inf, tau); break;
+    case M_TP06: tp06_rates(y, rate, inf, tau); break;
     }
 }
 

@@ -21,11 +21,12 @@ BBX_OK, BBX_EINVAL, BBX_ENOMEM, BBX_EDEVICE, BBX_ESTATE, BBX_EUNSTABLE, BBX_ENUM
     0, -1, -2, -3, -4, -5, -6, -7
 BBX_FP32, BBX_FP64 = 0, 1
 BBX_SCHEME_ADDITIVE, BBX_SCHEME_SPLIT = 0, 1
-BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, BBX_MODEL_FK4 = \
-    0, 1, 2, 3, 4, 5
+BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, BBX_MODEL_FK4, \
+    BBX_MODEL_TP06 = 0, 1, 2, 3, 4, 5, 6
 (BBX_READ_VAR, BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX, BBX_READ_STATUS,
  BBX_READ_REDUCE_MAX, BBX_READ_REDUCE_SUM, BBX_READ_NAN_FLAG, BBX_READ_STEP,
- BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT) = range(11)
+ BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT, BBX_READ_ECG, BBX_READ_ECG_SERIES,
+ BBX_READ_ECG_COUNT) = range(14)
 BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
 BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_NVARIANT = range(5)
 (BBX_ENS_INFO_VOXELS, BBX_ENS_INFO_TILES, BBX_ENS_INFO_VARIANT, BBX_ENS_INFO_DEVICE_BYTES,
@@ -37,12 +38,14 @@ SIGNATURES = {
     "bbx_grid_create": (_I, [_I, _I, _I, _D, _P, _P, _D, _D, _I, _P, C.POINTER(_P)]),
     "bbx_model_set": (_I, [_P, _I, _P, _I, _D, _I]),
     "bbx_state_set": (_I, [_P, _I, _P]),
+    "bbx_state_fill": (_I, [_P, _I, _D]),
     "bbx_stimulus_add": (_I, [_P, _P, _D, _D, _D, _D, _I]),
     "bbx_stimulus_clear": (_I, [_P]),
     "bbx_recording_set": (_I, [_P, _D]),
     "bbx_nan_check_set": (_I, [_P, _I64]),
     "bbx_clock_set": (_I, [_P, _I64]),
     "bbx_tabulation_set": (_I, [_P, _D]),
+    "bbx_ecg_set": (_I, [_P, _I, _P, _I64, _I64]),
     "bbx_step": (_I, [_P, _I64]),
     "bbx_readout": (_I, [_P, _I, _I, _P, _P, _SZ, _I]),
     "bbx_info": (_I, [_P, _I, C.POINTER(_I64)]),
@@ -146,6 +149,10 @@ def bbx_state_set(g, var, box_values):
     _check(_lib.bbx_state_set(g, int(var), _ptr(v)))
 
 
+def bbx_state_fill(g, var, value):
+    _check(_lib.bbx_state_fill(g, int(var), float(value)))
+
+
 def bbx_stimulus_add(g, region, amplitude, t_start, duration, period=0.0, count=1):
     r = np.ascontiguousarray(region, dtype=np.uint8)
     _check(_lib.bbx_stimulus_add(g, _ptr(r), float(amplitude), float(t_start), float(duration),
@@ -162,6 +169,12 @@ def bbx_recording_set(g, theta):
 
 def bbx_nan_check_set(g, every):
     _check(_lib.bbx_nan_check_set(g, int(every)))
+
+
+def bbx_ecg_set(g, xyz_mm, every=0, max_samples=0):
+    E = np.ascontiguousarray(np.asarray(xyz_mm, np.float64).reshape(-1, 3))
+    _check(_lib.bbx_ecg_set(g, E.shape[0], _ptr(E) if E.size else None, int(every),
+                            int(max_samples)))
 
 
 def bbx_tabulation_set(g, dv):
@@ -250,8 +263,28 @@ class Grid:
     def clock(self, step):
         bbx_clock_set(self.handle, step)
 
+    def fill(self, var, value):
+        bbx_state_fill(self.handle, var, value)
+
     def tabulate(self, dv):
         bbx_tabulation_set(self.handle, dv)
+
+    def ecg(self, xyz_mm, every=0, max_samples=0):
+        """Set pseudo-ECG electrodes (mm); every > 0 samples after every `every` steps."""
+        self._nelec = int(np.asarray(xyz_mm).size // 3)
+        bbx_ecg_set(self.handle, xyz_mm, every, max_samples)
+
+    def ecg_now(self):
+        out = np.empty(getattr(self, "_nelec", 0), np.float64)
+        return bbx_readout(self.handle, BBX_READ_ECG, 0, None, out)
+
+    def ecg_series(self):
+        cnt = np.empty(1, np.int64)
+        bbx_readout(self.handle, BBX_READ_ECG_COUNT, 0, None, cnt)
+        out = np.empty((int(cnt[0]), getattr(self, "_nelec", 0)), np.float64)
+        if out.size:
+            bbx_readout(self.handle, BBX_READ_ECG_SERIES, 0, None, out)
+        return out
 
     def sample_states(self, n, seed, out):
         bbx_sample_states(self.handle, n, seed, out)

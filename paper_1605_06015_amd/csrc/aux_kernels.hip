@@ -23,6 +23,22 @@ hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
+// box[idx[t]] = v for every tissue voxel t (sparse grids; void entries untouched).
+template <typename T>
+__global__ void k_fill_tissue(T *box, const int32_t *idx, int64_t nact, T v)
+{
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < nact) box[idx[t]] = v;
+}
+
+template <typename T>
+hipError_t launch_fill_tissue(T *box, const int32_t *idx, int64_t nact, T v, hipStream_t s)
+{
+    if (nact <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_tissue<T>, dim3(blocks_for(nact)), dim3(kBlock), 0, s, box, idx, nact, v);
+    return hipGetLastError();
+}
+
 // out[box] = NaN for void, src value for tissue.
 template <typename T>
 __global__ void k_to_box(const T *src, int src_is_box, const int32_t *idx, int dense,
@@ -272,6 +288,7 @@ hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab
 
 #define BBX_INST(T)                                                                          \
     template hipError_t launch_fill<T>(T *, T, int64_t, hipStream_t);                         \
+    template hipError_t launch_fill_tissue<T>(T *, const int32_t *, int64_t, T, hipStream_t); \
     template hipError_t launch_to_box<T>(const T *, int, const int32_t *, int, int64_t,       \
                                          int64_t, double *, hipStream_t);                     \
     template hipError_t launch_from_box<T>(const double *, T *, int, const int32_t *, int,    \

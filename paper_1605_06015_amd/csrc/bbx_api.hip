@@ -52,6 +52,7 @@ int model_nvar(int m)
     case BBX_MODEL_FHN: return 2;
     case BBX_MODEL_CRN: return 21;
     case BBX_MODEL_FK4: return 4;
+    case BBX_MODEL_TP06: return 19;
     default: return -1;
     }
 }
@@ -65,6 +66,7 @@ int model_nparams(int m)
     case BBX_MODEL_FHN: return 3;
     case BBX_MODEL_CRN: return 0;
     case BBX_MODEL_FK4: return 4;
+    case BBX_MODEL_TP06: return 0;
     default: return -1;
     }
 }
@@ -127,6 +129,10 @@ struct bbx_grid {
     unsigned long long *d_fb_total = nullptr;
     double *d_parts = nullptr, *d_red = nullptr;
     int *d_flag = nullptr;
+    // pseudo-ECG sampling
+    EcgElectrodes ecg = {};
+    int64_t ecg_every = 0, ecg_max = 0, ecg_count = 0;
+    double *d_ecg_series = nullptr, *d_ecg_parts = nullptr, *d_ecg_now = nullptr;
     int nparts = 1024;
     size_t bytes = 0;
 };
@@ -155,7 +161,7 @@ void free_all(bbx_grid *g)
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
-                  g->d_fb_list, g->d_fb_cnt, g->d_fb_total, g->d_tab, g->snet.w1, g->snet.w2, g->snet.w3,
+                  g->d_fb_list, g->d_fb_cnt, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
                   g->snet.bias, g->snet.norm};
     for (void *p : ps) dfree(p);
 }
@@ -304,6 +310,13 @@ int step_impl(bbx_grid *g, int64_t nsteps)
             if (!done) HIP_TRY(launch_step<T>(g->model, g->aniso, a, g->stream), "step launch");
         }
         g->cur ^= 1;
+        if (g->ecg_every > 0 && (n + 1) % g->ecg_every == 0 && g->ecg_count < g->ecg_max && g->nact > 0) {
+            StepArgs<T> b = a;
+            b.Vin = (const T *)g->d_V[g->cur];
+            HIP_TRY(launch_ecg<T>(b, g->aniso, g->ecg, g->d_ecg_parts,
+                                  g->d_ecg_series + g->ecg_count * g->ecg.n, g->stream), "pseudo-ECG");
+            g->ecg_count++;
+        }
         if (g->nan_every > 0 && (n + 1) % g->nan_every == 0)
             HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense,
                                         (const T *)g->d_st, nst, g->nact, g->pitch, g->d_flag,
@@ -354,6 +367,18 @@ int download_idx(const bbx_grid *g, std::vector<int32_t> &h_idx)
     HIP_TRY(hipMemcpyAsync(h_idx.data(), g->d_idx, g->nact * sizeof(int32_t),
                            hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
     HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    return BBX_OK;
+}
+
+// Tissue mask (box order) rebuilt from the tissue list.
+int download_mask(const bbx_grid *g, std::vector<uint8_t> &mask)
+{
+    mask.assign((size_t)g->nbox, g->dense ? 1 : 0);
+    if (g->dense) return BBX_OK;
+    std::vector<int32_t> h_idx;
+    int rc = download_idx(g, h_idx);
+    if (rc) return rc;
+    for (int32_t b : h_idx) mask[(size_t)b] = 1;
     return BBX_OK;
 }
 
@@ -504,6 +529,19 @@ int state_set_impl(bbx_grid *g, int var, const double *vals)
 }
 
 template <typename T>
+int state_fill_impl(bbx_grid *g, int var, double value)
+{
+    if (var == 0) {
+        if (g->dense) HIP_TRY(launch_fill<T>((T *)g->d_V[g->cur], (T)value, g->nbox, g->stream), "fill");
+        else HIP_TRY(launch_fill_tissue<T>((T *)g->d_V[g->cur], g->d_idx, g->nact, (T)value, g->stream), "fill");
+    } else {
+        HIP_TRY(launch_fill<T>((T *)g->d_st + (int64_t)(var - 1) * g->pitch, (T)value, g->nact, g->stream), "fill");
+    }
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    return BBX_OK;
+}
+
+template <typename T>
 int recording_impl(bbx_grid *g, double theta)
 {
     const size_t es = sizeof(T);
@@ -637,6 +675,36 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
         HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
         return BBX_OK;
     }
+    case BBX_READ_ECG: {
+        if (g->ecg.n <= 0) return fail(BBX_ESTATE, "no electrodes (bbx_ecg_set)");
+        if (out_bytes < (size_t)g->ecg.n * sizeof(double)) return fail(BBX_EINVAL, "out_bytes too small");
+        if (g->nact == 0) return fail(BBX_EINVAL, "the grid has no tissue");
+        StepArgs<T> a = make_args<T>(g);
+        a.Vin = (const T *)g->d_V[g->cur];
+        HIP_TRY(launch_ecg<T>(a, g->aniso, g->ecg, g->d_ecg_parts, g->d_ecg_now, g->stream), "pseudo-ECG");
+        HIP_TRY(hipMemcpyAsync(out, g->d_ecg_now, g->ecg.n * sizeof(double),
+                               on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    case BBX_READ_ECG_SERIES: {
+        if (g->ecg.n <= 0) return fail(BBX_ESTATE, "no electrodes (bbx_ecg_set)");
+        const size_t need = (size_t)g->ecg_count * g->ecg.n * sizeof(double);
+        if (out_bytes < need) return fail(BBX_EINVAL, "out_bytes too small");
+        if (need)
+            HIP_TRY(hipMemcpyAsync(out, g->d_ecg_series, need,
+                                   on_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, g->stream),
+                    "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return BBX_OK;
+    }
+    case BBX_READ_ECG_COUNT: {
+        if (on_dev) return fail(BBX_ENOTSUP, "ECG_COUNT is read to host memory only");
+        if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
+        memcpy(out, &g->ecg_count, sizeof(int64_t));
+        return BBX_OK;
+    }
     default:
         return fail(BBX_EINVAL, "unknown readout %d", what);
     }
@@ -752,6 +820,20 @@ int bbx_state_set(bbx_grid *g, int var, const double *box_values)
     }
 }
 
+int bbx_state_fill(bbx_grid *g, int var, double value)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (var < 0 || var >= g->nvar) return fail(BBX_EINVAL, "var %d out of range (nvar %d)", var, g->nvar);
+        if (var > 0 && g->model < 0) return fail(BBX_ESTATE, "set a model first");
+        if (!isfinite(value)) return fail(BBX_EINVAL, "value is not finite");
+        return g->prec ? state_fill_impl<double>(g, var, value) : state_fill_impl<float>(g, var, value);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
 int bbx_stimulus_add(bbx_grid *g, const uint8_t *region, double amplitude, double t_start,
                      double duration, double period, int count)
 {
@@ -822,6 +904,63 @@ int bbx_nan_check_set(bbx_grid *g, int64_t every)
     if (every < 0) return fail(BBX_EINVAL, "every must be >= 0");
     g->nan_every = every;
     return BBX_OK;
+}
+
+int bbx_ecg_set(bbx_grid *g, int nelec, const double *xyz_mm, int64_t every, int64_t max_samples)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (nelec < 0 || nelec > kMaxElectrodes) return fail(BBX_EINVAL, "nelec must be 0..%d", kMaxElectrodes);
+        if (nelec > 0 && !xyz_mm) return fail(BBX_EINVAL, "xyz is NULL");
+        if (nelec > 0 && (every < 0 || max_samples < 0 || max_samples > ((int64_t)1 << 26)))
+            return fail(BBX_EINVAL, "every must be >= 0 and max_samples in 0..2^26");
+        if (nelec > 0 && every > 0 && max_samples == 0) return fail(BBX_EINVAL, "sampling needs max_samples > 0");
+        EcgElectrodes el = {};
+        el.n = nelec;
+        el.h = g->h;
+        std::vector<uint8_t> mask;
+        for (int e = 0; e < nelec; e++) {
+            const double x = xyz_mm[3 * e], y = xyz_mm[3 * e + 1], z = xyz_mm[3 * e + 2];
+            if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return fail(BBX_EINVAL, "electrode %d not finite", e);
+            // an electrode on a tissue voxel centre would divide by zero
+            const double fx = x / g->h, fy = y / g->h, fz = z / g->h;
+            if (fx == floor(fx) && fy == floor(fy) && fz == floor(fz) && fx >= 0 && fy >= 0 && fz >= 0 &&
+                fx < g->nx && fy < g->ny && fz < g->nz) {
+                if (mask.empty()) {
+                    int rc = download_mask(g, mask);
+                    if (rc) return rc;
+                }
+                if (mask[(size_t)fx + (size_t)g->nx * ((size_t)fy + (size_t)g->ny * (size_t)fz)])
+                    return fail(BBX_EINVAL, "electrode %d sits on a tissue voxel centre", e);
+            }
+            el.x[e] = x;
+            el.y[e] = y;
+            el.z[e] = z;
+        }
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        dfree(g->d_ecg_series);
+        g->d_ecg_series = nullptr;
+        g->ecg_count = 0;
+        g->ecg_every = 0;
+        g->ecg_max = 0;
+        g->ecg = el;
+        if (nelec == 0) return BBX_OK;
+        hipError_t e = hipSuccess;
+        if (!g->d_ecg_parts) e = dalloc(g, &g->d_ecg_parts, (size_t)kEcgPartials * kMaxElectrodes * sizeof(double));
+        if (e == hipSuccess && !g->d_ecg_now) e = dalloc(g, &g->d_ecg_now, kMaxElectrodes * sizeof(double));
+        if (e == hipSuccess && every > 0)
+            e = dalloc(g, &g->d_ecg_series, (size_t)max_samples * nelec * sizeof(double));
+        if (e != hipSuccess) {
+            g->ecg.n = 0;
+            return hip_fail(e, "hipMalloc");
+        }
+        g->ecg_every = every;
+        g->ecg_max = every > 0 ? max_samples : 0;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
 }
 
 int bbx_tabulation_set(bbx_grid *g, double dv)
@@ -1226,7 +1365,8 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
             return BBX_OK;
         }
         if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the surrogate runs on FP32 grids");
-        if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN)
+        if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN &&
+            g->model != BBX_MODEL_TP06)
             return fail(BBX_ENOTSUP, "no surrogate step for model %d", g->model);
         if (m->nin != g->nvar || m->nout != g->nvar)
             return fail(BBX_EINVAL, "network is %d -> %d, the model has %d variables", m->nin, m->nout, g->nvar);

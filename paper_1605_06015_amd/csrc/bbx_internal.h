@@ -75,6 +75,19 @@ void api_clear_error();
 template <typename T>
 hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s);
 
+// Pseudo-ECG electrodes (ecg_kernels.hip): positions in mm, grid step h.
+constexpr int kMaxElectrodes = 16;
+constexpr int kEcgPartials = 1024;   // blocks of the ECG reduction
+struct EcgElectrodes {
+    double x[kMaxElectrodes], y[kMaxElectrodes], z[kMaxElectrodes];
+    double h;
+    int n;
+};
+// out[e] = pseudo-ECG of a.Vin at electrode e (FP64); partials: kEcgPartials * kMaxElectrodes.
+template <typename T>
+hipError_t launch_ecg(const StepArgs<T> &a, int aniso, const EcgElectrodes &el, double *partials,
+                      double *out, hipStream_t s);
+
 // Auxiliary kernels (aux_kernels.hip).
 template <typename T>
 hipError_t launch_to_box(const T *src, int src_is_box, const int32_t *idx, int dense,
@@ -93,6 +106,8 @@ template <typename T>
 hipError_t launch_weights(const StepArgs<T> &a, int aniso, double *W, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_fill_tissue(T *box, const int32_t *idx, int64_t nact, T v, hipStream_t s);
 hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab, hipStream_t s);
 constexpr double kTabVmin = -120.0, kTabVmax = 80.0;   // tabulated voltage range (mV)
 constexpr int kTabWidth = 32;                           // floats per table node

@@ -166,6 +166,131 @@ struct Fk4 {
     }
 };
 
+// ---------------------------------------------------------------- ten Tusscher-Panfilov 2006
+// ten Tusscher & Panfilov (2006) human ventricular model, epicardial cell, as
+// cited in "Cell models"; transcribed from its publications (the 2004 model
+// paper for the unchanged currents, the 2006 paper for the L-type current and
+// the subspace calcium dynamics).  g = K_i, Na_i, Ca_i, Ca_ss, Ca_SR, Rbar, Xr1,
+// Xr2, Xs, m, h, j, d, f, f2, fCass, s, r (V in mV, currents pA/pF, mM, ms).
+// Concentrations and Rbar: forward Euler of the published derivatives with
+// rapid-buffering factors; the twelve gates: Rush-Larsen.
+namespace tp {
+constexpr double kRTF = 8314.472 * 310.0 / 96485.3415;  // mV
+constexpr double kF = 96485.3415;
+constexpr double kCm = 0.185, kVc = 0.016404, kVsr = 0.001094, kVss = 0.00005468;
+constexpr double kKo = 5.4, kNao = 140.0, kCao = 2.0;
+constexpr double kNaCaDen = (87.5 * 87.5 * 87.5 + 140.0 * 140.0 * 140.0) * (1.38 + 2.0);
+}  // namespace tp
+
+template <typename T>
+struct Tp06 {
+    static constexpr int NV = 19, GATE0 = 7;
+    __device__ static T advance(const T *, T V, T *g, T dt, const float *)
+    {
+        using namespace tp;
+        const T Ki = g[0], Nai = g[1], Cai = g[2], Cass = g[3], CaSR = g[4], Rb = g[5];
+        const T RTF = T(kRTF), iRTF = T(1.0 / kRTF);
+        const T EK = RTF * lg(dv(T(kKo), Ki)), ENa = RTF * lg(dv(T(kNao), Nai));
+        const T EKs = RTF * lg(dv(T(kKo + 0.03 * kNao), Ki + T(0.03) * Nai));
+        const T ECa = T(0.5) * RTF * lg(dv(T(kCao), Cai));
+
+        const T m = g[9], h = g[10], j = g[11];
+        const T INa = T(14.838) * m * m * m * h * j * (V - ENa);
+        // L-type: 2F (0.25 Ca_ss e^z - Ca_o) z/(e^z - 1), z = 2 (V - 15) F/(RT)
+        const T z = T(2) * (V - T(15)) * iRTF;
+        const T ICaL = T(3.980e-5) * g[12] * g[13] * g[14] * g[15] * T(2.0 * kF)
+                       * (T(0.25) * Cass * ex(z) - T(kCao)) * bern(z);
+        const T Ito = T(0.294) * g[17] * g[16] * (V - EK);
+        const T IKr = T(0.153) * T(1.0) * g[6] * g[7] * (V - EK);     // sqrt(Ko/5.4) = 1
+        const T IKs = T(0.392) * g[8] * g[8] * (V - EKs);
+        const T aK1 = dv(T(0.1), T(1) + ex(T(0.06) * (V - EK - T(200))));
+        const T bK1 = dv(T(3) * ex(T(0.0002) * (V - EK + T(100))) + ex(T(0.1) * (V - EK - T(10))),
+                         T(1) + ex(T(-0.5) * (V - EK)));
+        const T IK1 = T(5.405) * T(1.0) * dv(aK1, aK1 + bK1) * (V - EK);
+        const T eg = ex(T(0.35) * V * iRTF), eg1 = ex(T(-0.65) * V * iRTF);
+        const T INaCa = T(1000.0) * dv(eg * Nai * Nai * Nai * T(kCao) - eg1 * T(kNao * kNao * kNao) * Cai * T(2.5),
+                                       T(kNaCaDen) * (T(1) + T(0.1) * eg1));
+        const T INaK = T(2.724 * kKo) * dv(Nai, T(kKo + 1.0) * (Nai + T(40))
+                                                   * (T(1) + T(0.1245) * ex(T(-0.1) * V * iRTF)
+                                                      + T(0.0353) * ex(-V * iRTF)));
+        const T IpCa = T(0.1238) * dv(Cai, T(0.0005) + Cai);
+        const T IpK = T(0.0146) * dv(V - EK, T(1) + ex((T(25) - V) * T(1.0 / 5.98)));
+        const T IbNa = T(0.00029) * (V - ENa);
+        const T IbCa = T(0.000592) * (V - ECa);
+
+        // calcium handling
+        const T ec = dv(T(1.5), CaSR);
+        const T kcasr = T(2.5) - dv(T(1.5), T(1) + ec * ec);
+        const T k1 = dv(T(0.15), kcasr), k2 = T(0.045) * kcasr;
+        const T c2 = Cass * Cass;
+        const T O = dv(k1 * c2 * Rb, T(0.060) + k1 * c2);
+        const T Irel = T(0.102) * O * (CaSR - Cass);
+        const T Iup = dv(T(0.006375), T(1) + dv(T(0.00025 * 0.00025), Cai * Cai));
+        const T Ileak = T(0.00036) * (CaSR - Cai);
+        const T Ixfer = T(0.0038) * (Cass - Cai);
+        const T bc = rcp(T(1) + dv(T(0.2 * 0.001), (Cai + T(0.001)) * (Cai + T(0.001))));
+        const T bsr = rcp(T(1) + dv(T(10.0 * 0.3), (CaSR + T(0.3)) * (CaSR + T(0.3))));
+        const T bss = rcp(T(1) + dv(T(0.4 * 0.00025), (Cass + T(0.00025)) * (Cass + T(0.00025))));
+        const T c2f = T(kCm / (kVc * kF));
+        g[0] = Ki + dt * (-(IK1 + Ito + IKr + IKs - T(2) * INaK + IpK) * c2f);
+        g[1] = Nai + dt * (-(INa + IbNa + T(3) * INaK + T(3) * INaCa) * c2f);
+        g[2] = Cai + dt * (bc * ((Ileak - Iup) * T(kVsr / kVc) + Ixfer
+                                 - (IbCa + IpCa - T(2) * INaCa) * T(kCm / (2.0 * kVc * kF))));
+        g[3] = Cass + dt * (bss * (-ICaL * T(kCm / (2.0 * kVss * kF)) + Irel * T(kVsr / kVss)
+                                   - Ixfer * T(kVc / kVss)));
+        g[4] = CaSR + dt * (bsr * (Iup - Irel - Ileak));
+        g[5] = Rb + dt * (-k2 * Cass * Rb + T(0.005) * (T(1) - Rb));
+
+        // gates
+        g[6] = rl_rate(g[6], lgs((T(-26) - V) * T(1.0 / 7.0)),
+                       rcp(dv(T(450), T(1) + ex((T(-45) - V) * T(0.1))) * dv(T(6), T(1) + ex((V + T(30)) * T(1.0 / 11.5)))), dt);
+        g[7] = rl_rate(g[7], lgs((V + T(88)) * T(1.0 / 24.0)),
+                       rcp(dv(T(3), T(1) + ex((T(-60) - V) * T(0.05))) * dv(T(1.12), T(1) + ex((V - T(60)) * T(0.05)))), dt);
+        g[8] = rl_rate(g[8], lgs((T(-5) - V) * T(1.0 / 14.0)),
+                       rcp(dv(T(1400), sq(T(1) + ex((T(5) - V) * T(1.0 / 6.0)))) * rcp(T(1) + ex((V - T(35)) * T(1.0 / 15.0))) + T(80)), dt);
+        const T mi = lgs((T(-56.86) - V) * T(1.0 / 9.03));
+        g[9] = rl_rate(m, mi * mi,
+                       rcp(rcp(T(1) + ex((T(-60) - V) * T(0.2)))
+                           * (dv(T(0.1), T(1) + ex((V + T(35)) * T(0.2))) + dv(T(0.10), T(1) + ex((V - T(50)) * T(1.0 / 200.0))))), dt);
+        const T hi = lgs((V + T(71.55)) * T(1.0 / 7.43));
+        T ah, bh, aj, bj;
+        if (V >= T(-40)) {
+            ah = T(0);
+            bh = dv(T(0.77), T(0.13) * (T(1) + ex(-(V + T(10.66)) * T(1.0 / 11.1))));
+            aj = T(0);
+            bj = dv(T(0.6) * ex(T(0.057) * V), T(1) + ex(T(-0.1) * (V + T(32))));
+        } else {
+            ah = T(0.057) * ex(-(V + T(80)) * T(1.0 / 6.8));
+            bh = T(2.7) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.3485) * V);
+            aj = dv((T(-2.5428e4) * ex(T(0.2444) * V) - T(6.948e-6) * ex(T(-0.04391) * V)) * (V + T(37.78)),
+                    T(1) + ex(T(0.311) * (V + T(79.23))));
+            bj = dv(T(0.02424) * ex(T(-0.01052) * V), T(1) + ex(T(-0.1378) * (V + T(40.14))));
+        }
+        g[10] = rl_rate(h, hi * hi, ah + bh, dt);
+        g[11] = rl_rate(j, hi * hi, aj + bj, dt);
+        g[12] = rl_rate(g[12], lgs((T(-8) - V) * T(1.0 / 7.5)),
+                        rcp((dv(T(1.4), T(1) + ex((T(-35) - V) * T(1.0 / 13.0))) + T(0.25))
+                                * dv(T(1.4), T(1) + ex((V + T(5)) * T(0.2)))
+                            + rcp(T(1) + ex((T(50) - V) * T(0.05)))), dt);
+        const T v27 = V + T(27);
+        g[13] = rl_rate(g[13], lgs((V + T(20)) * T(1.0 / 7.0)),
+                        rcp(T(1102.5) * ex(-v27 * v27 * T(1.0 / 225.0)) + dv(T(200), T(1) + ex((T(13) - V) * T(0.1)))
+                            + dv(T(180), T(1) + ex((V + T(30)) * T(0.1))) + T(20)), dt);
+        g[14] = rl_rate(g[14], T(0.67) * lgs((V + T(35)) * T(1.0 / 7.0)) + T(0.33),
+                        rcp(T(562) * ex(-v27 * v27 * T(1.0 / 240.0)) + dv(T(31), T(1) + ex((T(25) - V) * T(0.1)))
+                            + dv(T(80), T(1) + ex((V + T(30)) * T(0.1)))), dt);
+        const T cq = (Cass * T(20)) * (Cass * T(20));
+        g[15] = rl_rate(g[15], dv(T(0.6), T(1) + cq) + T(0.4), rcp(dv(T(80), T(1) + cq) + T(2)), dt);
+        const T v45 = V + T(45), v40 = V + T(40);
+        g[16] = rl_rate(g[16], lgs((V + T(20)) * T(0.2)),
+                        rcp(T(85) * ex(-v45 * v45 * T(1.0 / 320.0)) + dv(T(5), T(1) + ex((V - T(20)) * T(0.2))) + T(3)), dt);
+        g[17] = rl_rate(g[17], lgs((T(20) - V) * T(1.0 / 6.0)),
+                        rcp(T(9.5) * ex(-v40 * v40 * T(1.0 / 1800.0)) + T(0.8)), dt);
+
+        return -(INa + ICaL + Ito + IKr + IKs + IK1 + INaCa + INaK + IpCa + IpK + IbNa + IbCa);
+    }
+};
+
 // ---------------------------------------------------------------- Courtemanche 1998
 // Courtemanche, Ramirez & Nattel, Am J Physiol 275:H301 (1998), human atrial
 // myocyte; the paper uses it for its scaling runs.  Transcribed from that

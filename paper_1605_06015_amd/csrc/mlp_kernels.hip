@@ -785,6 +785,7 @@ hipError_t launch_surrogate_step(int model, int aniso, const StepArgs<float> &a,
     case 1: return sur_m<kin::Barkley<float>>(aniso, a, su, s);
     case 3: return sur_m<kin::Fhn<float>>(aniso, a, su, s);
     case 4: return sur_m<kin::Crn<float>>(aniso, a, su, s);
+    case 6: return sur_m<kin::Tp06<float>>(aniso, a, su, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -796,6 +797,7 @@ hipError_t launch_fallback(int model, int aniso, const StepArgs<float> &a, const
     case 1: return fb_m<kin::Barkley<float>>(aniso, a, su, s);
     case 3: return fb_m<kin::Fhn<float>>(aniso, a, su, s);
     case 4: return a.tab ? fb_m<kin::CrnTab>(aniso, a, su, s) : fb_m<kin::Crn<float>>(aniso, a, su, s);
+    case 6: return fb_m<kin::Tp06<float>>(aniso, a, su, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -823,6 +825,8 @@ hipError_t launch_ionic_map(int model, const StepArgs<float> &a, int nvar, const
         if (a.tab) hipLaunchKernelGGL(k_ionic<kin::CrnTab>, grid, block, 0, s, a, in, n, out);
         else hipLaunchKernelGGL(k_ionic<kin::Crn<float>>, grid, block, 0, s, a, in, n, out);
         break;
+    case 5: hipLaunchKernelGGL(k_ionic<kin::Fk4<float>>, grid, block, 0, s, a, in, n, out); break;
+    case 6: hipLaunchKernelGGL(k_ionic<kin::Tp06<float>>, grid, block, 0, s, a, in, n, out); break;
     default: return hipErrorInvalidValue;
     }
     (void)nvar;

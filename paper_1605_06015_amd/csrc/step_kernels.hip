@@ -185,6 +185,7 @@ hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s
             if (a.tab) return launch_m<float, kin::CrnTab>(aniso, a, s);
         return launch_m<T, kin::Crn<T>>(aniso, a, s);
     case 5: return launch_m<T, kin::Fk4<T>>(aniso, a, s);
+    case 6: return launch_m<T, kin::Tp06<T>>(aniso, a, s);
     default: return hipErrorInvalidValue;
     }
 }

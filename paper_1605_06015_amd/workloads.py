@@ -30,6 +30,15 @@ CRN_INITIAL = (-81.18, 11.17, 139.0, 1.013e-4, 1.488, 1.488, 2.908e-3, 0.9649, 0
 # --------------------------------------------------------------------------
 # Barkley 2D: 100x100, cross-field initial condition + seeded uniform noise
 # --------------------------------------------------------------------------
+# Published initial state of the ten Tusscher-Panfilov (2006) ventricular model,
+# epicardial cell, in the state order V, K_i, Na_i, Ca_i, Ca_ss, Ca_SR, Rbar, Xr1,
+# Xr2, Xs, m, h, j, d, f, f2, fCass, s, r.
+TP06_NAMES = ("V", "Ki", "Nai", "Cai", "Cass", "CaSR", "Rbar", "Xr1", "Xr2", "Xs", "m", "h",
+              "j", "d", "f", "f2", "fCass", "s", "r")
+TP06_INITIAL = (-85.23, 136.89, 8.604, 0.000126, 0.00036, 3.64, 0.9073, 0.00621, 0.4712,
+                0.0095, 0.00172, 0.7444, 0.7045, 3.373e-5, 0.7888, 0.9755, 0.9953, 0.999998,
+                2.42e-8)
+
 BARKLEY_2D = dict(nx=100, ny=100, nz=1, h=0.2, dt=0.008, D=1.0, a=0.75, b=0.02, eps=0.02,
                   steps=2000)
 
@@ -210,3 +219,136 @@ def fk4_ensemble(n=96, side_lo=64, side_hi=768, seed=4, h=0.25, Dpar=0.1171, ani
         stims.append((i, 0, s // 2, 0, s // 2, s1_amp, float(np.round(t2, 1)), s1_ms))
     return dict(nx=sides.copy(), ny=sides.copy(), Dpar=Dp, Dperp=Dq, angle=angle,
                 params=params, stims=stims, h=h)
+
+
+# ---------------------------------------------------------------- biventricular-like double shell
+def _ellipsoid_s(x, y, z, h, axes, centre):
+    X = (x + 0.5) * h - centre[0]
+    Y = (y + 0.5) * h - centre[1]
+    Z = (z + 0.5) * h - centre[2]
+    return np.sqrt((X / axes[0]) ** 2 + (Y / axes[1]) ** 2 + (Z / axes[2]) ** 2), X, Y, Z
+
+
+def double_shell(nx=512, ny=512, nz=384, h=0.2, active_frac=0.25, seed=5, tol=0.005,
+                 rv_ratio=0.45, with_fibres=True):
+    """Bi-ventricular-like tissue: two half-ellipsoidal shells with their bases on the top z
+    face.  The left shell (outer semi-axes about (0.30, 0.36, 0.95) of the box, seeded
+    +-5%) has a wall of relative thickness tau; the right shell (about (0.44, 0.46, 0.85),
+    centred further along x) wraps it with a wall of relative thickness rv_ratio * tau and
+    keeps only what lies outside the left shell.  tau is found by bisection so that the
+    active fraction is active_frac +- tol.  Fibres rotate from -60 to +60 degrees through
+    each wall (transmural depth from the shell's own inner to outer surface).  Built slab
+    by slab along z to bound host memory.
+
+    Returns dict(mask, fibre (None unless with_fibres), tau, lv=(axes, centre),
+    rv=(axes, centre), apex (mm, of the left shell))."""
+    rng = np.random.default_rng(seed)
+    L = np.array([nx * h, ny * h, nz * h])
+    j = 1.0 + rng.uniform(-0.05, 0.05, 6)
+    lv_ax = np.array([0.30, 0.36, 0.95]) * L * j[:3]
+    lv_c = np.array([0.40, 0.50, 1.0]) * L
+    rv_ax = np.array([0.44, 0.46, 0.85]) * L * j[3:]
+    rv_c = np.array([0.54, 0.50, 1.0]) * L
+    # keep both shells inside the box
+    lv_ax = np.minimum(lv_ax, [min(lv_c[0], L[0] - lv_c[0]) - h, 0.5 * L[1] - h, L[2] - h])
+    rv_ax = np.minimum(rv_ax, [min(rv_c[0], L[0] - rv_c[0]) - h, 0.5 * L[1] - h, L[2] - h])
+    y2, x2 = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    s_lv = np.empty((nz, ny, nx), np.float32)
+    s_rv = np.empty((nz, ny, nx), np.float32)
+    for z in range(nz):
+        s_lv[z] = _ellipsoid_s(x2, y2, z, h, lv_ax, lv_c)[0]
+        s_rv[z] = _ellipsoid_s(x2, y2, z, h, rv_ax, rv_c)[0]
+
+    def tissue(tau, zs=slice(None)):
+        a, b = s_lv[zs], s_rv[zs]
+        lv = (a <= 1.0) & (a >= 1.0 - tau)
+        rv = (b <= 1.0) & (b >= 1.0 - rv_ratio * tau) & (a > 1.0)
+        return lv, rv
+
+    target = active_frac * s_lv.size
+    lo, hi = 0.0, 1.0
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        cnt = 0
+        for z0 in range(0, nz, 32):
+            lv, rv = tissue(mid, slice(z0, z0 + 32))
+            cnt += np.count_nonzero(lv) + np.count_nonzero(rv)
+        if cnt < target:
+            lo = mid
+        else:
+            hi = mid
+    tau = 0.5 * (lo + hi)
+    mask = np.zeros((nz, ny, nx), np.uint8)
+    fibre = np.zeros((nz, ny, nx, 3), np.float64) if with_fibres else None
+    for z in range(nz):
+        lv, rv = tissue(tau, z)
+        mask[z] = lv | rv
+        if with_fibres and mask[z].any():
+            for sel, ax, c, s, th in ((lv, lv_ax, lv_c, s_lv[z], tau), (rv, rv_ax, rv_c, s_rv[z], rv_ratio * tau)):
+                if not sel.any():
+                    continue
+                _, X, Y, Z = _ellipsoid_s(x2[sel], y2[sel], z, h, ax, c)
+                e = (s[sel].astype(np.float64) - (1.0 - th)) / th
+                fibre[z][sel] = _fibres_from_normal(X / ax[0] ** 2, Y / ax[1] ** 2,
+                                                    np.broadcast_to(Z / ax[2] ** 2, X.shape), e)
+    frac = mask.mean()
+    if abs(frac - active_frac) > tol:
+        raise RuntimeError(f"double_shell: active fraction {frac:.4f} misses {active_frac}")
+    apex = lv_c - np.array([0.0, 0.0, lv_ax[2]])
+    return dict(mask=mask, fibre=fibre, tau=tau, lv=(lv_ax, lv_c), rv=(rv_ax, rv_c), apex=apex)
+
+
+def region_near_slabs(mask, h, point_mm, radius_mm):
+    """region_near computed one z plane at a time (for large boxes)."""
+    nz, ny, nx = mask.shape
+    y2, x2 = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    out = np.zeros_like(mask)
+    for z in range(nz):
+        dz2 = ((z + 0.5) * h - point_mm[2]) ** 2
+        if dz2 > radius_mm ** 2:
+            continue
+        d2 = ((x2 + 0.5) * h - point_mm[0]) ** 2 + ((y2 + 0.5) * h - point_mm[1]) ** 2 + dz2
+        out[z] = (d2 <= radius_mm ** 2) & (mask[z] != 0)
+    return out
+
+
+# The 3D TP06 workload: 512x512x384 biventricular-like double shell at 25% active,
+# h 0.2 mm, dt 0.02 ms, D_par 0.3 / D_perp 0.03 mm^2/ms, 1 s.  Scroll-wave
+# initiation: S1 within 3 mm of the left shell's apex at t = 0; S2 on the tissue of
+# the half y < Ly/2 above mid-height at t = 320 ms (after the S1 wave back has passed
+# through most of the walls).  Eight pseudo-ECG electrodes 20 mm outside the box.
+TP06_3D = dict(nx=512, ny=512, nz=384, h=0.2, dt=0.02, Dpar=0.3, Dperp=0.03, active=0.25,
+               seed=5, theta=-40.0, s1_amp=60.0, s1_ms=2.0, s1_radius=3.0, s2_amp=60.0,
+               s2_t=320.0, s2_ms=2.0, t_end=1000.0, ecg_every_ms=1.0)
+
+
+def tp06_biv(nx=512, ny=512, nz=384, h=0.2, seed=5, active=0.25, s1_radius=3.0,
+             with_fibres=True):
+    """Geometry, stimulus regions and electrodes of the 3D TP06 workload."""
+    g = double_shell(nx, ny, nz, h, active, seed, with_fibres=with_fibres)
+    mask = g["mask"]
+    s1 = region_near_slabs(mask, h, g["apex"], s1_radius)
+    if s1.sum() == 0:
+        raise RuntimeError("tp06_biv: empty S1 region")
+    s2 = np.zeros_like(mask)
+    s2[nz // 2:, : ny // 2, :] = mask[nz // 2:, : ny // 2, :]
+    L = np.array([nx, ny, nz]) * h
+    c = 0.5 * L
+    d = 20.0
+    electrodes = np.array([[-d, c[1], c[2]], [L[0] + d, c[1], c[2]], [c[0], -d, c[2]],
+                           [c[0], L[1] + d, c[2]], [c[0], c[1], -d], [c[0], c[1], L[2] + d],
+                           [-d, -d, c[2]], [L[0] + d, L[1] + d, -d]])
+    g.update(s1=s1, s2=s2, electrodes=electrodes)
+    return g
+
+
+def tp06_cup(nx, ny, nz, seed=5, active=0.35, h=0.25):
+    """A small TP06 test tissue: the ellipsoidal cup with an apex stimulus region and the
+    published epicardial initial state."""
+    g = cup_shell(nx, ny, nz, h, active, seed)
+    stim = region_near(g["mask"], h, g["apex"], 1.0)
+    if stim.sum() == 0:
+        raise RuntimeError("tp06_cup: empty stimulus region")
+    state = np.stack([np.full(g["mask"].shape, v) for v in TP06_INITIAL])
+    g.update(stim=stim, state=state)
+    return g

@@ -1,0 +1,191 @@
+"""ten Tusscher-Panfilov 2006 kinetics and the FP64 pseudo-ECG reduction on the GPU
+against the FP64 oracle: small tissues element by element, and the full 512x512x384
+biventricular-like workload on voxels sampled with the oracle run on crops around
+them (a voxel's value after k steps depends only on voxels within k of it, plus
+the fibres one further)."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1605_06015_amd import workloads as WL
+from parity_util import Problem, gpu_state, make_gpu, rec_arrays, rel_errs, run_oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+@pytest.fixture(scope="module")
+def B():
+    from paper_1605_06015_amd import bbx
+    return bbx
+
+
+def tp06_problem(nx, ny, nz, seed=5, dt=0.02, theta=None, h=0.25):
+    g = WL.tp06_cup(nx, ny, nz, seed=seed, h=h)
+    return Problem(g["mask"], h, g["fibre"], 0.3, 0.03, O.MODEL_TP06, [], dt, state=g["state"],
+                   stims=[(g["stim"], 60.0, 0.0, 2.0, 0.0, 1)], theta=theta)
+
+
+def test_tp06_small_cup_fp64_through_upstroke():
+    p = tp06_problem(24, 24, 12)
+    s = run_oracle(p, 600, nthreads=8)
+    g = make_gpu(p, 1)
+    g.step(600)
+    e = rel_errs(gpu_state(g, 19), s.state, p.mask)
+    assert np.all(e <= TOL64), e
+    assert s.state[0][p.mask == 1].max() > 0.0          # the tissue near the apex is excited
+
+
+def test_tp06_fp32_within_0p5mV_and_1dt():
+    p = tp06_problem(24, 24, 12, theta=-40.0)
+    s = run_oracle(p, 0, nthreads=8)
+    g = make_gpu(p, 0)
+    m = p.mask == 1
+    worst = 0.0
+    for _ in range(60):
+        s.step(50)
+        g.step(50)
+        worst = max(worst, np.abs(g.get(0)[m] - s.state[0][m]).max())
+    print("tp06 fp32 max |dV| (mV):", worst)
+    assert worst <= 0.5
+    ro = rec_arrays(s, p.mask)
+    at_g = g.read(1)
+    act_o = np.isfinite(ro["at"]) & m
+    assert np.array_equal(act_o, np.isfinite(at_g) & m)
+    assert act_o.sum() > 0.5 * m.sum()
+    assert np.abs(at_g[act_o] - ro["at"][act_o]).max() <= p.dt
+
+
+def ecg_cases():
+    cup = WL.cup_shell(20, 20, 10, 0.25, 0.35, 3)
+    bm, bf = WL.full_box_rotating(12, 10, 8)
+    blob = WL.random_blob_mask(14, 11, 9, seed=4)
+    return {"cup_rotating": (cup["mask"], cup["fibre"]),
+            "dense_rotating": (bm, bf),
+            "blob_isotropic": (blob, None)}
+
+
+@pytest.mark.parametrize("case", ["cup_rotating", "dense_rotating", "blob_isotropic"])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_ecg_matches_oracle(B, case, prec):
+    """The pseudo-ECG of a smooth random field, at electrodes around and inside the box
+    (off voxel centres): FP64 grids within 1e-12 of the oracle relative to the summed
+    term size; FP32 grids, on the FP32 field they hold, within 2e-6 (FP32 evaluation of
+    (L V)_p, FP64 sums)."""
+    mask, fib = ecg_cases()[case]
+    h = 0.25
+    nz, ny, nx = mask.shape
+    rng = np.random.default_rng(7)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    V = -80 + 40 * np.sin(0.4 * x + 0.3) * np.cos(0.3 * y) + 5 * np.sin(0.5 * z) + rng.uniform(-1, 1, mask.shape)
+    E = np.array([[-3.0, 1.1, 0.7], [nx * h + 2.0, ny * h / 2 + 0.13, 1.0], [1.37, 1.21, 1.11],
+                  [0.5 * nx * h + 0.1, -4.0, nz * h + 3.0]])
+    g = B.Grid(mask, h, fib, 0.3, 0.05, prec)
+    g.model(B.BBX_MODEL_NONE, [], 0.005)
+    g.set(0, V)
+    g.ecg(E)
+    got = g.ecg_now()
+    Vg = g.get(0)
+    Vg[mask == 0] = 0.0
+    want, S = O.pseudo_ecg(mask, h, fib, 0.3, 0.05, Vg, E, return_scale=True)
+    tol = 1e-12 if prec == 1 else 2e-6
+    assert np.all(np.abs(got - want) <= tol * S), (got, want, S)
+
+
+def test_ecg_series_sampling(B):
+    """every = 10: samples after steps 10, 20, ... of V at that step, bitwise equal to an
+    on-demand evaluation at the same step; capped at max_samples."""
+    p = tp06_problem(16, 16, 8, seed=8)
+    E = [[-2.0, 2.0, 1.0], [5.0, -3.0, 4.1]]
+    a = make_gpu(p, 0)
+    a.ecg(E, every=10, max_samples=5)
+    a.step(37)
+    ser = a.ecg_series()
+    assert ser.shape == (3, 2)
+    b = make_gpu(p, 0)
+    b.ecg(E)
+    for k in range(3):
+        b.step(10)
+        assert np.array_equal(b.ecg_now(), ser[k])
+    a.step(100)
+    assert a.ecg_series().shape == (5, 2)
+
+
+def test_ecg_errors(B):
+    p = tp06_problem(12, 12, 6, seed=8)
+    g = make_gpu(p, 0)
+    with pytest.raises(B.BBXError) as ex:
+        g.ecg_now()
+    assert ex.value.code == B.BBX_ESTATE
+    t = np.argwhere(p.mask == 1)[0]                       # (z, y, x) of a tissue voxel
+    with pytest.raises(B.BBXError) as ex:
+        g.ecg([[t[2] * p.h, t[1] * p.h, t[0] * p.h]])
+    assert ex.value.code == B.BBX_EINVAL
+    with pytest.raises(B.BBXError) as ex:
+        g.ecg(np.ones((17, 3)) * -5.0)
+    assert ex.value.code == B.BBX_EINVAL
+
+
+def crop_oracle(g3, state0, stims, c, r, nsteps, dt):
+    """Oracle run of `nsteps` on the crop of radius r around voxel c = (z, y, x)."""
+    mask = g3["mask"]
+    sl = tuple(slice(max(0, c[i] - r), min(mask.shape[i], c[i] + r + 1)) for i in range(3))
+    m = np.ascontiguousarray(mask[sl])
+    f = np.ascontiguousarray(g3["fibre"][sl])
+    s = O.Sim(m, WL.TP06_3D["h"], f, WL.TP06_3D["Dpar"], WL.TP06_3D["Dperp"], O.MODEL_TP06, [], dt)
+    for v in range(19):
+        s.state[v] = state0[v]
+    for (reg, amp, n0, ln) in stims:
+        s.stimuli.append(O.Stimulus(np.ascontiguousarray(reg[sl]), amp, n0, ln))
+    s.step(nsteps)
+    loc = tuple(c[i] - sl[i].start for i in range(3))
+    return s.state[(slice(None),) + loc]
+
+
+def test_tp06_full_size_sampled(B):
+    """The 512x512x384 double shell (25.2 M tissue voxels), FP32, in the benchmark's
+    launch configuration: after 3 steps with S1 on, 48 sampled tissue voxels (half in
+    the S1 region) match the oracle run on crops around them (|dV| <= 1e-3 mV, gates
+    <= 1e-5, concentrations <= 1e-5 relative); the pseudo-ECG of the resulting field
+    matches the oracle's (chunked over the whole tissue) within 2e-6 of the term size."""
+    c = WL.TP06_3D
+    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_radius"])
+    g = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32)
+    g.model(B.BBX_MODEL_TP06, [], c["dt"])
+    for v, val in enumerate(WL.TP06_INITIAL):
+        g.fill(v, val)
+    g.stimulus(g3["s1"], c["s1_amp"], 0.0, c["s1_ms"])
+    g.stimulus(g3["s2"], c["s2_amp"], c["s2_t"], c["s2_ms"])
+    g.nan_check(0)
+    g.step(3)
+    rng = np.random.default_rng(0)
+    tis = np.argwhere(g3["mask"] == 1)
+    s1 = np.argwhere(g3["s1"] == 1)
+    picks = np.concatenate([tis[rng.integers(0, len(tis), 24)], s1[rng.integers(0, len(s1), 24)]])
+    stims = [(g3["s1"], c["s1_amp"], 0, int(round(c["s1_ms"] / c["dt"]))),
+             (g3["s2"], c["s2_amp"], int(round(c["s2_t"] / c["dt"])), int(round(c["s2_ms"] / c["dt"])))]
+    pick_idx = tuple(picks.T)
+    vals = np.empty((19, len(picks)))
+    V = None
+    for v in range(19):                                   # one box array at a time
+        arr = g.get(v)
+        vals[v] = arr[pick_idx]
+        if v == 0:
+            V = arr
+        del arr
+    for k, p in enumerate(picks):
+        p = tuple(int(i) for i in p)
+        ref = crop_oracle(g3, WL.TP06_INITIAL, stims, p, 4, 3, c["dt"])
+        got = vals[:, k]
+        assert abs(got[0] - ref[0]) <= 1e-3, (p, got[0], ref[0])
+        assert np.all(np.abs(got[7:] - ref[7:]) <= 1e-5), p
+        assert np.all(np.abs(got[1:7] - ref[1:7]) <= 1e-5 * np.abs(ref[1:7]) + 1e-12), p
+    E = g3["electrodes"]
+    g.ecg(E)
+    phi = g.ecg_now()
+    V[g3["mask"] == 0] = 0.0
+    want, S = O.pseudo_ecg(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], V, E,
+                           return_scale=True)
+    assert np.all(S > 0)
+    assert np.all(np.abs(phi - want) <= 2e-6 * S), (phi, want, S)

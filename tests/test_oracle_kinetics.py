@@ -327,3 +327,58 @@ def test_fk4_tau_parameters_act():
     base = apd(FK4_EPI)
     assert apd([0.11, 30.0181 * 0.8, 1.8875, 200.0]) < base     # stronger repolarising current
     assert apd([0.11, 30.0181, 1.8875 * 0.8, 200.0]) > base     # stronger depolarising current
+
+
+# ------------------------------------------------ ten Tusscher-Panfilov 2006
+def tp06_cell(dt=0.02, stim=None):
+    s = cell(O.MODEL_TP06, [], WL.TP06_INITIAL, dt, stim)
+    return s
+
+
+def test_tp06_resting_state_is_steady():
+    """The published epicardial initial state is close to rest: the net current is small
+    and V stays within 0.5 mV of it over 100 ms without stimulus."""
+    rate, inf, tau = O.model_eval(O.MODEL_TP06, [], np.array(WL.TP06_INITIAL))
+    assert abs(rate[0]) < 0.01
+    for i in (7, 9, 10, 11, 13, 17, 18):                # fast gates at (near) steady state
+        assert abs(WL.TP06_INITIAL[i] - inf[i]) < 0.01, (WL.TP06_NAMES[i], inf[i])
+    s = tp06_cell()
+    s.step(5000)
+    assert abs(s.state[0, 0, 0, 0] - WL.TP06_INITIAL[0]) < 0.5
+
+
+def test_tp06_action_potential_shape():
+    """1 ms, 52 pA/pF stimulus (the model publication's protocol): overshoot, APD90 and the
+    calcium transient in the ranges that publication reports for epicardial cells."""
+    s = tp06_cell(stim=[O.Stimulus(ONE, 52.0, 0, 50)])
+    s.start_recording(-40.0)
+    V, Ca = [], []
+    for _ in range(3000):
+        s.step(10)
+        V.append(s.state[0, 0, 0, 0])
+        Ca.append(s.state[3, 0, 0, 0])
+    V, Ca = np.array(V), np.array(Ca)
+    assert 30.0 < V.max() < 45.0
+    assert 260.0 < s.rec.apd[0] < 320.0                 # measured 290 ms
+    assert 0.5e-3 < Ca.max() < 1.5e-3
+    assert -86.5 < V[-1] < -84.5
+    assert s.rec.status[0] == 3 and s.rec.at[0] < 2.0
+
+
+def tp06_state(V):
+    y = np.array(WL.TP06_INITIAL, float)
+    y[0] = V
+    return y
+
+
+@pytest.mark.parametrize("Vs", [15.0, -40.0])
+def test_tp06_removable_singularity_and_branch(Vs):
+    """The L-type current's 0/0 at V = 15 mV is continuous; the h/j rate branches at
+    -40 mV join without a gap in the rates that matter at that voltage."""
+    r0, i0, t0 = O.model_eval(O.MODEL_TP06, [], tp06_state(Vs))
+    for dlt in (1e-7, 1e-5):
+        rm, _, _ = O.model_eval(O.MODEL_TP06, [], tp06_state(Vs - dlt))
+        rp, _, _ = O.model_eval(O.MODEL_TP06, [], tp06_state(Vs + dlt))
+        if Vs == 15.0:
+            assert abs(r0[0] - 0.5 * (rm[0] + rp[0])) < 1e-6 * max(1.0, abs(r0[0]))
+    assert np.all(np.isfinite(r0)) and np.all(np.isfinite(t0[7:])) and np.all(t0[7:] > 0)
