@@ -170,35 +170,42 @@ def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / sec / 1e9
 
 
-def surrogate_line(stream, t_ms=500.0, iters=20000, v_hi=-75.0):
-    """Surrogate-with-fallback on the same CRN workload: train on paced runs of the cup
-    (outside the timed region), anchor the resting state, then time a full run with the
-    plain FP32 kinetics and with the surrogate accepting tissue below v_hi mV, and
-    compare activation-time and APD90 maps."""
+def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000, v_hi=-81.0):
+    """Surrogate-with-fallback on the 128x128x64 cup with `model` kinetics: train on paced
+    runs of the cup (outside the timed region), anchor the resting state, then time a full
+    run with the plain FP32 kinetics and with the surrogate accepting tissue below v_hi mV,
+    and compare activation-time and APD90 maps."""
     import torch
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import surrogate as SU
+    mid, nv, c, geo, rest, amp, dur = SU._model_setup(model)
     t0 = time.perf_counter()
-    S, S1 = SU.generate_pairs(runs=3, t_ms=1200.0, per_sample=2048, seed=2, stream=stream)
+    S, S1 = SU.generate_pairs(runs=3, t_ms=1200.0, per_sample=2048, seed=2, stream=stream, model=model)
     t1 = time.perf_counter()
     anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32, stream)
-    anchor.model(B.BBX_MODEL_CRN, [], 0.01)
-    tr = SU.train(S, S1, iters=iters, batch=4096, lr=1e-3, seed=0, stream=stream, anchor_grid=anchor)
+    anchor.model(mid, [], c["dt"])
+    tr = SU.train(S, S1, iters=iters, batch=4096, lr=1e-3, seed=0, stream=stream, anchor_grid=anchor,
+                  model=model)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del S, S1
-    c_dt = 0.01
-    nsteps = int(round(t_ms / c_dt))
+    nsteps = int(round(t_ms / c["dt"]))
+    g = geo(128, 128, 64, seed=c["seed"], active=c["active"], h=c["h"])
+    m = g["mask"] == 1
     res = {}
     for name in ("plain", "surrogate"):
-        grid, g = crn_workload(B.BBX_FP32, stream)
+        grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
+        grid.model(mid, [], c["dt"])
+        for v in range(nv):
+            grid.set(v, g["state"][v])
+        grid.stimulus(g["stim"], amp, 0.0, dur)
+        grid.record(-40.0)
         grid.nan_check(0)
         if name == "surrogate":
-            lo, hi, dv = SU.accepted_box(tr.stats)
+            lo, hi, dv = SU.accepted_box(tr.stats, nvar=nv)
             hi[0] = v_hi                      # the network handles tissue below v_hi only
             grid.surrogate(tr.mlp, lo, hi, dv)
         sec = time_steps(grid, stream, nsteps, 0)
-        m = g["mask"] == 1
         res[name] = dict(sec=sec, at=grid.read(B.BBX_READ_ACT_TIME)[m], apd=grid.read(B.BBX_READ_APD90)[m],
                          fb=int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]), nact=grid.nact)
         grid.close()
@@ -208,15 +215,16 @@ def surrogate_line(stream, t_ms=500.0, iters=20000, v_hi=-75.0):
     bapd = np.isfinite(p["apd"]) & np.isfinite(q["apd"])
     dapd = np.abs(p["apd"][bapd] - q["apd"][bapd])
     value = q["nact"] * nsteps / q["sec"]
-    return {"workload": f"CRN cup 128x128x64, {t_ms:.0f} ms, FP32, surrogate 21-128-128-21 SiLU "
-                        "(BF16 MFMA, FP32 accumulate) with per-voxel fallback",
+    return {"workload": f"{model.upper()} cup 128x128x64, {t_ms:.0f} ms, FP32, surrogate {nv}-128-128-{nv} "
+                        "SiLU (BF16 MFMA, FP32 accumulate) with per-voxel fallback",
             "value": value, "unit": "voxel-updates/s", "ms_per_step": q["sec"] / nsteps * 1e3,
+            "plain_ms_per_step": p["sec"] / nsteps * 1e3,
             "accepted_v_below_mV": v_hi,
             "speedup_vs_plain": p["sec"] / q["sec"],
             "fallback_fraction": q["fb"] / (q["nact"] * nsteps),
             "at_err_vs_plain_ms": {"max": float(dat.max()) if dat.size else None,
                                    "mean": float(dat.mean()) if dat.size else None,
-                                   "dt": c_dt, "activated_plain": int(np.isfinite(p["at"]).sum()),
+                                   "dt": c["dt"], "activated_plain": int(np.isfinite(p["at"]).sum()),
                                    "activated_surrogate": int(np.isfinite(q["at"]).sum())},
             "apd90_err_vs_plain_ms": {"max": float(dapd.max()) if dapd.size else None,
                                       "mean": float(dapd.mean()) if dapd.size else None,
@@ -459,7 +467,8 @@ def main():
         out["stencil_roofline"] = stencil_roofline(stream)
         out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
         out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
-        out["surrogate"] = surrogate_line(stream, t_ms=args.sur_ms)
+        out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms, v_hi=-81.0)
+        out["surrogate_tp06"] = surrogate_line(stream, "tp06", t_ms=args.sur_ms, v_hi=-85.0)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -26,27 +26,38 @@ class Trained:
     npairs: int
 
 
+def _model_setup(model):
+    """(model id, nvar, workload dict, geometry, resting state) of a surrogate workload."""
+    if model == "crn":
+        c = WL.CRN_3D
+        return B.BBX_MODEL_CRN, 21, c, WL.crn_cup, WL.CRN_INITIAL, c["stim_amp"], c["stim_ms"]
+    if model == "tp06":
+        c = dict(WL.CRN_3D, dt=0.02, stim_amp=60.0, stim_ms=2.0)
+        return B.BBX_MODEL_TP06, 19, c, WL.tp06_cup, WL.TP06_INITIAL, 60.0, 2.0
+    raise ValueError(f"no surrogate workload for model {model!r}")
+
+
 def generate_pairs(nx=128, ny=128, nz=64, runs=3, t_ms=1200.0, every_ms=1.0, per_sample=2048,
-                   cl_range=(250.0, 1000.0), seed=2, stream=None):
-    """States of the 3D CRN cup paced from the apex at seeded cycle lengths, sampled
-    every `every_ms` at `per_sample` random tissue voxels, and their plain kinetic
-    one-step images.  Returns device tensors S, S1 of shape (N, 21) (FP32)."""
+                   cl_range=(250.0, 1000.0), seed=2, stream=None, model="crn"):
+    """States of the 3D cup (CRN or TP06 kinetics) paced from the apex at seeded cycle
+    lengths, sampled every `every_ms` at `per_sample` random tissue voxels, and their
+    plain kinetic one-step images.  Returns device tensors S, S1 of shape (N, nvar) (FP32)."""
     import torch
-    c = WL.CRN_3D
+    mid, nv, c, geo, _, amp, dur = _model_setup(model)
     rng = np.random.default_rng(seed)
-    g0 = WL.crn_cup(nx, ny, nz, seed=c["seed"], active=c["active"], h=c["h"])
+    g0 = geo(nx, ny, nz, seed=c["seed"], active=c["active"], h=c["h"])
     nsamp = int(round(t_ms / every_ms))
-    S = torch.empty((runs * nsamp * per_sample, 21), dtype=torch.float32, device="cuda")
+    S = torch.empty((runs * nsamp * per_sample, nv), dtype=torch.float32, device="cuda")
     S1 = torch.empty_like(S)
     k = 0
     every = int(round(every_ms / c["dt"]))
     for r in range(runs):
         cl = float(rng.uniform(*cl_range))
         grid = B.Grid(g0["mask"], c["h"], g0["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
-        grid.model(B.BBX_MODEL_CRN, [], c["dt"])
-        for v in range(21):
+        grid.model(mid, [], c["dt"])
+        for v in range(nv):
             grid.set(v, g0["state"][v])
-        grid.stimulus(g0["stim"], c["stim_amp"], 0.0, c["stim_ms"], period=cl, count=0)
+        grid.stimulus(g0["stim"], amp, 0.0, dur, period=cl, count=0)
         grid.nan_check(0)
         for i in range(nsamp):
             grid.step(every)
@@ -59,16 +70,18 @@ def generate_pairs(nx=128, ny=128, nz=64, runs=3, t_ms=1200.0, every_ms=1.0, per
     return S[:k], S1[:k]
 
 
-def train(S, S1, iters=20000, batch=4096, lr=1e-3, seed=0, stream=None, anchor_grid=None):
-    """Fit the normalisation and train a 21 -> 128 -> 128 -> 21 network.  If
-    anchor_grid is given (a grid with the plain CRN kinetics), the network is
+def train(S, S1, iters=20000, batch=4096, lr=1e-3, seed=0, stream=None, anchor_grid=None,
+          model="crn"):
+    """Fit the normalisation and train an nvar -> 128 -> 128 -> nvar network.  If
+    anchor_grid is given (a grid with the plain kinetics of `model`), the network is
     anchored so that the published resting state is an exact fixed point."""
     import torch
-    m = B.Mlp(21, 21, seed=seed, stream=stream)
+    _, nv, _, _, rest, _, _ = _model_setup(model)
+    m = B.Mlp(nv, nv, seed=seed, stream=stream)
     stats = m.fit_norm(S, S1)
     hist = m.train(S, S1, batch, iters, lr, seed=seed + 1)
     if anchor_grid is not None:
-        s0 = torch.tensor([WL.CRN_INITIAL], dtype=torch.float32, device="cuda")
+        s0 = torch.tensor([rest], dtype=torch.float32, device="cuda")
         s1 = torch.empty_like(s0)
         anchor_grid.ionic_map(s0, s1)
         torch.cuda.synchronize()
@@ -76,11 +89,11 @@ def train(S, S1, iters=20000, batch=4096, lr=1e-3, seed=0, stream=None, anchor_g
     return Trained(m, stats, hist, int(S.shape[0]))
 
 
-def accepted_box(stats, margin=0.02, dv_cap=None):
+def accepted_box(stats, margin=0.02, dv_cap=None, nvar=21):
     """Accepted kinetic inputs: the training range widened by `margin` of its width;
     |dV| up to the training maximum (or dv_cap if smaller)."""
-    lo = stats[2, :21].copy()
-    hi = stats[3, :21].copy()
+    lo = stats[2, :nvar].copy()
+    hi = stats[3, :nvar].copy()
     # a feature that barely varied in training still gets a box of 1e-3 of its size
     w = np.maximum(hi - lo, 1e-3 * np.maximum(np.abs(lo), np.abs(hi)))
     w = np.maximum(w, 1e-12)
@@ -93,6 +106,6 @@ def accepted_box(stats, margin=0.02, dv_cap=None):
 
 
 def attach(grid, trained, margin=0.02, dv_cap=None):
-    lo, hi, dv = accepted_box(trained.stats, margin, dv_cap)
+    lo, hi, dv = accepted_box(trained.stats, margin, dv_cap, trained.mlp.nin)
     grid.surrogate(trained.mlp, lo, hi, dv)
     return lo, hi, dv

@@ -250,3 +250,47 @@ def test_training_pipeline_and_gain(env):
     print("surrogate share of voxel updates", share, "AT err mean/max (ms)", err.mean(), err.max())
     assert 0.05 < share < 1.0
     assert err.max() < 2.0
+
+
+def test_tp06_surrogate_pipeline(env):
+    """The same pipeline with TP06 kinetics (19 variables): trained loss well below the
+    mean-increment predictor, all-fallback equals the plain TP06 step bitwise, and the
+    attached network takes a share of the updates with activation times kept close."""
+    B, torch = env
+    from paper_1605_06015_amd import surrogate as SU
+    S, S1 = SU.generate_pairs(nx=40, ny=40, nz=20, runs=1, t_ms=400.0, per_sample=1024, seed=4,
+                              model="tp06")
+    assert S.shape[1] == 19
+    anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32)
+    anchor.model(B.BBX_MODEL_TP06, [], 0.02)
+    tr = SU.train(S, S1, iters=3000, batch=4096, lr=1e-3, seed=0, anchor_grid=anchor, model="tp06")
+    final = float(np.mean(tr.loss[-50:]))
+    print("tp06 training loss final", final)
+    assert final < 0.05
+    g0 = WL.tp06_cup(40, 40, 20, seed=1)
+    runs = {}
+    for name in ("plain", "all_fallback", "surrogate"):
+        g = B.Grid(g0["mask"], 0.25, g0["fibre"], 0.3, 0.03, B.BBX_FP32)
+        g.model(B.BBX_MODEL_TP06, [], 0.02)
+        for v in range(19):
+            g.set(v, g0["state"][v])
+        g.stimulus(g0["stim"], 60.0, 0.0, 2.0)
+        g.record(-40.0)
+        if name == "all_fallback":
+            g.surrogate(tr.mlp, np.full(19, 1.0), np.full(19, -1.0), 1e9)
+        if name == "surrogate":
+            lo, hi, dv = SU.accepted_box(tr.stats, nvar=19)
+            hi[0] = -84.0
+            g.surrogate(tr.mlp, lo, hi, dv)
+        g.step(3000)
+        runs[name] = (gpu_state(g, 19), g.read(B.BBX_READ_ACT_TIME), g.read(B.BBX_READ_FALLBACK_COUNT)[0], g.nact)
+    assert np.array_equal(runs["plain"][0], runs["all_fallback"][0], equal_nan=True)
+    at_p, at_s = runs["plain"][1], runs["surrogate"][1]
+    m = g0["mask"] == 1
+    both = np.isfinite(at_p) & np.isfinite(at_s) & m
+    assert both.sum() > 0.9 * m.sum()
+    err = np.abs(at_p[both] - at_s[both])
+    share = 1.0 - runs["surrogate"][2] / (3000 * runs["surrogate"][3])
+    print("tp06 surrogate share", share, "AT err mean/max (ms)", err.mean(), err.max())
+    assert 0.02 < share < 1.0
+    assert err.max() < 2.0
