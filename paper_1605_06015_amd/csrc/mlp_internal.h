@@ -44,6 +44,8 @@ struct SurArgs {
     float dv_max;                    // largest accepted |dV| per step
     int32_t *fb_list;                // [nact] voxels falling back this step
     int32_t *fb_cnt;                 // [2] list lengths, alternating per step
+    int32_t *acc_list;               // [nact] voxels whose input the network accepts
+    int32_t *acc_cnt;                // [2] list lengths, alternating per step
     unsigned long long *fb_total;    // running count of fallbacks
     int parity;
 };

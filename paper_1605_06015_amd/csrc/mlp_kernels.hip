@@ -586,19 +586,64 @@ hipError_t mlp_anchor(const MlpDev &d, const float *s0, const float *s1, float *
 uint64_t mlp_mix64(uint64_t z) { return mix64(z); }
 
 // ------------------------------------------------------- surrogate step
-// Fused step with the network as kinetics (FP32).  One persistent workgroup per
-// CU stages the weights in LDS once and walks chunks of kSurBlock tissue voxels
-// (one per thread).  Each thread computes its Laplacian and stimulus,
-// the kinetic input s = (V or V* = V + dt LV, g) and its normalised form, which
-// goes to the wave's LDS staging rows; each wave then runs the network on its
-// 64 voxels as four 16-sample tiles, writes the outputs back to the staging
-// rows, and each thread applies or rejects its prediction.  Rejected voxels
-// (input outside [lo, hi], gate outside [0, 1], |dV| > dv_max, non-finite) are
-// appended to the fallback list and left untouched for the plain kernel.
-// Accepted gate predictions within kGateTol of [0, 1] are clamped into it.
+// A surrogate step is three launches.  (1) k_sur_classify, one thread per tissue
+// voxel: voxels whose kinetic input s = (V or V* = V + dt LV, g) lies in the
+// accepted box [lo, hi] are appended to the network list; every other voxel gets
+// the plain update right there (the plain step's own arithmetic).  (2) k_sur_net:
+// one persistent workgroup per CU stages the weights in LDS once and walks the
+// network list in chunks of kSurBlock voxels (one per thread): each thread
+// recomputes its Laplacian and stimulus and writes its normalised input to the
+// wave's LDS staging rows; the wave runs the network on its 64 voxels as four
+// 16-sample tiles, and each thread applies or rejects its prediction (gate
+// outside [0, 1], |dV| > dv_max, non-finite); rejected voxels go to the fallback
+// list.  Accepted gate predictions within kGateTol of [0, 1] are clamped into it.
+// (3) k_fallback: the plain update of the fallback list.  The network's cost is
+// thus paid only for the voxels it may take.
 template <class M, bool ANISO>
-__global__ __launch_bounds__(kSurBlock) void k_step_mlp(const StepArgs<float> a, const SurArgs su)
+__global__ __launch_bounds__(kBlock) void k_sur_classify(const StepArgs<float> a, const SurArgs su)
 {
+    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
+    if (lb >= a.nblk) return;                              // workgroup-uniform exit
+    const int t = lb * kBlock + (int)threadIdx.x;
+    const bool valid = t < a.nact;
+    int idx = 0;
+    uint32_t bits = 0;
+    float Vp = 0.f, LV = 0.f;
+    bool ok = false;
+    if (valid) {
+        voxel_of(a, t, idx, bits);
+        Vp = a.Vin[idx];
+        LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
+        const float s0 = a.split ? Vp + a.dt * LV : Vp;
+        ok = s0 >= su.lo[0] && s0 <= su.hi[0];
+#pragma unroll
+        for (int i = 1; i < M::NV; i++) {
+            const float y = a.st[(i - 1) * a.pitch + t];
+            ok = ok && y >= su.lo[i] && y <= su.hi[i];
+        }
+    }
+    // append the accepted voxels: one atomic per wave, slots by prefix count
+    const uint64_t acc = __ballot(ok);
+    if (acc) {
+        const int l = (int)threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)acc) - 1;
+        int base = 0;
+        if (l == leader) base = atomicAdd(&su.acc_cnt[su.parity], __popcll(acc));
+        base = __shfl(base, leader);
+        if (ok) {
+            const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(acc >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)acc, 0u));
+            su.acc_list[base + below] = t;
+        }
+    }
+    if (valid && !ok) update_voxel<float, M>(a, t, idx, Vp, LV);
+}
+
+template <class M, bool ANISO>
+__global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, const SurArgs su)
+{
+    const int n = su.acc_cnt[su.parity];
+    if ((int)blockIdx.x * kSurBlock >= n) return;         // nothing for this workgroup
     constexpr int NW = kSurBlock / 64;
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
     __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
@@ -611,13 +656,14 @@ __global__ __launch_bounds__(kSurBlock) void k_step_mlp(const StepArgs<float> a,
     const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
     const float *nrm = su.net.norm;
 
-    for (int lb = blockIdx.x; lb < a.nblk; lb += gridDim.x) {
-        const int t = lb * kSurBlock + (int)threadIdx.x;
-        const bool valid = t < a.nact;
+    for (int k0 = (int)blockIdx.x * kSurBlock; k0 < n; k0 += (int)gridDim.x * kSurBlock) {
+        const int k = k0 + (int)threadIdx.x;
+        const bool valid = k < n;
+        const int t = valid ? su.acc_list[k] : 0;
         int idx = 0;
         float Vp = 0.f, LV = 0.f, Is = 0.f;
         float s[NV] = {};
-        bool ok = valid;
+        bool ok = valid;                                   // the input box was checked
         __bf16 *xrow = xin[wv] + l * kS1;
         if (valid) {
             uint32_t bits;
@@ -628,8 +674,6 @@ __global__ __launch_bounds__(kSurBlock) void k_step_mlp(const StepArgs<float> a,
             s[0] = a.split ? Vp + a.dt * LV : Vp;
 #pragma unroll
             for (int i = 1; i < NV; i++) s[i] = a.st[(i - 1) * a.pitch + t];
-#pragma unroll
-            for (int i = 0; i < NV; i++) ok = ok && s[i] >= su.lo[i] && s[i] <= su.hi[i];
         }
         __syncthreads();                                       // previous chunk done with LDS
 #pragma unroll
@@ -721,8 +765,10 @@ __global__ __launch_bounds__(256) void k_fallback(const StepArgs<float> a, const
         update_voxel<float, M>(a, t, idx, Vp, LV);
     }
     if (gid == 0) {
+        // input-rejected voxels (updated by the classifier) plus output-rejected ones
+        *su.fb_total += (unsigned long long)(a.nact - su.acc_cnt[su.parity]) + (unsigned long long)n;
         su.fb_cnt[su.parity ^ 1] = 0;
-        *su.fb_total += (unsigned long long)n;
+        su.acc_cnt[su.parity ^ 1] = 0;
     }
 }
 
@@ -760,10 +806,14 @@ static hipError_t sur_m(int aniso, const StepArgs<float> &a, const SurArgs &su, 
     int dev = 0, ncu = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    const dim3 grid((unsigned)(a.nblk < ncu ? a.nblk : ncu)), block(kSurBlock);
-    if (a.nblk == 0) return hipSuccess;
-    if (aniso) hipLaunchKernelGGL((k_step_mlp<M, true>), grid, block, 0, s, a, su);
-    else hipLaunchKernelGGL((k_step_mlp<M, false>), grid, block, 0, s, a, su);
+    if (a.nact == 0) return hipSuccess;
+    const dim3 gc((unsigned)(a.per_xcd * kXcd)), bc(kBlock);
+    if (aniso) hipLaunchKernelGGL((k_sur_classify<M, true>), gc, bc, 0, s, a, su);
+    else hipLaunchKernelGGL((k_sur_classify<M, false>), gc, bc, 0, s, a, su);
+    const int nchunk = (int)((a.nact + kSurBlock - 1) / kSurBlock);
+    const dim3 grid((unsigned)(nchunk < ncu ? nchunk : ncu)), block(kSurBlock);
+    if (aniso) hipLaunchKernelGGL((k_sur_net<M, true>), grid, block, 0, s, a, su);
+    else hipLaunchKernelGGL((k_sur_net<M, false>), grid, block, 0, s, a, su);
     return hipGetLastError();
 }
 
