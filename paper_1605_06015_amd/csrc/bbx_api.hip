@@ -120,13 +120,12 @@ struct bbx_grid {
     double tab_dv = 0;                 // > 0: CRN voltage-only terms from a table
     float *d_tab = nullptr;
     int tab_n = 0;
-    // attached surrogate (FP32 grids): network copy, accepted box, fallback list
+    // attached surrogate (FP32 grids): network copy, accepted box, network list
     int sur = 0;
     MlpDev snet = {};
     float *d_slo = nullptr, *d_shi = nullptr;
     float dv_max = 0;
-    int32_t *d_fb_list = nullptr, *d_fb_cnt = nullptr;   // d_fb_cnt: [fallback x2 | accepted x2]
-    int32_t *d_acc_list = nullptr;
+    int32_t *d_acc_list = nullptr, *d_acc_cnt = nullptr;   // network list, lengths [2]
     unsigned long long *d_fb_total = nullptr;
     double *d_parts = nullptr, *d_red = nullptr;
     int *d_flag = nullptr;
@@ -162,7 +161,7 @@ void free_all(bbx_grid *g)
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
-                  g->d_fb_list, g->d_fb_cnt, g->d_acc_list, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
+                  g->d_acc_list, g->d_acc_cnt, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
                   g->snet.bias, g->snet.norm};
     for (void *p : ps) dfree(p);
 }
@@ -276,10 +275,8 @@ SurArgs sur_args(const bbx_grid *g, int parity)
     su.lo = g->d_slo;
     su.hi = g->d_shi;
     su.dv_max = g->dv_max;
-    su.fb_list = g->d_fb_list;
-    su.fb_cnt = g->d_fb_cnt;
     su.acc_list = g->d_acc_list;
-    su.acc_cnt = g->d_fb_cnt + 2;
+    su.acc_cnt = g->d_acc_cnt;
     su.fb_total = g->d_fb_total;
     su.parity = parity;
     return su;
@@ -306,7 +303,6 @@ int step_impl(bbx_grid *g, int64_t nsteps)
                     b.per_xcd = (b.nblk + kXcd - 1) / kXcd;
                     const SurArgs su = sur_args(g, (int)(n & 1));
                     HIP_TRY(launch_surrogate_step(g->model, g->aniso, b, su, g->stream), "surrogate step");
-                    HIP_TRY(launch_fallback(g->model, g->aniso, b, su, g->stream), "fallback");
                     done = true;
                 }
             }
@@ -985,8 +981,8 @@ int bbx_clock_set(bbx_grid *g, int64_t step)
     g_err.clear();
     if (!g) return fail(BBX_EINVAL, "grid is NULL");
     if (step < 0) return fail(BBX_EINVAL, "step must be >= 0");
-    // the fallback list lengths alternate with the step's parity: restart both
-    if (g->d_fb_cnt) HIP_TRY(hipMemsetAsync(g->d_fb_cnt, 0, 4 * sizeof(int32_t), g->stream), "hipMemsetAsync");
+    // the network list lengths alternate with the step's parity: restart both
+    if (g->d_acc_cnt) HIP_TRY(hipMemsetAsync(g->d_acc_cnt, 0, 2 * sizeof(int32_t), g->stream), "hipMemsetAsync");
     g->n = step;
     return BBX_OK;
 }
@@ -1386,9 +1382,8 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
                 (e = dalloc(g, &g->snet.norm, 4 * kP * sizeof(float))) != hipSuccess ||
                 (e = dalloc(g, &g->d_slo, kP * sizeof(float))) != hipSuccess ||
                 (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
-                (e = dalloc(g, &g->d_fb_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
                 (e = dalloc(g, &g->d_acc_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
-                (e = dalloc(g, &g->d_fb_cnt, 4 * sizeof(int32_t))) != hipSuccess ||
+                (e = dalloc(g, &g->d_acc_cnt, 2 * sizeof(int32_t))) != hipSuccess ||
                 (e = dalloc(g, &g->d_fb_total, sizeof(unsigned long long))) != hipSuccess)
                 return hip_fail(e, "hipMalloc");
         }
@@ -1402,7 +1397,7 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
         HIP_TRY(hipMemcpyAsync(g->snet.norm, m->dev.norm, 4 * kP * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
         HIP_TRY(hipMemcpyAsync(g->d_slo, lo, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
         HIP_TRY(hipMemcpyAsync(g->d_shi, hi, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
-        HIP_TRY(hipMemsetAsync(g->d_fb_cnt, 0, 4 * sizeof(int32_t), st), "hipMemsetAsync");
+        HIP_TRY(hipMemsetAsync(g->d_acc_cnt, 0, 2 * sizeof(int32_t), st), "hipMemsetAsync");
         HIP_TRY(hipMemsetAsync(g->d_fb_total, 0, sizeof(unsigned long long), st), "hipMemsetAsync");
         HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
         g->dv_max = dv_max;

@@ -42,8 +42,6 @@ struct SurArgs {
     MlpDev net;
     const float *lo, *hi;            // [nvar] accepted input box
     float dv_max;                    // largest accepted |dV| per step
-    int32_t *fb_list;                // [nact] voxels falling back this step
-    int32_t *fb_cnt;                 // [2] list lengths, alternating per step
     int32_t *acc_list;               // [nact] voxels whose input the network accepts
     int32_t *acc_cnt;                // [2] list lengths, alternating per step
     unsigned long long *fb_total;    // running count of fallbacks
@@ -66,8 +64,6 @@ hipError_t mlp_stats(const float *S, const float *S1, int64_t n, int nin, double
 
 hipError_t launch_surrogate_step(int model, int aniso, const StepArgs<float> &a, const SurArgs &su,
                                  hipStream_t s);
-hipError_t launch_fallback(int model, int aniso, const StepArgs<float> &a, const SurArgs &su,
-                           hipStream_t s);
 hipError_t launch_sample(const StepArgs<float> &a, int nvar, int64_t n, uint64_t seed, float *out,
                          hipStream_t s);
 hipError_t launch_ionic_map(int model, const StepArgs<float> &a, int nvar, const float *in,

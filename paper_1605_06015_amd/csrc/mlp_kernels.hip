@@ -586,7 +586,7 @@ hipError_t mlp_anchor(const MlpDev &d, const float *s0, const float *s1, float *
 uint64_t mlp_mix64(uint64_t z) { return mix64(z); }
 
 // ------------------------------------------------------- surrogate step
-// A surrogate step is three launches.  (1) k_sur_classify, one thread per tissue
+// A surrogate step is two launches.  (1) k_sur_classify, one thread per tissue
 // voxel: voxels whose kinetic input s = (V or V* = V + dt LV, g) lies in the
 // accepted box [lo, hi] are appended to the network list; every other voxel gets
 // the plain update right there (the plain step's own arithmetic).  (2) k_sur_net:
@@ -595,10 +595,10 @@ uint64_t mlp_mix64(uint64_t z) { return mix64(z); }
 // recomputes its Laplacian and stimulus and writes its normalised input to the
 // wave's LDS staging rows; the wave runs the network on its 64 voxels as four
 // 16-sample tiles, and each thread applies or rejects its prediction (gate
-// outside [0, 1], |dV| > dv_max, non-finite); rejected voxels go to the fallback
-// list.  Accepted gate predictions within kGateTol of [0, 1] are clamped into it.
-// (3) k_fallback: the plain update of the fallback list.  The network's cost is
-// thus paid only for the voxels it may take.
+// outside [0, 1], |dV| > dv_max, non-finite); rejected
+// voxels get the plain update in place (rare).  Accepted gate predictions within
+// kGateTol of [0, 1] are clamped into it.  The network's cost is thus paid only for
+// the voxels it may take.
 template <class M, bool ANISO>
 __global__ __launch_bounds__(kBlock) void k_sur_classify(const StepArgs<float> a, const SurArgs su)
 {
@@ -643,7 +643,17 @@ template <class M, bool ANISO>
 __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, const SurArgs su)
 {
     const int n = su.acc_cnt[su.parity];
-    if ((int)blockIdx.x * kSurBlock >= n) return;         // nothing for this workgroup
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        // input-rejected voxels were updated by the classifier; the next step's list
+        // (other parity) starts empty
+        atomicAdd(su.fb_total, (unsigned long long)(a.nact - n));
+        su.acc_cnt[su.parity ^ 1] = 0;
+    }
+    // the list is dealt to waves in chunks of 64, wave-major across workgroups
+    // (chunk c goes to wave c / G of workgroup c % G, G = gridDim.x), so that a
+    // short list still spreads over many CUs; a workgroup whose first chunk is
+    // past the end has nothing to do
+    if ((int)blockIdx.x * 64 >= n) return;
     constexpr int NW = kSurBlock / 64;
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
     __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
@@ -656,8 +666,10 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
     const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
     const float *nrm = su.net.norm;
 
-    for (int k0 = (int)blockIdx.x * kSurBlock; k0 < n; k0 += (int)gridDim.x * kSurBlock) {
-        const int k = k0 + (int)threadIdx.x;
+    const int nwave = (int)gridDim.x * NW, gw = wv * (int)gridDim.x + (int)blockIdx.x;
+    const int iters = (n + 64 * nwave - 1) / (64 * nwave);          // uniform over the grid
+    for (int it = 0; it < iters; it++) {
+        const int k = (it * nwave + gw) * 64 + l;
         const bool valid = k < n;
         const int t = valid ? su.acc_list[k] : 0;
         int idx = 0;
@@ -721,18 +733,13 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
 #pragma unroll
         for (int i = M::GATE0; i < NV; i++)
             ok = ok && s[i] + d[i] >= -kGateTol && s[i] + d[i] <= 1.0f + kGateTol;
-        // compact the rejected voxels into the fallback list: one atomic per wave,
-        // slots by prefix count of the wave's ballot over its valid lanes
+        // a rejected prediction falls back to the plain update of this voxel, here
+        // (rare; counted with one atomic per wave)
         const uint64_t rej = __ballot(!ok);
         if (rej) {
-            const int leader = __ffsll((unsigned long long)rej) - 1;
-            int base = 0;
-            if (l == leader) base = atomicAdd(&su.fb_cnt[su.parity], __popcll(rej));
-            base = __shfl(base, leader);
+            if (l == __ffsll((unsigned long long)rej) - 1) atomicAdd(su.fb_total, (unsigned long long)__popcll(rej));
             if (!ok) {
-                const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(rej >> 32),
-                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)rej, 0u));
-                su.fb_list[base + below] = t;
+                update_voxel<float, M>(a, t, idx, Vp, LV);
                 continue;
             }
         }
@@ -744,31 +751,6 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
         }
         a.Vout[idx] = Vn;
         record_voxel(a, t, Vp, Vn);
-    }
-}
-
-// Plain kinetics for the voxels the surrogate rejected this step (grid-stride
-// over the list; every wave exits when the list is exhausted).  Also clears the
-// other step's list length and adds this step's to the running total.
-template <class M, bool ANISO>
-__global__ __launch_bounds__(256) void k_fallback(const StepArgs<float> a, const SurArgs su)
-{
-    const int n = su.fb_cnt[su.parity];
-    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
-    for (int k = gid; k < n; k += gridDim.x * blockDim.x) {
-        const int t = su.fb_list[k];
-        int idx;
-        uint32_t bits;
-        voxel_of(a, t, idx, bits);
-        const float Vp = a.Vin[idx];
-        const float LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-        update_voxel<float, M>(a, t, idx, Vp, LV);
-    }
-    if (gid == 0) {
-        // input-rejected voxels (updated by the classifier) plus output-rejected ones
-        *su.fb_total += (unsigned long long)(a.nact - su.acc_cnt[su.parity]) + (unsigned long long)n;
-        su.fb_cnt[su.parity ^ 1] = 0;
-        su.acc_cnt[su.parity ^ 1] = 0;
     }
 }
 
@@ -817,37 +799,14 @@ static hipError_t sur_m(int aniso, const StepArgs<float> &a, const SurArgs &su, 
     return hipGetLastError();
 }
 
-template <class M>
-static hipError_t fb_m(int aniso, const StepArgs<float> &a, const SurArgs &su, hipStream_t s)
-{
-    int grid = (int)((a.nact + 255) / 256);
-    if (grid > 1024) grid = 1024;
-    if (grid < 1) grid = 1;
-    if (aniso) hipLaunchKernelGGL((k_fallback<M, true>), dim3(grid), dim3(256), 0, s, a, su);
-    else hipLaunchKernelGGL((k_fallback<M, false>), dim3(grid), dim3(256), 0, s, a, su);
-    return hipGetLastError();
-}
-
 hipError_t launch_surrogate_step(int model, int aniso, const StepArgs<float> &a, const SurArgs &su,
                                  hipStream_t s)
 {
     switch (model) {
     case 1: return sur_m<kin::Barkley<float>>(aniso, a, su, s);
     case 3: return sur_m<kin::Fhn<float>>(aniso, a, su, s);
-    case 4: return sur_m<kin::Crn<float>>(aniso, a, su, s);
+    case 4: return a.tab ? sur_m<kin::CrnTab>(aniso, a, su, s) : sur_m<kin::Crn<float>>(aniso, a, su, s);
     case 6: return sur_m<kin::Tp06<float>>(aniso, a, su, s);
-    default: return hipErrorInvalidValue;
-    }
-}
-
-hipError_t launch_fallback(int model, int aniso, const StepArgs<float> &a, const SurArgs &su,
-                           hipStream_t s)
-{
-    switch (model) {
-    case 1: return fb_m<kin::Barkley<float>>(aniso, a, su, s);
-    case 3: return fb_m<kin::Fhn<float>>(aniso, a, su, s);
-    case 4: return a.tab ? fb_m<kin::CrnTab>(aniso, a, su, s) : fb_m<kin::Crn<float>>(aniso, a, su, s);
-    case 6: return fb_m<kin::Tp06<float>>(aniso, a, su, s);
     default: return hipErrorInvalidValue;
     }
 }
