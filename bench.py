@@ -311,7 +311,7 @@ def ensemble_line(steps=None, chunk=1000):
     nvox = e.nvox
     per = sec / steps
     gbs = ENS_BYTES_PER_VOXEL * nvox / per / 1e9
-    names = ["64x4 LDS", "32x8 LDS", "16x16 LDS", "64x4 direct"]
+    names = ["64x4 LDS", "32x8 LDS", "16x16 LDS", "64x4 direct", "64x32 march", "64x128 march"]
     e.close()
     return {"workload": f"{len(w['nx'])} 2D FK4 tissues, sides {int(w['nx'].min())}-{int(w['nx'].max())} "
                         f"({nvox} voxels), per-tissue D/angle/time constants, S1-S2, "

@@ -337,10 +337,13 @@ const char *bbx_last_error(void);
 typedef struct bbx_ensemble bbx_ensemble;
 
 /* Tile variants of the ensemble step (bbx_ensemble_variant_set / _tune):
- * LDS-staged tiles of 64x4, 32x8 or 16x16 voxels, or 64x4 tiles that read
- * neighbours straight from memory. */
+ * LDS-staged tiles of 64x4, 32x8 or 16x16 voxels; 64x4 tiles that read
+ * neighbours straight from memory; or 64-column strips of 32 or 128 rows that
+ * each wave marches row by row (x neighbours from adjacent lanes, the next row
+ * loaded while the current one is computed). */
 enum { BBX_ENS_TILE_64x4 = 0, BBX_ENS_TILE_32x8 = 1, BBX_ENS_TILE_16x16 = 2,
-       BBX_ENS_DIRECT_64x4 = 3, BBX_ENS_NVARIANT = 4 };
+       BBX_ENS_DIRECT_64x4 = 3, BBX_ENS_MARCH_64x32 = 4, BBX_ENS_MARCH_64x128 = 5,
+       BBX_ENS_NVARIANT = 6 };
 
 /* Info queries for bbx_ensemble_info. */
 enum { BBX_ENS_INFO_VOXELS = 0, BBX_ENS_INFO_TILES = 1, BBX_ENS_INFO_VARIANT = 2,
@@ -394,7 +397,7 @@ int bbx_ensemble_variant_set(bbx_ensemble *e, int variant);
 
 /* Autotune: time `steps` steps of every variant on a scratch copy of the
  * current state (the ensemble's own state and clock are untouched), select
- * the fastest and return it in *variant (may be NULL); times_ms[4] (may be
+ * the fastest and return it in *variant (may be NULL); times_ms[BBX_ENS_NVARIANT] (may be
  * NULL) receives each variant's time.  Synchronises the stream. */
 int bbx_ensemble_tune(bbx_ensemble *e, int steps, int *variant, double *times_ms);
 

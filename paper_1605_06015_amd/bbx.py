@@ -28,7 +28,8 @@ BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, 
  BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT, BBX_READ_ECG, BBX_READ_ECG_SERIES,
  BBX_READ_ECG_COUNT) = range(14)
 BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
-BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_NVARIANT = range(5)
+(BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_MARCH_64x32,
+ BBX_ENS_MARCH_64x128, BBX_ENS_NVARIANT) = range(7)
 (BBX_ENS_INFO_VOXELS, BBX_ENS_INFO_TILES, BBX_ENS_INFO_VARIANT, BBX_ENS_INFO_DEVICE_BYTES,
  BBX_ENS_INFO_GRAPH_CHUNK, BBX_ENS_INFO_NVAR) = range(6)
 
