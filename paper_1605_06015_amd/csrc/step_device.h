@@ -9,13 +9,17 @@
 namespace bbx {
 
 // V_{p+off} - V_p if neighbour bit b is set (tissue), else 0.  FULL: the whole
-// workgroup is known to be interior (every neighbour is tissue).
+// workgroup is known to be interior (every neighbour is tissue).  The load is
+// unconditional, from the voxel itself when the neighbour is absent (always in
+// bounds), so that the gathers issue back to back without branches.
 template <typename T, bool FULL>
 __device__ __forceinline__ T nbd(const T *__restrict__ V, int idx, int off, uint32_t bits, int b,
                                  T Vp)
 {
     if (FULL) return V[idx + off] - Vp;
-    return ((bits >> b) & 1u) ? V[idx + off] - Vp : T(0);
+    const bool on = (bits >> b) & 1u;
+    const T v = V[on ? idx + off : idx];
+    return on ? v - Vp : T(0);
 }
 
 // (L V)_p in the difference form of the paper's weights (see step_kernels.hip).
