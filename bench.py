@@ -411,7 +411,7 @@ def main():
             grid.close()
         elif args.profile == "ensemble":
             e, _, _ = ensemble_workload(stream)
-            e.variant(B.BBX_ENS_TILE_64x4)
+            e.variant(B.BBX_ENS_DIRECT_64x4)
             e.step(args.warmup + args.steps)
             e.close()
         elif args.profile in ("crn", "crn_tab"):
