@@ -301,13 +301,14 @@ int bbx_sample_states(bbx_grid *g, int64_t n, uint64_t seed, float *out_dev);
 int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev);
 
 /* Attach a trained network as the kinetics of an FP32 grid (NULL detaches).
- * nin = nout = the model's nvar.  Each step then evaluates the network for
- * every tissue voxel and falls back to the plain kinetics for a voxel whose
- * kinetic input leaves [lo, hi] (nvar floats each), whose predicted gates
- * leave [-1e-3, 1 + 1e-3] (accepted gates are clamped to [0, 1]), whose
- * predicted |dV| exceeds dv_max, or whose prediction is not finite.  Supported
- * models: Barkley, FHN, CRN, TP06.  The network's weights are copied; it may be
- * destroyed after. */
+ * nin = nout = the model's nvar.  Each step then gives the plain kinetic
+ * update to every tissue voxel whose kinetic input leaves [lo, hi] (nvar
+ * floats each), evaluates the network for the others, and falls back to the
+ * plain update for a voxel whose predicted gates leave [-1e-3, 1 + 1e-3]
+ * (accepted gates are clamped to [0, 1]), whose predicted |dV| exceeds dv_max,
+ * or whose prediction is not finite.  A fallback voxel gets exactly the plain
+ * step's arithmetic.  Supported models: Barkley, FHN, CRN, TP06.  The
+ * network's weights are copied; it may be destroyed after. */
 int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi,
                       float dv_max);
 

@@ -79,3 +79,41 @@ def test_null_grid_calls_fail_cleanly(bbx):
     assert lib.bbx_info(None, 0, C.byref(v)) == bbx.BBX_EINVAL
     lib.bbx_grid_destroy(None)
     assert "NULL" in bbx.bbx_last_error()
+    assert lib.bbx_state_fill(None, 0, 1.0) == bbx.BBX_EINVAL
+    assert lib.bbx_ecg_set(None, 0, None, 0, 0) == bbx.BBX_EINVAL
+    assert lib.bbx_tabulation_set(None, 0.1) == bbx.BBX_EINVAL
+
+
+def test_ensemble_validation_before_device(bbx):
+    """Every argument check of bbx_ensemble_create runs before any device work."""
+    E = bbx.BBX_EINVAL
+    one = np.array([8], np.int32)
+    p4 = np.array([[0.11, 30.0, 1.9, 200.0]])
+    mk = lambda *a, **k: bbx.bbx_ensemble_create(*a, **k)
+    # sizes, coefficients, model and parameter count
+    assert _err(mk, np.array([0], np.int32), one, 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4, 0.05, 0) == E
+    assert _err(mk, one, one, 0.0, 0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4, 0.05, 0) == E
+    assert _err(mk, one, one, 0.25, -0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4, 0.05, 0) == E
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, np.nan, bbx.BBX_MODEL_FK4, p4, 0.05, 0) == E
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4[:, :3], 0.05, 0) == E
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, 0.0, 42, p4, 0.05, 0) == E
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4, 0.05, 3) == E
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_CRN, np.zeros((1, 0)), 0.05, 0) == \
+        bbx.BBX_ENOTSUP
+    assert _err(mk, one, one, 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_FK4, p4, 0.3, 0) == bbx.BBX_EUNSTABLE
+    # more than 2^31 voxels in total (checked before any allocation)
+    big = np.array([65536, 65536], np.int32)
+    assert _err(mk, big, np.array([32768, 32768], np.int32), 0.25, 0.1, 0.1, 0.0, bbx.BBX_MODEL_NONE,
+                np.zeros((2, 0)), 0.05, 0) == E
+    assert "2^31" in bbx.bbx_last_error()
+    lib = bbx._lib
+    assert lib.bbx_ensemble_step(None, 1) == E
+    assert lib.bbx_ensemble_state_set(None, 0, 0, None) == E
+    assert lib.bbx_ensemble_graph_set(None, 2) == E
+    assert lib.bbx_ensemble_variant_set(None, 0) == E
+    assert lib.bbx_ensemble_tune(None, 1, None, None) == E
+    assert lib.bbx_ensemble_recording_set(None, 0.5) == E
+    assert lib.bbx_ensemble_stimulus_add(None, 0, 0, 1, 0, 1, 1.0, 0.0, 1.0, 0.0, 1) == E
+    v = C.c_int64()
+    assert lib.bbx_ensemble_info(None, 0, C.byref(v)) == E
+    lib.bbx_ensemble_destroy(None)
