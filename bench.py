@@ -120,10 +120,84 @@ def cpu_baseline(seconds_target=12.0):
     t3 = time.perf_counter()
     per_step = (t3 - t2) / (n2 - n1)
     nact = int(g["mask"].sum())
+    # the same oracle on one core, a few steps (context: the scalar reference rate)
+    s1 = O.Sim(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], O.MODEL_CRN, [], c["dt"],
+               nthreads=1)
+    s1.state[:] = s.state
+    t4 = time.perf_counter()
+    s1.step(3)
+    serial = nact * 3 / (time.perf_counter() - t4)
     return {"value": nact / per_step, "unit": "voxel-updates/s", "cores": nthreads,
-            "kind": "oracle",
+            "kind": "oracle", "serial_value": serial,
             "sample": f"CRN 128x128x64 cup ({nact} tissue voxels), FP64 oracle, {n2 - n1} steps "
-                      f"after 2 warm-up steps, {t3 - t2:.1f} s, OpenMP over voxels"}
+                      f"after 2 warm-up steps, {t3 - t2:.1f} s, OpenMP over voxels "
+                      f"(serial_value: 3 steps on one core)"}
+
+
+_SHELL = {}
+
+
+def shell_geometry():
+    """The 512x512x384 double shell of the TP06 workload (generated once per process)."""
+    from paper_1605_06015_amd import workloads as WL
+    if "g" not in _SHELL:
+        c = WL.TP06_3D
+        _SHELL["g"] = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"],
+                                  c["s1_radius"])
+    return _SHELL["g"]
+
+
+def _stencil_case(stream, mask, h, fib, steps, warmup, bytes_per_voxel):
+    from paper_1605_06015_amd import bbx as B
+    grid = B.Grid(mask, h, fib, 0.3, 0.03, B.BBX_FP32, stream)
+    grid.model(B.BBX_MODEL_NONE, [], 0.01)
+    grid.fill(0, -40.0)
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, steps, warmup)
+    nact = grid.nact
+    grid.close()
+    per = sec / steps
+    gbs = bytes_per_voxel * nact / per / 1e9
+    return {"tissue_voxels": nact, "us_per_launch": round(per * 1e6, 2), "achieved": round(gbs, 1),
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bytes_per_voxel,
+            "voxel_updates_per_s": nact / per}
+
+
+def stencil_cases(stream, steps=100, warmup=10):
+    """The other two HBM-roofline stencil cases: the dense box with an isotropic tensor
+    (7-point, V read + written: 8 B/voxel) and the 25%-active double shell through the
+    tissue list (19-point: V read + written, index, neighbour bits, fibre, face
+    coefficients: 40 B/voxel)."""
+    nx, ny, nz = 512, 512, 384
+    out = {"dense_isotropic_7pt": _stencil_case(stream, np.ones((nz, ny, nx), np.uint8), 0.2, None,
+                                                steps, warmup, 8)}
+    g = shell_geometry()
+    out["double_shell_19pt"] = _stencil_case(stream, g["mask"], 0.2, g["fibre"], steps, warmup, 40)
+    return out
+
+
+def paper_shape_line(stream, n=300, steps=200, warmup=20):
+    """The paper's full-box scaling workload shape on one GPU: CRN on a dense n^3 box with
+    fibres rotating through z, FP32 (every voxel tissue: the z-marching dense kernel)."""
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    mask, fib = WL.full_box_rotating(n, n, n)
+    grid = B.Grid(mask, 0.25, fib, 0.3, 0.03, B.BBX_FP32, stream)
+    del fib
+    grid.model(B.BBX_MODEL_CRN, [], 0.01)
+    for v, val in enumerate(WL.CRN_INITIAL):
+        grid.fill(v, val)
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, steps, warmup)
+    nact = grid.nact
+    grid.close()
+    per = sec / steps
+    bpv = 21 * 4 * 2 + 24              # dense box: no index / neighbour-bit arrays, no recorder
+    gbs = bpv * nact / per / 1e9
+    return {"workload": f"CRN dense {n}^3 box, fibres rotating through z, FP32, {steps} steps",
+            "value": nact / per, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bpv}}
 
 
 def stencil_roofline(stream, steps=100, warmup=10):
@@ -335,7 +409,7 @@ def tp06_workload(stream):
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import workloads as WL
     c = WL.TP06_3D
-    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_radius"])
+    g3 = shell_geometry()
     grid = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
     grid.model(B.BBX_MODEL_TP06, [], c["dt"])
     for v, val in enumerate(WL.TP06_INITIAL):
@@ -465,6 +539,8 @@ def main():
             out["tabulated"] = tabulated_line(stream, args.tab, args.steps, args.warmup)
             out["tabulated"]["speedup_vs_plain"] = round(ms_per_step / out["tabulated"]["ms_per_step"], 3)
         out["stencil_roofline"] = stencil_roofline(stream)
+        out["stencil_roofline"]["other_cases"] = stencil_cases(stream)
+        out["paper_shape"] = paper_shape_line(stream)
         out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
         out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
         out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms, v_hi=-81.0)

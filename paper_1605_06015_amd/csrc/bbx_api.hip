@@ -214,7 +214,10 @@ StepArgs<T> make_args(const bbx_grid *g)
     a.vmax = (T *)g->d_vmax;
     a.apd = (T *)g->d_apd;
     a.vrep = (T *)g->d_vrep;
-    if (g->dense) {
+    // Dense boxes with light kinetics (<= 4 variables) use the z-marching LDS kernel;
+    // with the 19/21-variable models the one-voxel-per-thread kernel is faster
+    // (measured on a 300^3 CRN box: 1.02 vs 1.12 ms per step), and a.zc = 0 selects it.
+    if (g->dense && g->nvar <= 4) {
         a.gx = (g->nx + kTileX - 1) / kTileX;
         a.gy = (g->ny + kTileY - 1) / kTileY;
         // z-chunk: long enough to amortise the two extra halo planes, short enough
@@ -224,6 +227,7 @@ StepArgs<T> make_args(const bbx_grid *g)
         a.zc = zc;
         a.nblk = a.gx * a.gy * ((g->nz + zc - 1) / zc);
     } else {
+        a.zc = 0;
         a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
     }
     a.per_xcd = (a.nblk + kXcd - 1) / kXcd;

@@ -35,8 +35,9 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
     if (lb >= a.nblk) return;
     const int t = lb * kBlock + (int)threadIdx.x;
     if (t >= a.nact) return;
-    const int idx = a.idx[t];
-    const uint32_t bits = a.nbr[t];
+    int idx;
+    uint32_t bits;
+    voxel_of(a, t, idx, bits);         // dense boxes keep no index / bit arrays
     const T Vp = a.Vin[idx];
     const T LV = laplacian<T, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
     update_voxel<T, M>(a, t, idx, Vp, LV);
@@ -162,7 +163,7 @@ template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
     const dim3 grid(a.per_xcd * kXcd), block(kBlock);
-    if (a.dense) {
+    if (a.dense && a.zc > 0) {
         if (aniso) hipLaunchKernelGGL((k_step_dense<T, M, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step_dense<T, M, false>), grid, block, 0, s, a);
     } else {

@@ -322,6 +322,27 @@ def test_dense_box_fp64(aniso):
     assert rel_errs(gpu_state(g, 1), s.state, mask)[0] <= TOL64
 
 
+@pytest.mark.parametrize("prec,tol", [(1, TOL64), (0, None)])
+def test_dense_box_crn(prec, tol):
+    """A dense box with a many-variable model takes the one-voxel-per-thread path (the
+    z-marching kernel serves light models): CRN on a 20x12x8 all-tissue box, rotating
+    fibres, corner stimulus, 300 steps.  FP64 <= 1e-10 normwise; FP32 |dV| <= 1e-3 mV."""
+    mask, fib = WL.full_box_rotating(20, 12, 8)
+    st = np.stack([np.full(mask.shape, v) for v in WL.CRN_INITIAL])
+    reg = np.zeros_like(mask)
+    reg[:3, :4, :5] = 1
+    p = Problem(mask, 0.25, fib, 0.3, 0.03, O.MODEL_CRN, [], 0.01, state=st,
+                stims=[(reg, 40.0, 0.0, 2.0, 0.0, 1)])
+    s = run_oracle(p, 300)
+    g = make_gpu(p, prec)
+    g.step(300)
+    x = gpu_state(g, 21)
+    if prec == 1:
+        assert np.all(rel_errs(x, s.state, mask) <= tol)
+    else:
+        assert np.abs(x[0] - s.state[0]).max() <= 1e-3
+
+
 def test_dt_above_stability_bound_rejected(B):
     mask = np.ones((1, 10, 10), np.uint8)
     g = B.Grid(mask, 0.2, None, 1.0, 1.0, B.BBX_FP64)
