@@ -159,13 +159,50 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
     }
 }
 
+// Isotropic dense boxes: each thread marches its own (x, y) column through the
+// z-chunk keeping V of planes z-1, z, z+1 in registers; the four in-plane
+// neighbours come from memory (cache hits) and plane z+2 is loaded one plane
+// ahead.  No LDS and no barriers.
+template <typename T, class M>
+__global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
+{
+    const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
+    if (lb >= a.nblk) return;
+    const int bx = lb % a.gx, r = lb / a.gx;
+    const int by = r % a.gy, bz = r / a.gy;
+    const int z0 = bz * a.zc, z1 = min(a.nz, z0 + a.zc);
+    const int x = bx * kTileX + (int)(threadIdx.x % kTileX), y = by * kTileY + (int)(threadIdx.x / kTileX);
+    if (x >= a.nx || y >= a.ny) return;
+    const bool px = x + 1 < a.nx, mx = x > 0, py = y + 1 < a.ny, my = y > 0;
+    const int plane = a.nx * a.ny;
+    const int c0 = x + a.nx * y;
+    const int de = px ? 1 : 0, dw = mx ? -1 : 0, dn = py ? a.nx : 0, ds = my ? -a.nx : 0;
+    T Vm = z0 > 0 ? a.Vin[c0 + (z0 - 1) * plane] : T(0);
+    T Vc = a.Vin[c0 + z0 * plane];
+    T Vq = z0 + 1 < a.nz ? a.Vin[c0 + (z0 + 1) * plane] : T(0);
+    for (int z = z0; z < z1; z++) {
+        const T Vnext = (z + 2 < a.nz && z + 1 < z1) ? a.Vin[c0 + (z + 2) * plane] : T(0);
+        const int idx = c0 + z * plane;
+        const T E = a.Vin[idx + de], W = a.Vin[idx + dw], N = a.Vin[idx + dn], S = a.Vin[idx + ds];
+        const bool pz = z + 1 < a.nz, mz = z > 0;
+        const T ex_ = px ? E - Vc : T(0), wx = mx ? W - Vc : T(0);
+        const T ny_ = py ? N - Vc : T(0), sy_ = my ? S - Vc : T(0);
+        const T up = pz ? Vq - Vc : T(0), dnv = mz ? Vm - Vc : T(0);
+        const T LV = a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dnv));
+        update_voxel<T, M>(a, idx, idx, Vc, LV);
+        Vm = Vc;
+        Vc = Vq;
+        Vq = Vnext;
+    }
+}
+
 template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
     const dim3 grid(a.per_xcd * kXcd), block(kBlock);
     if (a.dense && a.zc > 0) {
         if (aniso) hipLaunchKernelGGL((k_step_dense<T, M, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step_dense<T, M, false>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step_zreg<T, M>), grid, block, 0, s, a);
     } else {
         if (aniso) hipLaunchKernelGGL((k_step<T, M, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_step<T, M, false>), grid, block, 0, s, a);
