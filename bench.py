@@ -200,6 +200,48 @@ def paper_shape_line(stream, n=300, steps=200, warmup=20):
                          "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bpv}}
 
 
+def barkley_line(stream):
+    """The 2D Barkley cross-field workload (100x100, FP64, 2,000 steps): 10^4 voxels make
+    each step a few microseconds of launch and latency, not a roofline case."""
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.BARKLEY_2D
+    u, v = WL.barkley_cross_field(c["nx"], c["ny"], seed=0)
+    mask = np.ones((1, c["ny"], c["nx"]), np.uint8)
+    grid = B.Grid(mask, c["h"], None, c["D"], c["D"], B.BBX_FP64, stream)
+    grid.model(B.BBX_MODEL_BARKLEY, [c["a"], c["b"], c["eps"]], c["dt"])
+    grid.set(0, u)
+    grid.set(1, v)
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, 2000, 100)
+    nact = grid.nact
+    grid.close()
+    return {"workload": "Barkley 2D 100x100, 5-point, FP64, cross-field start, 2000 steps",
+            "value": nact * 2000 / sec, "unit": "voxel-updates/s", "us_per_step": sec / 2000 * 1e6}
+
+
+def thin_shell_line(stream, steps=500, warmup=50):
+    """Atrium-like sparsity: CRN on a thin double shell at 8.3% of a 237x271x300 box
+    (tissue list), FP32."""
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    g = WL.double_shell(237, 271, 300, h=0.25, active_frac=0.083, seed=6)
+    grid = B.Grid(g["mask"], 0.25, g["fibre"], 0.3, 0.03, B.BBX_FP32, stream)
+    grid.model(B.BBX_MODEL_CRN, [], 0.01)
+    for v, val in enumerate(WL.CRN_INITIAL):
+        grid.fill(v, val)
+    grid.nan_check(0)
+    sec = time_steps(grid, stream, steps, warmup)
+    nact = grid.nact
+    grid.close()
+    per = sec / steps
+    gbs = 200 * nact / per / 1e9                       # 201 B/voxel without the recorder byte
+    return {"workload": f"CRN thin double shell, 237x271x300 box, 8.3% active ({nact} tissue voxels), FP32",
+            "value": nact / per, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
+            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": 200}}
+
+
 def stencil_roofline(stream, steps=100, warmup=10):
     """Pure-diffusion FP32 stencil on a dense 512x512x384 box with fibres rotating
     through z (the HBM roofline workload: V is 403 MB, beyond the Infinity Cache)."""
@@ -541,6 +583,8 @@ def main():
         out["stencil_roofline"] = stencil_roofline(stream)
         out["stencil_roofline"]["other_cases"] = stencil_cases(stream)
         out["paper_shape"] = paper_shape_line(stream)
+        out["thin_shell"] = thin_shell_line(stream)
+        out["barkley_2d"] = barkley_line(stream)
         out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
         out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
         out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms, v_hi=-81.0)
