@@ -154,14 +154,16 @@ struct Fk4 {
         const T Jso = Hw ? rcp(tso) : dv(u, to);
         const T Jsi = Hw ? dv(-w * s, p[2]) : T(0);
         // gates
-        const T tvm = Hvm ? T(1150) : T(60);
+        // each gate: one Rush-Larsen step with the branch's steady state and rate
+        // selected first (one exponential per gate)
         const T vinf = u < thvm ? T(1) : T(0);
-        g[0] = Hv ? rl_rate(v, T(0), rcp(T(1.4506)), dt) : rl_rate(v, vinf, rcp(tvm), dt);
+        const T kvm = Hvm ? T(1.0 / 1150.0) : T(1.0 / 60.0);
+        g[0] = rl_rate(v, Hv ? T(0) : vinf, Hv ? T(1.0 / 1.4506) : kvm, dt);
         const T twm = T(60) + (T(15) - T(60)) * (T(1) + th(T(65) * (u - T(0.03)))) * T(0.5);
         const T winf = Ho ? T(0.94) : T(1) - dv(u, T(0.07));
-        g[1] = Hw ? rl_rate(w, T(0), rcp(p[3]), dt) : rl_rate(w, winf, rcp(twm), dt);
+        g[1] = rl_rate(w, Hw ? T(0) : winf, rcp(Hw ? p[3] : twm), dt);
         const T sinf = (T(1) + th(T(2.0994) * (u - T(0.9087)))) * T(0.5);
-        g[2] = rl_rate(s, sinf, rcp(Hw ? T(16) : T(2.7342)), dt);
+        g[2] = rl_rate(s, sinf, Hw ? T(1.0 / 16.0) : T(1.0 / 2.7342), dt);
         return -(Jfi + Jso + Jsi);
     }
 };

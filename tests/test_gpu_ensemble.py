@@ -183,7 +183,7 @@ def test_tune_leaves_state_and_clock(B):
 
 
 def test_full_size_ensemble_few_steps(B):
-    """The 96-tissue workload (20.7 M voxels, sides 64..768) in the launch configuration
+    """The 96-tissue workload (24.0 M voxels, sides drawn from 64..768) in the launch configuration
     the benchmark times (graph mode, tuned tile): after 4 steps with S1 on, the smallest,
     a middle and the largest tissue match the FP64 oracle (FP32: |du| <= 1e-5, gates
     <= 1e-5 absolute)."""
@@ -266,3 +266,42 @@ def test_ensemble_errors(B):
     with pytest.raises(B.BBXError) as ex:
         e.read(B.BBX_READ_ACT_TIME, 0)
     assert ex.value.code == B.BBX_ESTATE
+
+
+@pytest.mark.parametrize("model", ["none", "barkley", "zfk", "fhn"])
+def test_ensemble_other_models_fp64(B, model):
+    """The ensemble runs every 2D model: four tissues (13x9 to 1x11) with per-tissue
+    parameters, D and fibre angle, random initial states, 300 steps, each tissue against
+    the oracle within 1e-10 normwise per variable."""
+    mid = {"none": O.MODEL_NONE, "barkley": O.MODEL_BARKLEY, "zfk": O.MODEL_ZFK, "fhn": O.MODEL_FHN}[model]
+    base = {"none": [], "barkley": [0.75, 0.02, 0.02], "zfk": [0.13], "fhn": [0.3, 0.7, 0.5]}[model]
+    nv = O.nvar(mid)
+    sizes = [(13, 9), (30, 21), (1, 11), (17, 1)]
+    rng = np.random.default_rng(21)
+    n = len(sizes)
+    nx = np.array([s[0] for s in sizes], np.int32)
+    ny = np.array([s[1] for s in sizes], np.int32)
+    Dp = rng.uniform(0.8, 1.2, n)
+    Dq = Dp / 3
+    ang = rng.uniform(0, np.pi, n)
+    prm = np.array(base, float)[None, :] * rng.uniform(0.8, 1.2, (n, len(base))) if base else np.zeros((n, 0))
+    h, dt = 0.5, 0.01
+    e = B.Ensemble(nx, ny, h, Dp, Dq, ang, mid, prm, dt, B.BBX_FP64)
+    states = []
+    for i in range(n):
+        st = np.stack([rng.uniform(0, 1 if v == 0 else 0.5, (int(ny[i]), int(nx[i]))) for v in range(nv)])
+        states.append(st)
+        for v in range(nv):
+            e.set(i, v, st[v])
+    e.step(300)
+    for i in range(n):
+        mask = np.ones((1, int(ny[i]), int(nx[i])), np.uint8)
+        fib = np.zeros(mask.shape + (3,))
+        fib[..., 0] = np.cos(ang[i])
+        fib[..., 1] = np.sin(ang[i])
+        s = O.Sim(mask, h, fib, Dp[i], Dq[i], mid, list(prm[i]), dt)
+        s.state[:] = states[i][:, None]
+        s.step(300)
+        got = np.stack([e.get(i, v)[None] for v in range(nv)])
+        err = rel_errs(got, s.state, mask)
+        assert np.all(err <= TOL64), (model, i, err)
