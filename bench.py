@@ -9,8 +9,8 @@ voxels), dt 0.01 ms.  Inputs are resident in HBM before timing starts; the
 timed region is K steps bracketed by synchronisations, timed with HIP events
 on the stream the kernels are launched on.
 
-Prints ONE JSON line (see the keys below).  --gpus N>1 is refused: this
-build runs on one GPU.
+Prints ONE JSON line (see the keys below).  --gpus N>1 is refused: the
+benchmark runs on one GPU.
 """
 from __future__ import annotations
 
@@ -511,7 +511,7 @@ def main():
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported",
+        print(f"bench.py: the benchmark runs on one GPU; --gpus {args.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
 

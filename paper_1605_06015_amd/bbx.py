@@ -87,7 +87,7 @@ class BBXError(RuntimeError):
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
-        raise ImportError(f"libbbx.so not built ({path}); run __graft_entry__.build()")
+        raise ImportError(f"libbbx.so not built ({path}); run python paper_1605_06015_amd/build.py")
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
