@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-updates/s (FP32 plain vs surrogate) at ≤1dt activation-time error; %HBM roof"
 HBM_PEAK_GBS = 8000.0
+VALU_PEAK_GINST = 614.4   # 256 CUs x 2.4 GHz x one wave64 VALU instruction per CU-cycle
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 STEP_SOURCES = [os.path.join(ROOT, "paper_1605_06015_amd", "csrc", f)
                 for f in ("step_kernels.hip", "step_device.h", "kinetics.h", "bbx_internal.h")]
@@ -49,9 +50,9 @@ def source_hash(paths=STEP_SOURCES) -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(name: str, bytes_alg: float):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if they were taken
-    on the current kernel sources; else None."""
+def measured_counters(name: str):
+    """Counter figures per launch from a committed rocprofv3 summary, if they were taken on
+    the current kernel sources; else None."""
     path = os.path.join(PROFILE_DIR, name)
     if not os.path.exists(path):
         return None
@@ -61,7 +62,7 @@ def measured_traffic(name: str, bytes_alg: float):
         return None
     if d.get("source_hash") != source_hash():
         return None
-    return d.get("bytes_per_launch")
+    return d
 
 
 def time_steps(grid, stream, steps, warmup):
@@ -559,7 +560,15 @@ def main():
     value = nact * args.steps / sec
     per_launch = sec / args.steps
     achieved = CRN_BYTES_PER_VOXEL * nact / per_launch / 1e9
-    traffic = measured_traffic("step_crn_cup128_fp32_traffic.json", CRN_BYTES_PER_VOXEL * nact)
+    ctr = measured_counters("step_crn_cup128_fp32_traffic.json")
+    traffic = ctr.get("bytes_per_launch") if ctr else None
+    valu = None
+    if ctr and ctr.get("valu_insts_per_launch"):
+        # VALU issue: one wave64 instruction per CU per cycle, 256 CUs at 2.4 GHz
+        gi = ctr["valu_insts_per_launch"] / per_launch / 1e9
+        valu = {"achieved": round(gi, 1), "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
+                "frac": round(gi / VALU_PEAK_GINST, 4),
+                "insts_per_launch": ctr["valu_insts_per_launch"]}
     out = {
         "metric": METRIC, "value": value, "unit": "voxel-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -573,7 +582,7 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": "k_step<float, Crn, aniso>",
                      "bytes_per_voxel": CRN_BYTES_PER_VOXEL,
-                     "us_per_launch": round(per_launch * 1e6, 2)},
+                     "us_per_launch": round(per_launch * 1e6, 2), "valu": valu},
     }
     grid.close()
     if not args.no_extras:
