@@ -389,8 +389,10 @@ template <typename T>
 int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
 {
     // tissue list (increasing box order)
+    int64_t count = 0;
+    for (int64_t b = 0; b < g->nbox; b++) count += mask[b] != 0;
     std::vector<int32_t> idx;
-    idx.reserve((size_t)g->nbox);
+    idx.reserve((size_t)count);
     for (int64_t b = 0; b < g->nbox; b++)
         if (mask[b]) idx.push_back((int32_t)b);
     g->nact = (int64_t)idx.size();

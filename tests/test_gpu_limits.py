@@ -1,0 +1,73 @@
+"""A box at the library's size limit: 1290^3 = 2,146,689,000 voxels, just under the
+2^31 - 1 that box indices may reach.  Two small tissue blobs sit at opposite corners (the
+far one holds the largest box indices).  Each tissue voxel's update reads only its own
+neighbourhood, so after the same FP32 run every value equals, bit for bit, that of the
+same blob simulated alone in a box of its own size (the blob boxes themselves are
+checked against the oracle by the other parity tests).  This checks every box index,
+neighbour offset and box-layout readout near the limit without an oracle run over
+2 G voxels."""
+import numpy as np
+import pytest
+
+from paper_1605_06015_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+N = 1290
+H, D, DT, STEPS = 0.5, 1.0, 0.01, 300
+BARKLEY = [0.75, 0.02, 0.02]
+
+
+def setup_grid(B, mask, stim):
+    g = B.Grid(mask, H, None, D, D, B.BBX_FP32)
+    g.model(B.BBX_MODEL_BARKLEY, BARKLEY, DT)
+    g.fill(0, 0.0)
+    g.fill(1, 0.0)
+    g.stimulus(stim, 1.0, 0.0, 1.0)
+    return g
+
+
+def test_box_at_index_limit_matches_blob_boxes():
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    assert N ** 3 <= 2 ** 31 - 1
+    blobs = [WL.random_blob_mask(14, 11, 9, seed=4), WL.random_blob_mask(12, 13, 10, seed=6)]
+    where = [tuple(slice(N - s, N) for s in blobs[0].shape),        # far corner
+             tuple(slice(0, s) for s in blobs[1].shape)]            # origin corner
+    stims = []
+    for m in blobs:
+        st = np.zeros_like(m)
+        st[:, :, :4] = m[:, :, :4]                                  # the low-x end of each blob
+        stims.append(st)
+
+    small = []
+    for m, st in zip(blobs, stims):
+        g = setup_grid(B, m, st)
+        g.step(STEPS)
+        small.append((g.get(0), g.get(1)))
+        assert np.nanmax(small[-1][0][m == 1]) > 0.5                # the blob is excited
+        g.close()
+
+    mask = np.zeros((N, N, N), np.uint8)
+    stim = np.zeros((N, N, N), np.uint8)
+    for m, st, w in zip(blobs, stims, where):
+        mask[w] = m
+        stim[w] = st
+    print("limit box: creating", flush=True)
+    big = setup_grid(B, mask, stim)
+    del stim
+    assert big.nact == sum(int(m.sum()) for m in blobs)
+    big.step(STEPS)
+    print("limit box: stepped", flush=True)
+    out = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+    for var in (0, 1):
+        B.bbx_readout(big.handle, B.BBX_READ_VAR, var, None, out.data_ptr(), out.numel() * 8, 1)
+        torch.cuda.synchronize()
+        for (m, w, (u, v)) in zip(blobs, where, small):
+            z, y, x = np.nonzero(m)
+            flat = ((z + w[0].start) * N + (y + w[1].start)) * N + (x + w[2].start)
+            got = out[torch.from_numpy(flat).to("cuda")].cpu().numpy()
+            want = (u if var == 0 else v)[m == 1]
+            assert np.array_equal(got, want), (var, np.abs(got - want).max())
+    del out
+    big.close()
