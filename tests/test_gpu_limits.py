@@ -71,3 +71,30 @@ def test_box_at_index_limit_matches_blob_boxes():
             assert np.array_equal(got, want), (var, np.abs(got - want).max())
     del out
     big.close()
+
+
+def test_ensemble_at_voxel_limit_last_tissue_matches_alone():
+    """Two 46340 x 23170 tissues and a small 9 x 7 one after them: 2,147,395,663 voxels in
+    total, just under the 2^31 limit, so the small tissue holds the largest voxel offsets.
+    FP32 Barkley, a stimulus on the small tissue, 100 steps: its values equal, bit for bit,
+    those of the same tissue alone in an ensemble of one."""
+    from paper_1605_06015_amd import bbx as B
+    nx, ny = [46340, 46340, 9], [23170, 23170, 7]
+    assert sum(a * b for a, b in zip(nx, ny)) < 2 ** 31
+
+    def run(nxs, nys):
+        k = len(nxs)
+        e = B.Ensemble(nxs, nys, H, [D] * k, [0.5 * D] * k, [0.3] * k, B.BBX_MODEL_BARKLEY,
+                       BARKLEY * k, DT, B.BBX_FP32)
+        e.stimulus(k - 1, 0, 3, 0, 7, 1.0, 0.0, 1.0)
+        e.step(100)
+        out = [e.get(k - 1, v) for v in range(2)]
+        e.close()
+        return out
+
+    alone = run(nx[2:], ny[2:])
+    assert alone[0].max() > 0.5
+    print("ensemble at the limit: running", flush=True)
+    full = run(nx, ny)
+    for v in range(2):
+        assert np.array_equal(full[v], alone[v]), v
