@@ -121,7 +121,7 @@ __device__ __forceinline__ void voxel_of(const StepArgs<T> &a, int t, int &idx, 
 
 // Everything after the Laplacian for one voxel: stimulus, kinetics, stores and
 // the recorder.
-template <typename T, class M>
+template <typename T, class M, bool NT = false>
 __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int idx, T Vp, T LV)
 {
     const T Is = stim_current(a, t);
@@ -134,7 +134,10 @@ __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int id
     const T Vn = a.split ? Vin + a.dt * (r + Is) : Vp + a.dt * (r + Is + LV);
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
-    a.Vout[idx] = Vn;
+    if constexpr (NT)
+        __builtin_nontemporal_store(Vn, &a.Vout[idx]);   // streaming write (a.nt_store)
+    else
+        a.Vout[idx] = Vn;
 
     record_voxel(a, t, Vp, Vn);
 }

@@ -28,7 +28,7 @@ namespace bbx {
 // Tissue-list path: one thread per tissue voxel, 256 consecutive list entries per
 // workgroup.  Logical workgroup ids are dealt so that XCD k gets the k-th
 // contiguous eighth of the list, keeping neighbour rows and planes in its L2.
-template <typename T, class M, bool ANISO>
+template <typename T, class M, bool ANISO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
 {
     const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
@@ -40,7 +40,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
     voxel_of(a, t, idx, bits);         // dense boxes keep no index / bit arrays
     const T Vp = a.Vin[idx];
     const T LV = laplacian<T, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-    update_voxel<T, M>(a, t, idx, Vp, LV);
+    update_voxel<T, M, NT>(a, t, idx, Vp, LV);
 }
 
 // Dense-box path (every voxel is tissue): a workgroup owns a 64 x 4 column tile
@@ -91,7 +91,7 @@ __device__ __forceinline__ T laplacian_lds(const StepArgs<T> &a, const T *Pm, co
            + cx * (ex_ - wx) + cy * (ny_ - sy_) + cz * (up - dn);
 }
 
-template <typename T, class M, bool ANISO>
+template <typename T, class M, bool ANISO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
 {
     __shared__ T ring[3][kPlane];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
             const bool full = xy_in && z > 0 && z + 1 < a.nz;
             const T LV = full ? laplacian_lds<T, ANISO, true>(a, Pm, Pc, Pp, c, geo, bits, Vp)
                               : laplacian_lds<T, ANISO, false>(a, Pm, Pc, Pp, c, geo, bits, Vp);
-            update_voxel<T, M>(a, idx, idx, Vp, LV);
+            update_voxel<T, M, NT>(a, idx, idx, Vp, LV);
         }
         __syncthreads();                                   // slot of plane z-1 is free
         if (pre) {
@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
 // z-chunk keeping V of planes z-1, z, z+1 in registers; the four in-plane
 // neighbours come from memory (cache hits) and plane z+2 is loaded one plane
 // ahead.  No LDS and no barriers.
-template <typename T, class M>
+template <typename T, class M, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
 {
     const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
@@ -189,24 +189,31 @@ __global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
         const T ny_ = py ? N - Vc : T(0), sy_ = my ? S - Vc : T(0);
         const T up = pz ? Vq - Vc : T(0), dnv = mz ? Vm - Vc : T(0);
         const T LV = a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dnv));
-        update_voxel<T, M>(a, idx, idx, Vc, LV);
+        update_voxel<T, M, NT>(a, idx, idx, Vc, LV);
         Vm = Vc;
         Vc = Vq;
         Vq = Vnext;
     }
 }
 
-template <typename T, class M>
-static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
+template <typename T, class M, bool NT>
+static void launch_kernel(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
     const dim3 grid(a.per_xcd * kXcd), block(kBlock);
     if (a.dense && a.zc > 0) {
-        if (aniso) hipLaunchKernelGGL((k_step_dense<T, M, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step_zreg<T, M>), grid, block, 0, s, a);
+        if (aniso) hipLaunchKernelGGL((k_step_dense<T, M, true, NT>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step_zreg<T, M, NT>), grid, block, 0, s, a);
     } else {
-        if (aniso) hipLaunchKernelGGL((k_step<T, M, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step<T, M, false>), grid, block, 0, s, a);
+        if (aniso) hipLaunchKernelGGL((k_step<T, M, true, NT>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step<T, M, false, NT>), grid, block, 0, s, a);
     }
+}
+
+template <typename T, class M>
+static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
+{
+    if (a.nt_store) launch_kernel<T, M, true>(aniso, a, s);
+    else launch_kernel<T, M, false>(aniso, a, s);
     return hipGetLastError();
 }
 
