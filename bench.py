@@ -221,6 +221,38 @@ def barkley_line(stream):
             "value": nact * 2000 / sec, "unit": "voxel-updates/s", "us_per_step": sec / 2000 * 1e6}
 
 
+GOLDEN_MAPS = os.path.join(ROOT, "tests", "golden", "crn_cup128_at_apd.csv")
+
+
+def headline_accuracy(stream):
+    """The headline workload run in FP32 for its full 500 ms, in the timed launch
+    configuration, against the FP64 oracle's activation times and APD90 at 4,000 seeded
+    tissue voxels (a file the oracle wrote)."""
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    if not os.path.exists(GOLDEN_MAPS):
+        return None
+    d = np.loadtxt(GOLDEN_MAPS, delimiter=",", skiprows=2)
+    idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+    grid, _ = crn_workload(B.BBX_FP32, stream)
+    n = int(round(WL.CRN_3D["t_end"] / WL.CRN_3D["dt"]))
+    grid.step(n)
+    at = grid.read(B.BBX_READ_ACT_TIME).ravel()[idx]
+    apd = grid.read(B.BBX_READ_APD90).ravel()[idx]
+    grid.close()
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+
+    def fin(x):
+        return float(x) if np.isfinite(x) else None
+    ea, ep = np.abs(at[fa] - at_o[fa]), np.abs(apd[fp] - apd_o[fp])
+    return {"reference": "FP64 oracle, 500 ms, 4000 seeded tissue voxels",
+            "dt_ms": WL.CRN_3D["dt"],
+            "same_activated_set": bool(np.array_equal(np.isfinite(at), fa)),
+            "same_repolarised_set": bool(np.array_equal(np.isfinite(apd), fp)),
+            "at_max_err_ms": fin(ea.max()), "at_mean_err_ms": fin(ea.mean()),
+            "apd90_max_err_ms": fin(ep.max()), "apd90_mean_err_ms": fin(ep.mean())}
+
+
 def thin_shell_line(stream, steps=500, warmup=50):
     """Atrium-like sparsity: CRN on a thin double shell at 8.3% of a 237x271x300 box
     (tissue list), FP32."""
@@ -585,6 +617,7 @@ def main():
                      "us_per_launch": round(per_launch * 1e6, 2), "valu": valu},
     }
     grid.close()
+    out["accuracy"] = headline_accuracy(stream)
     if not args.no_extras:
         if args.tab > 0:
             out["tabulated"] = tabulated_line(stream, args.tab, args.steps, args.warmup)

@@ -1,0 +1,68 @@
+"""The 3D CRN workload (128x128x64 cup, 35% active, rotating fibres) run for its full
+500 ms in the benchmark's launch configuration, against activation times and APD90
+that the FP64 oracle wrote for 4,000 seeded tissue voxels (tests/golden/
+crn_cup128_at_apd.csv, made by make_crn_cup_maps.py beside it).
+
+FP64: activation times and APD90 within 2e-6 ms: the file holds 9 significant digits
+(at most 5e-7 ms of rounding for an APD90 near 300 ms), and the 1e-10 relative state bar
+moves a threshold crossing far less than that.
+FP32: the same voxels activate; activation times within 1 dt (0.01 ms); APD90 within
+2 ms.  The APD bound follows from the voltage bar: at the 90% repolarisation level
+(about -68 mV) the CRN membrane potential of a single FP64 oracle cell falls at
+0.26 mV/ms, so a 0.5 mV voltage error moves that crossing by about 2 ms."""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1605_06015_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crn_cup128_at_apd.csv")
+
+
+def load_golden():
+    d = np.loadtxt(GOLDEN, delimiter=",", skiprows=2)
+    return d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+
+
+def run_headline(prec):
+    from paper_1605_06015_amd import bbx as B
+    c = WL.CRN_3D
+    g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
+    grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], prec)
+    grid.model(B.BBX_MODEL_CRN, [], c["dt"])
+    for v in range(21):
+        grid.set(v, g["state"][v])
+    grid.stimulus(g["stim"], c["stim_amp"], 0.0, c["stim_ms"])
+    grid.record(c["theta"])
+    n = int(round(c["t_end"] / c["dt"]))
+    for _ in range(10):
+        grid.step(n // 10)
+    assert grid.read(B.BBX_READ_STEP) == n
+    return (grid.read(B.BBX_READ_ACT_TIME).ravel(), grid.read(B.BBX_READ_APD90).ravel(),
+            g["mask"].ravel())
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_crn_headline_500ms_against_oracle_maps(prec):
+    idx, at_o, apd_o = load_golden()
+    at, apd, mask = run_headline(prec)
+    assert np.all(mask[idx] == 1)
+    assert np.isfinite(at_o).mean() > 0.9                  # the wave covers the cup
+    assert np.isfinite(apd_o).mean() > 0.9                 # and it repolarises
+    at_g, apd_g = at[idx], apd[idx]
+    assert np.array_equal(np.isnan(at_g), np.isnan(at_o))
+    assert np.array_equal(np.isnan(apd_g), np.isnan(apd_o))
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+    dat = np.abs(at_g[fa] - at_o[fa]).max()
+    dapd = np.abs(apd_g[fp] - apd_o[fp]).max()
+    print(f"prec {prec}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms, "
+          f"AT range {at_o[fa].min():.2f}-{at_o[fa].max():.2f} ms, "
+          f"APD90 range {apd_o[fp].min():.1f}-{apd_o[fp].max():.1f} ms")
+    if prec == 1:
+        assert dat <= 2e-6 and dapd <= 2e-6, (dat, dapd)
+    else:
+        assert dat <= WL.CRN_3D["dt"] + 1e-9, dat
+        assert dapd <= 2.0, dapd
