@@ -42,6 +42,9 @@ struct EnsArgs {
     T theta;
     uint8_t *status;
     T *at, *vmax, *apd, *vrep;
+    // 1: state read and V written with non-temporal accesses (ensembles whose state
+    // exceeds the Infinity Cache)
+    int nt;
 };
 
 // Launch step j of a batch (step *nbase + j) with tile variant v.

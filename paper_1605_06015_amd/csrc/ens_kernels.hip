@@ -61,22 +61,26 @@ __device__ __forceinline__ T ens_stim(const EnsArgs<T> &a, const EnsTissue<T> &t
 }
 
 // Kinetics, V update, stores and recorder of voxel t of a tissue.
-template <typename T, class M>
+template <typename T, class M, bool NT>
 __device__ __forceinline__ void ens_update(const EnsArgs<T> &a, const EnsTissue<T> &ti, int64_t n,
                                            int64_t t, T Vp, T LV, T Is, T *Vout)
 {
     T g[M::NV > 1 ? M::NV - 1 : 1];
 #pragma unroll
-    for (int i = 0; i < M::NV - 1; i++) g[i] = a.st[i * a.pitch + t];
+    for (int i = 0; i < M::NV - 1; i++) {
+        if constexpr (NT) g[i] = __builtin_nontemporal_load(&a.st[i * a.pitch + t]);
+        else g[i] = a.st[i * a.pitch + t];
+    }
     const T r = M::advance(ti.prm, Vp, g, a.dt, nullptr);
     const T Vn = Vp + a.dt * (r + Is + LV);
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
-    Vout[t] = Vn;
+    if constexpr (NT) __builtin_nontemporal_store(Vn, &Vout[t]);
+    else Vout[t] = Vn;
     if (a.rec) record_event(a, t, T((double)n * a.dt64), Vp, Vn);
 }
 
-template <typename T, class M, int TX, int TY, bool LDS>
+template <typename T, class M, int TX, int TY, bool LDS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_ens_step(const EnsArgs<T> a, int j)
 {
     static_assert(TX * TY == kBlock, "one voxel per thread");
@@ -132,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void k_ens_step(const EnsArgs<T> a, int j)
     }
     const T LV = ens_laplacian(ti, px, mx, py, my, Vp, E, W, N, S, NE, SW, SE, NW);
     const T Is = ens_stim(a, ti, n, x, y);
-    ens_update<T, M>(a, ti, n, ti.off + (int64_t)(x + nx * y), Vp, LV, Is, Vout);
+    ens_update<T, M, NT>(a, ti, n, ti.off + (int64_t)(x + nx * y), Vp, LV, Is, Vout);
 }
 
 // Row-marching variant: a workgroup owns a 64-column strip of 4R rows, each wave
@@ -141,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_ens_step(const EnsArgs<T> a, int j)
 // shuffles); lanes 0 and 63 also carry the halo columns x0-1 and x0+64.  Row y+2
 // is loaded while row y is computed, so each V value is read from memory once
 // and every wave keeps loads in flight through its rows.
-template <typename T, class M, int R>
+template <typename T, class M, int R, bool NT>
 __global__ __launch_bounds__(kBlock) void k_ens_march(const EnsArgs<T> a, int j)
 {
     const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
@@ -186,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_ens_march(const EnsArgs<T> a, int j)
                 const EnsStim<T> St = a.stims[k];
                 if (((son >> (k - ti.s0)) & 1u) & (y >= St.y0) & (y < St.y1)) Is += St.amp;
             }
-            ens_update<T, M>(a, ti, n, ti.off + (int64_t)(x + nx * y), Vc, LV, Is, Vout);
+            ens_update<T, M, NT>(a, ti, n, ti.off + (int64_t)(x + nx * y), Vc, LV, Is, Vout);
         }
         Vm = Vc;
         Vc = Vq;
@@ -213,19 +217,26 @@ void ens_tile_shape(int variant, int *tx, int *ty)
     }
 }
 
-template <typename T, class M>
-static hipError_t ens_m(int variant, const EnsArgs<T> &a, int j, hipStream_t s)
+template <typename T, class M, bool NT>
+static hipError_t ens_v(int variant, const EnsArgs<T> &a, int j, hipStream_t s)
 {
     const dim3 grid(a.per_xcd * kXcd), block(kBlock);
     switch (variant) {
-    case 0: hipLaunchKernelGGL((k_ens_step<T, M, 64, 4, true>), grid, block, 0, s, a, j); break;
-    case 1: hipLaunchKernelGGL((k_ens_step<T, M, 32, 8, true>), grid, block, 0, s, a, j); break;
-    case 2: hipLaunchKernelGGL((k_ens_step<T, M, 16, 16, true>), grid, block, 0, s, a, j); break;
-    case 3: hipLaunchKernelGGL((k_ens_step<T, M, 64, 4, false>), grid, block, 0, s, a, j); break;
-    case 4: hipLaunchKernelGGL((k_ens_march<T, M, 8>), grid, block, 0, s, a, j); break;
-    case 5: hipLaunchKernelGGL((k_ens_march<T, M, 32>), grid, block, 0, s, a, j); break;
+    case 0: hipLaunchKernelGGL((k_ens_step<T, M, 64, 4, true, NT>), grid, block, 0, s, a, j); break;
+    case 1: hipLaunchKernelGGL((k_ens_step<T, M, 32, 8, true, NT>), grid, block, 0, s, a, j); break;
+    case 2: hipLaunchKernelGGL((k_ens_step<T, M, 16, 16, true, NT>), grid, block, 0, s, a, j); break;
+    case 3: hipLaunchKernelGGL((k_ens_step<T, M, 64, 4, false, NT>), grid, block, 0, s, a, j); break;
+    case 4: hipLaunchKernelGGL((k_ens_march<T, M, 8, NT>), grid, block, 0, s, a, j); break;
+    case 5: hipLaunchKernelGGL((k_ens_march<T, M, 32, NT>), grid, block, 0, s, a, j); break;
     default: return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+
+template <typename T, class M>
+static hipError_t ens_m(int variant, const EnsArgs<T> &a, int j, hipStream_t s)
+{
+    return a.nt ? ens_v<T, M, true>(variant, a, j, s) : ens_v<T, M, false>(variant, a, j, s);
     return hipGetLastError();
 }
 
