@@ -214,10 +214,12 @@ StepArgs<T> make_args(const bbx_grid *g)
     a.vmax = (T *)g->d_vmax;
     a.apd = (T *)g->d_apd;
     a.vrep = (T *)g->d_vrep;
-    // Measured: non-temporal V stores take 9.5% off the TP06 step on the 403 MB box of
-    // the 512x512x384 double shell and 3% off the dense 512x512x384 stencil, change
-    // nothing on a 108 MB dense box and slow the cache-resident cases (4-77 MB boxes).
-    a.nt_store = (double)g->nbox * sizeof(T) > kNtStoreBytes;
+    // Measured: streaming accesses take 13% off the TP06 step on the 512x512x384 double
+    // shell (403 MB box, 1.9 GB state), 3% off the dense 512x512x384 stencil and 1.4% off
+    // a 300^3 CRN box (108 MB box, 2.3 GB state), and slow the cases that fit the cache
+    // (CRN cup: 4 MB box, 31 MB state; thin shell: 77 MB box, 128 MB state).
+    a.nt = (double)g->nbox * sizeof(T) > kInfinityCacheBytes ||
+           (double)g->nact * (g->nvar - 1) * sizeof(T) > kInfinityCacheBytes;
     // Dense boxes with light kinetics (<= 4 variables) use the z-marching LDS kernel;
     // with the 19/21-variable models the one-voxel-per-thread kernel is faster
     // (measured on a 300^3 CRN box: 1.02 vs 1.12 ms per step), and a.zc = 0 selects it.

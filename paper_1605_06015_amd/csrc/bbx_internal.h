@@ -10,7 +10,7 @@ constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
 constexpr int kMaxStim = 32;     // stimuli per grid (bit per stimulus in a uint32)
 constexpr int kMaxParams = 8;    // model parameters
 constexpr int kXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
-constexpr double kNtStoreBytes = 256.0 * 1024 * 1024;   // MI355X Infinity Cache size
+constexpr double kInfinityCacheBytes = 256.0 * 1024 * 1024;   // MI355X Infinity Cache size
 
 // The 18 non-corner neighbours of the 19-point stencil, in bit order: the six
 // faces, then the edges of the xy, xz and yz planes as (+,+), (-,-), (+,-), (-,+).
@@ -59,10 +59,10 @@ struct StepArgs {
     uint8_t *status;
     T *at, *vmax, *apd;
     T *vrep;                   // rest level until the peak is known, then the 90% level
-    // 1: V_{n+1} is written with non-temporal stores (box arrays larger than the
-    // Infinity Cache, where caching the write stream only evicts the V_n lines the
-    // neighbour gathers reuse)
-    int nt_store;
+    // 1: the state is read and V_{n+1} written with non-temporal accesses (box or
+    // state arrays larger than the Infinity Cache, where caching these streams only
+    // evicts the V_n lines the neighbour gathers reuse)
+    int nt;
     // XCD-aware block mapping; dense boxes use 64 x 4 (x, y) tiles, gx * gy per plane
     int nblk, per_xcd;
     int gx, gy, zc;            // dense: tiles along x, y; planes per z-chunk

@@ -254,7 +254,7 @@ EnsArgs<T> make_args(const bbx_ensemble *e)
     a.apd = (T *)e->d_apd;
     a.vrep = (T *)e->d_vrep;
     // Measured on the 96-tissue FK4 ensemble (384 MB of state): 195 -> 182 us per step.
-    a.nt = (double)e->nvox * e->nvar * sizeof(T) > kNtStoreBytes;
+    a.nt = (double)e->nvox * e->nvar * sizeof(T) > kInfinityCacheBytes;
     return a;
 }
 

@@ -141,7 +141,7 @@ __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int id
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
     if constexpr (NT)
-        __builtin_nontemporal_store(Vn, &a.Vout[idx]);   // streaming write (a.nt_store)
+        __builtin_nontemporal_store(Vn, &a.Vout[idx]);   // streaming write (a.nt)
     else
         a.Vout[idx] = Vn;
 

@@ -212,7 +212,7 @@ static void launch_kernel(int aniso, const StepArgs<T> &a, hipStream_t s)
 template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
-    if (a.nt_store) launch_kernel<T, M, true>(aniso, a, s);
+    if (a.nt) launch_kernel<T, M, true>(aniso, a, s);
     else launch_kernel<T, M, false>(aniso, a, s);
     return hipGetLastError();
 }
