@@ -304,5 +304,6 @@ hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab
 BBX_INST(float)
 BBX_INST(double)
 template hipError_t launch_fill<uint8_t>(uint8_t *, uint8_t, int64_t, hipStream_t);
+template hipError_t launch_fill<int>(int *, int, int64_t, hipStream_t);
 
 }  // namespace bbx

@@ -297,9 +297,10 @@ int step_impl(bbx_grid *g, int64_t nsteps)
 {
     StepArgs<T> a = make_args<T>(g);
     const int nst = g->nvar - 1;
-    if (g->nan_every > 0) HIP_TRY(hipMemsetAsync(g->d_flag, 0, sizeof(int), g->stream), "hipMemsetAsync");
+    // a fill kernel, not a memset: a caller may capture bbx_step into a graph
+    if (g->nan_every > 0) HIP_TRY(launch_fill<int>(g->d_flag, 0, 1, g->stream), "flag clear");
     for (int64_t s = 0; s < nsteps; s++) {
-        const int64_t n = g->n + s;
+        const int64_t n = g->n;
         a.Vin = (const T *)g->d_V[g->cur];
         a.Vout = (T *)g->d_V[g->cur ^ 1];
         a.stim_on = g->stims.empty() ? 0u : stim_mask(g, n);
@@ -319,6 +320,7 @@ int step_impl(bbx_grid *g, int64_t nsteps)
             if (!done) HIP_TRY(launch_step<T>(g->model, g->aniso, a, g->stream), "step launch");
         }
         g->cur ^= 1;
+        g->n = n + 1;                  // clock and buffer parity stay consistent on errors
         if (g->ecg_every > 0 && (n + 1) % g->ecg_every == 0 && g->ecg_count < g->ecg_max && g->nact > 0) {
             StepArgs<T> b = a;
             b.Vin = (const T *)g->d_V[g->cur];
@@ -332,7 +334,6 @@ int step_impl(bbx_grid *g, int64_t nsteps)
                                         g->stream),
                     "finite check");
     }
-    g->n += nsteps;
     if (g->nan_every > 0) {
         HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense,
                                     (const T *)g->d_st, nst, g->nact, g->pitch, g->d_flag,
