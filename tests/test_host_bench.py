@@ -1,0 +1,48 @@
+"""Host-side checks of the benchmark script and the stored reference data (no GPU)."""
+import json
+import os
+import subprocess
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_1605_06015_amd import workloads as WL  # noqa: E402
+
+
+def test_bench_refuses_more_than_one_gpu():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode != 0
+    assert "one GPU" in (r.stdout + r.stderr)
+
+
+def test_counter_summary_is_consistent():
+    """The committed counter file of the headline kernel: bytes add up, the VALU count
+    is there, and the traffic is within 10% of the algorithmic bytes of the workload."""
+    d = json.load(open(os.path.join(ROOT, "profiles", "step_crn_cup128_fp32_traffic.json")))
+    assert d["bytes_per_launch"] == d["bytes_read"] + d["bytes_written"]
+    assert d["valu_insts_per_launch"] > 0 and d["waves_per_launch"] > 0
+    alg = bench.CRN_BYTES_PER_VOXEL * 367000
+    assert 0.9 * alg <= d["bytes_per_launch"] <= 1.1 * alg
+    assert len(d["source_hash"]) == 16
+
+
+def test_golden_maps_match_the_workload():
+    """The stored oracle maps belong to the current CRN cup: every sampled index is a
+    tissue voxel of the generator's mask, the sample is the file's 4,000 distinct voxels,
+    and the activation times grow with distance from the stimulated apex."""
+    d = np.loadtxt(bench.GOLDEN_MAPS, delimiter=",", skiprows=2)
+    idx, at, apd = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+    assert len(idx) == 4000 and len(np.unique(idx)) == 4000
+    c = WL.CRN_3D
+    g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
+    assert np.all(g["mask"].ravel()[idx] == 1)
+    assert np.all(np.isfinite(at)) and np.all(np.isfinite(apd))
+    z, y, x = np.unravel_index(idx, g["mask"].shape)
+    stim = np.argwhere(g["stim"] == 1).mean(axis=0)
+    dist = np.sqrt((z - stim[0]) ** 2 + (y - stim[1]) ** 2 + (x - stim[2]) ** 2)
+    assert np.corrcoef(dist, at)[0, 1] > 0.8
