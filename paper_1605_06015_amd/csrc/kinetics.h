@@ -33,13 +33,6 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float dv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double dv(double a, double b) { return a / b; }
-// e^{c x} for a coefficient c: FP32 folds c log2(e) into one constant for the
-// hardware exp2 (one multiply instead of two); FP64 computes exp(c x).
-__device__ __forceinline__ float exc(float x, double c)
-{
-    return __builtin_amdgcn_exp2f(x * (float)(c * 1.4426950408889634));
-}
-__device__ __forceinline__ double exc(double x, double c) { return exp(c * x); }
 
 // z / (e^z - 1).  Near z = 0 the quotient is 0/0; there the Bernoulli series
 // 1 - z/2 + z^2/12 - z^4/720 + z^6/30240 replaces it (next term z^8/1209600).
@@ -85,13 +78,6 @@ template <typename T>
 __device__ __forceinline__ T lgs(T x)
 {
     return rcp(T(1) + ex(x));
-}
-
-// Logistic 1 / (1 + e^{c x}).
-template <typename T>
-__device__ __forceinline__ T lgsc(T x, double c)
-{
-    return rcp(T(1) + exc(x, c));
 }
 
 // ---------------------------------------------------------------- pure diffusion
@@ -342,89 +328,89 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
     // fast sodium current gates m, h, j from opening/closing rates
     {
         T am = T(3.2) * bern(T(-0.1) * (V + T(47.13)));
-        T bm = T(0.08) * exc(V, -1.0 / 11.0);
+        T bm = T(0.08) * ex(-V * T(1.0 / 11.0));
         T ah, bh, aj, bj;
         if (V < T(-40)) {
-            ah = T(0.135) * exc(V + T(80), -1.0 / 6.8);
-            bh = T(3.56) * exc(V, 0.079) + T(3.1e5) * exc(V, 0.35);
-            aj = (T(-127140) * exc(V, 0.2444) - T(3.474e-5) * exc(V, -0.04391))
-                 * (V + T(37.78)) * lgsc(V + T(79.23), 0.311);
-            bj = T(0.1212) * exc(V, -0.01052) * lgsc(V + T(40.14), -0.1378);
+            ah = T(0.135) * ex((V + T(80)) * T(-1.0 / 6.8));
+            bh = T(3.56) * ex(T(0.079) * V) + T(3.1e5) * ex(T(0.35) * V);
+            aj = (T(-127140) * ex(T(0.2444) * V) - T(3.474e-5) * ex(T(-0.04391) * V))
+                 * (V + T(37.78)) * lgs(T(0.311) * (V + T(79.23)));
+            bj = T(0.1212) * ex(T(-0.01052) * V) * lgs(T(-0.1378) * (V + T(40.14)));
         } else {
             ah = T(0);
-            bh = T(1.0 / 0.13) * lgsc(V + T(10.66), -1.0 / 11.1);
+            bh = T(1.0 / 0.13) * lgs((V + T(10.66)) * T(-1.0 / 11.1));
             aj = T(0);
-            bj = T(0.3) * exc(V, -2.535e-7) * lgsc(V + T(32), -0.1);
+            bj = T(0.3) * ex(T(-2.535e-7) * V) * lgs(T(-0.1) * (V + T(32)));
         }
         T k = am + bm;
         c[CV_M] = am * rcp(k);
-        c[CV_MA] = exc(k, -(double)dt);
+        c[CV_MA] = ex(-dt * k);
         k = ah + bh;
         c[CV_H] = ah * rcp(k);
-        c[CV_HA] = exc(k, -(double)dt);
+        c[CV_HA] = ex(-dt * k);
         k = aj + bj;
         c[CV_J] = aj * rcp(k);
-        c[CV_JA] = exc(k, -(double)dt);
+        c[CV_JA] = ex(-dt * k);
     }
     // transient outward (oa, oi) and ultrarapid (ua, ui) potassium gates; the
     // activation rates of oa and ua share one form; Q10 factor 3
     {
-        T a_act = T(0.65) * rcp(exc(V + T(10), -1.0 / 8.5) + exc(V - T(30), -1.0 / 59.0));
-        T b_act = T(0.65) * rcp(T(2.5) + exc(V + T(82), 1.0 / 17.0));
-        const T ea = exc(a_act + b_act, -3.0 * (double)dt);
-        c[CV_OA] = lgsc(V + T(20.47), -1.0 / 17.54);
+        T a_act = T(0.65) * rcp(ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
+        T b_act = T(0.65) * rcp(T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
+        const T ea = ex(-dt * T(3) * (a_act + b_act));
+        c[CV_OA] = lgs((V + T(20.47)) * T(-1.0 / 17.54));
         c[CV_OAA] = ea;
-        c[CV_UA] = lgsc(V + T(30.3), -1.0 / 9.6);
+        c[CV_UA] = lgs((V + T(30.3)) * T(-1.0 / 9.6));
         c[CV_UAA] = ea;
-        T aoi = rcp(T(18.53) + exc(V + T(113.7), 1.0 / 10.95));
-        T boi = rcp(T(35.56) + exc(V + T(1.26), -1.0 / 7.44));
-        c[CV_OI] = lgsc(V + T(43.1), 1.0 / 5.3);
-        c[CV_OIA] = exc(aoi + boi, -3.0 * (double)dt);
-        T aui = rcp(T(21) + exc(V - T(185), -1.0 / 28.0));
-        T bui = exc(V - T(158), 1.0 / 16.0);
-        c[CV_UI] = lgsc(V - T(99.45), 1.0 / 27.48);
-        c[CV_UIA] = exc(aui + bui, -3.0 * (double)dt);
+        T aoi = rcp(T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
+        T boi = rcp(T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
+        c[CV_OI] = lgs((V + T(43.1)) * T(1.0 / 5.3));
+        c[CV_OIA] = ex(-dt * T(3) * (aoi + boi));
+        T aui = rcp(T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
+        T bui = ex((V - T(158)) * T(1.0 / 16.0));
+        c[CV_UI] = lgs((V - T(99.45)) * T(1.0 / 27.48));
+        c[CV_UIA] = ex(-dt * T(3) * (aui + bui));
     }
     // rapid and slow delayed rectifier gates
     {
         T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
         T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
-        c[CV_XR] = lgsc(V + T(14.1), -1.0 / 6.5);
-        c[CV_XRA] = exc(axr + bxr, -(double)dt);
+        c[CV_XR] = lgs((V + T(14.1)) * T(-1.0 / 6.5));
+        c[CV_XRA] = ex(-dt * (axr + bxr));
         T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
         T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
-        c[CV_XS] = rcp(sq(T(1) + exc(V - T(19.9), -1.0 / 12.7)));
-        c[CV_XSA] = exc(axs + bxs, -2.0 * (double)dt);
+        c[CV_XS] = rcp(sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7))));
+        c[CV_XSA] = ex(-dt * T(2) * (axs + bxs));
     }
     // L-type calcium gates d, f
     {
         T zd = (V + T(10)) * T(1.0 / 6.24);
         // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
         T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
-        c[CV_D] = lgsc(V + T(10), -1.0 / 8.0);
-        c[CV_DA] = exc(kd, -(double)dt);
+        c[CV_D] = lgs((V + T(10)) * T(-1.0 / 8.0));
+        c[CV_DA] = ex(-dt * kd);
         T vv = V + T(10);
         T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
-        c[CV_F] = lgsc(V + T(28), 1.0 / 6.9);
-        c[CV_FA] = exc(kf, -(double)dt);
+        c[CV_F] = lgs((V + T(28)) * T(1.0 / 6.9));
+        c[CV_FA] = ex(-dt * kf);
     }
     // release gate w
     {
         T zw = (V - T(7.9)) * T(0.2);
         // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
         T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
-        c[CV_W] = T(1) - lgsc(V - T(40), -1.0 / 17.0);
-        c[CV_WA] = exc(kw, -(double)dt);
+        c[CV_W] = T(1) - lgs((V - T(40)) * T(-1.0 / 17.0));
+        c[CV_WA] = ex(-dt * kw);
     }
     // voltage factors of currents
     {
         const T vf = V * T(1.0 / kRTF);
-        c[CV_K1] = lgsc(V + T(80), 0.07);
-        c[CV_KR] = lgsc(V + T(15), 1.0 / 22.4);
-        c[CV_GKUR] = T(0.005) + T(0.05) * lgsc(V - T(15), -1.0 / 13.0);
+        c[CV_K1] = lgs(T(0.07) * (V + T(80)));
+        c[CV_KR] = lgs((V + T(15)) * T(1.0 / 22.4));
+        c[CV_GKUR] = T(0.005) + T(0.05) * lgs((V - T(15)) * T(-1.0 / 13.0));
         const T sigma = T((8.006372134620099 - 1.0) / 7.0);  // (e^{[Na]o/67.3} - 1)/7
-        c[CV_FNAK] = rcp(T(1) + T(0.1245) * exc(vf, -0.1) + T(0.0365) * sigma * exc(vf, -1.0));
-        const T eg = exc(vf, 0.35), eg1 = exc(vf, -0.65);
+        c[CV_FNAK] = rcp(T(1) + T(0.1245) * ex(T(-0.1) * vf) + T(0.0365) * sigma * ex(-vf));
+        const T eg = ex(T(0.35) * vf), eg1 = ex(T(-0.65) * vf);
         const T den = T(kNaCa) * rcp(T(1) + T(0.1) * eg1);
         c[CV_EG] = eg * den;
         c[CV_EG1] = eg1 * den;
