@@ -132,7 +132,9 @@ enum { BBX_INFO_NACTIVE = 0, BBX_INFO_NVAR = 1, BBX_INFO_NBOX = 2, BBX_INFO_DEVI
  *   hip_stream     hipStream_t to enqueue on, or NULL.
  * Voxels outside the box count as void, which gives the no-flux condition at
  * the box faces too.  A tissue voxel whose fibre has length < 1e-12 gives
- * BBX_EINVAL.  Allocates device memory; *out receives the grid.
+ * BBX_EINVAL, and so does a box of more than 2^31 - 1 voxels (box indices are
+ * 32-bit).  Allocates device memory (two box-sized V arrays plus the per-tissue
+ * state); *out receives the grid.
  */
 int bbx_grid_create(int nx, int ny, int nz, double h, const uint8_t *mask, const double *fibre,
                     double D_par, double D_perp, int precision, void *hip_stream,
