@@ -98,3 +98,42 @@ def test_ensemble_at_voxel_limit_last_tissue_matches_alone():
     full = run(nx, ny)
     for v in range(2):
         assert np.array_equal(full[v], alone[v]), v
+
+
+@pytest.mark.parametrize("aniso", [True, False])
+def test_dense_box_beyond_cache_streaming_kernels_sampled(aniso):
+    """A dense 512x512x264 box (277 MB of V in FP32, above the 256 MB Infinity Cache, so
+    the streaming instantiations of the z-marching kernels run: the LDS ring with rotating
+    fibres, the register march when isotropic), pure diffusion of a smooth field for 3
+    steps: 32 sampled voxels match the FP64 oracle run on 9^3 crops around them (a value
+    after 3 steps depends only on voxels within 3 of it, plus the fibres one further)."""
+    from oracle import oracle as O
+    from paper_1605_06015_amd import bbx as B
+    nx, ny, nz, h, dt, Dpar, Dperp = 512, 512, 264, 0.25, 0.01, 0.3, 0.03
+    assert nx * ny * nz * 4 > 256 * 1024 * 1024
+    mask, fib = WL.full_box_rotating(nx, ny, nz)
+    if not aniso:
+        fib = None
+    z, y, x = np.ogrid[0:nz, 0:ny, 0:nx]
+    V = -60.0 + 20.0 * np.sin(0.05 * x + 0.3) * np.cos(0.07 * y) + 10.0 * np.sin(0.11 * z)
+    g = B.Grid(mask, h, fib, Dpar, Dperp, B.BBX_FP32)
+    g.model(B.BBX_MODEL_NONE, [], dt)
+    g.set(0, V)
+    g.step(3)
+    got = g.get(0)
+    g.close()
+    rng = np.random.default_rng(3)
+    picks = np.stack([rng.integers(0, nz, 32), rng.integers(0, ny, 32), rng.integers(0, nx, 32)], 1)
+    picks[:4] = [[0, 0, 0], [nz - 1, ny - 1, nx - 1], [nz // 2, 0, nx - 1], [nz - 1, ny // 2, 0]]
+    r = 4
+    Vb = np.broadcast_to(V, (nz, ny, nx))
+    for c in picks:
+        sl = tuple(slice(max(0, c[i] - r), min((nz, ny, nx)[i], c[i] + r + 1)) for i in range(3))
+        cm = np.ascontiguousarray(mask[sl])
+        cf = None if fib is None else np.ascontiguousarray(fib[sl])
+        s = O.Sim(cm, h, cf, Dpar, Dperp, O.MODEL_NONE, [], dt)
+        s.state[0] = Vb[sl]
+        s.step(3)
+        loc = tuple(int(c[i] - sl[i].start) for i in range(3))
+        want = s.state[0][loc]
+        assert abs(got[tuple(c)] - want) <= 1e-4, (tuple(c), got[tuple(c)], want)
