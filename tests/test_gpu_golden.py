@@ -66,3 +66,29 @@ def test_crn_headline_500ms_against_oracle_maps(prec):
     else:
         assert dat <= WL.CRN_3D["dt"] + 1e-9, dat
         assert dapd <= 2.0, dapd
+
+
+def test_crn_headline_500ms_tabulated_against_oracle_maps():
+    """The FP32 step with the CRN voltage terms read from a table (spacing 0.05 mV, the
+    benchmark's tabulated run) over the same 500 ms: activation times within 1 dt and APD90
+    within 2 ms of the untabulated FP64 oracle's maps, same activated voxels."""
+    from paper_1605_06015_amd import bbx as B
+    idx, at_o, apd_o = load_golden()
+    c = WL.CRN_3D
+    g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
+    grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32)
+    grid.model(B.BBX_MODEL_CRN, [], c["dt"])
+    grid.tabulate(0.05)
+    for v in range(21):
+        grid.set(v, g["state"][v])
+    grid.stimulus(g["stim"], c["stim_amp"], 0.0, c["stim_ms"])
+    grid.record(c["theta"])
+    grid.step(int(round(c["t_end"] / c["dt"])))
+    at = grid.read(B.BBX_READ_ACT_TIME).ravel()[idx]
+    apd = grid.read(B.BBX_READ_APD90).ravel()[idx]
+    assert np.array_equal(np.isnan(at), np.isnan(at_o))
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+    dat = np.abs(at[fa] - at_o[fa]).max()
+    dapd = np.abs(apd[fp] - apd_o[fp]).max()
+    print(f"tabulated: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
+    assert dat <= c["dt"] + 1e-9 and dapd <= 2.0, (dat, dapd)
