@@ -92,3 +92,40 @@ def test_crn_headline_500ms_tabulated_against_oracle_maps():
     dapd = np.abs(apd[fp] - apd_o[fp]).max()
     print(f"tabulated: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
     assert dat <= c["dt"] + 1e-9 and dapd <= 2.0, (dat, dapd)
+
+
+TP06_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tp06_cup64_at_apd.csv")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tp06_cup_500ms_against_oracle_maps(prec):
+    """TP06 on a 64x64x32 cup for 500 ms (dt 0.02 ms) against the FP64 oracle's activation
+    times and APD90 at 4,000 seeded tissue voxels (tests/golden/tp06_cup64_at_apd.csv, made
+    by make_tp06_cup_maps.py).  FP64 to the file's 9 significant digits (2e-6 ms).  FP32:
+    same activated voxels, activation times within 1 dt, APD90 within 0.5 ms: at the 90%
+    level a single FP64 oracle cell repolarises at 2.1 mV/ms, so the 0.5 mV bar moves the
+    crossing by about 0.24 ms; the bound leaves room for slopes down to 1 mV/ms in tissue."""
+    from paper_1605_06015_amd import bbx as B
+    d = np.loadtxt(TP06_GOLDEN, delimiter=",", skiprows=2)
+    idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+    g = WL.tp06_cup(64, 64, 32, seed=5, h=0.25)
+    grid = B.Grid(g["mask"], 0.25, g["fibre"], 0.3, 0.03, prec)
+    grid.model(B.BBX_MODEL_TP06, [], 0.02)
+    for v in range(19):
+        grid.set(v, g["state"][v])
+    grid.stimulus(g["stim"], 60.0, 0.0, 2.0)
+    grid.record(-40.0)
+    grid.step(25000)
+    at = grid.read(B.BBX_READ_ACT_TIME).ravel()[idx]
+    apd = grid.read(B.BBX_READ_APD90).ravel()[idx]
+    assert np.array_equal(np.isnan(at), np.isnan(at_o))
+    assert np.array_equal(np.isnan(apd), np.isnan(apd_o))
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+    assert fa.mean() > 0.9 and fp.mean() > 0.9
+    dat = np.abs(at[fa] - at_o[fa]).max()
+    dapd = np.abs(apd[fp] - apd_o[fp]).max()
+    print(f"tp06 prec {prec}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
+    if prec == 1:
+        assert dat <= 2e-6 and dapd <= 2e-6, (dat, dapd)
+    else:
+        assert dat <= 0.02 + 1e-9 and dapd <= 0.5, (dat, dapd)

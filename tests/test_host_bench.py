@@ -46,3 +46,17 @@ def test_golden_maps_match_the_workload():
     stim = np.argwhere(g["stim"] == 1).mean(axis=0)
     dist = np.sqrt((z - stim[0]) ** 2 + (y - stim[1]) ** 2 + (x - stim[2]) ** 2)
     assert np.corrcoef(dist, at)[0, 1] > 0.8
+
+
+def test_tp06_golden_maps_match_the_workload():
+    """The stored TP06 oracle maps belong to the current 64x64x32 TP06 cup."""
+    path = os.path.join(ROOT, "tests", "golden", "tp06_cup64_at_apd.csv")
+    d = np.loadtxt(path, delimiter=",", skiprows=2)
+    idx, at = d[:, 0].astype(np.int64), d[:, 1]
+    assert len(idx) == 4000 and len(np.unique(idx)) == 4000
+    g = WL.tp06_cup(64, 64, 32, seed=5, h=0.25)
+    assert np.all(g["mask"].ravel()[idx] == 1)
+    z, y, x = np.unravel_index(idx, g["mask"].shape)
+    stim = np.argwhere(g["stim"] == 1).mean(axis=0)
+    dist = np.sqrt((z - stim[0]) ** 2 + (y - stim[1]) ** 2 + (x - stim[2]) ** 2)
+    assert np.corrcoef(dist, at)[0, 1] > 0.8
