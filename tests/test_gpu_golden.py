@@ -129,3 +129,36 @@ def test_tp06_cup_500ms_against_oracle_maps(prec):
         assert dat <= 2e-6 and dapd <= 2e-6, (dat, dapd)
     else:
         assert dat <= 0.02 + 1e-9 and dapd <= 0.5, (dat, dapd)
+
+
+FK4_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "fk4_ens_smallest_at_apd.csv")
+
+
+def test_fk4_ensemble_full_protocol_against_oracle_maps():
+    """The 96-tissue FK4 ensemble run as the benchmark runs it (tuned tile, graph replay in
+    chunks of 1,000 steps, FP32, the whole 20,000-step S1-S2 protocol): the smallest tissue's
+    activation times (threshold 0.5) and APD90 against the FP64 oracle's at 3,000 seeded
+    voxels (tests/golden/fk4_ens_smallest_at_apd.csv, made by make_fk4_tissue_maps.py).
+    Bars: same activated voxels, activation times within 1 dt (0.05 ms), APD90 within 0.75 ms
+    (the 0.0075 bar on u over the 0.020/ms slope of u at the 90% level of a single FP64
+    oracle cell is 0.37 ms)."""
+    import torch
+    import bench
+    from paper_1605_06015_amd import bbx as B
+    d = np.loadtxt(FK4_GOLDEN, delimiter=",", skiprows=2)
+    idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+    e, w, c = bench.ensemble_workload(torch.cuda.current_stream())
+    i = int(np.argmin(w["nx"]))
+    e.tune(20)
+    e.graph(1000)
+    e.step(c["steps"])
+    at = e.read(B.BBX_READ_ACT_TIME, i).ravel()[idx]
+    apd = e.read(B.BBX_READ_APD90, i).ravel()[idx]
+    e.close()
+    assert np.array_equal(np.isnan(at), np.isnan(at_o))
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+    assert fa.all() and fp.mean() > 0.9
+    dat = np.abs(at[fa] - at_o[fa]).max()
+    dapd = np.abs(apd[fp] - apd_o[fp]).max()
+    print(f"fk4 ensemble tissue {i}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
+    assert dat <= c["dt"] + 1e-9 and dapd <= 0.75, (dat, dapd)
