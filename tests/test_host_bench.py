@@ -60,3 +60,22 @@ def test_tp06_golden_maps_match_the_workload():
     stim = np.argwhere(g["stim"] == 1).mean(axis=0)
     dist = np.sqrt((z - stim[0]) ** 2 + (y - stim[1]) ** 2 + (x - stim[2]) ** 2)
     assert np.corrcoef(dist, at)[0, 1] > 0.8
+
+
+def test_fk4_golden_maps_match_the_workload():
+    """The stored FK4 maps belong to the smallest tissue of the current ensemble workload,
+    and its S1 wave (from the left columns) activates voxels later further right."""
+    path = os.path.join(ROOT, "tests", "golden", "fk4_ens_smallest_at_apd.csv")
+    head = open(path).readline()
+    d = np.loadtxt(path, delimiter=",", skiprows=2)
+    idx, at = d[:, 0].astype(np.int64), d[:, 1]
+    c = WL.FK4_ENSEMBLE
+    w = WL.fk4_ensemble(n=c["n"], side_lo=c["side_lo"], side_hi=c["side_hi"], seed=c["seed"],
+                        h=c["h"], Dpar=c["Dpar"], aniso=c["aniso"], spread=c["spread"],
+                        s1_amp=c["s1_amp"], s1_ms=c["s1_ms"], apd_est_ms=c["apd_est_ms"],
+                        cv_est_mm_ms=c["cv_est_mm_ms"])
+    i = int(np.argmin(w["nx"]))
+    s = int(w["nx"][i])
+    assert f"tissue {i} ({s}x{s}" in head
+    assert len(np.unique(idx)) == len(idx) == 3000 and idx.max() < s * s
+    assert np.corrcoef(idx % s, at)[0, 1] > 0.5
