@@ -29,21 +29,29 @@ namespace bbx {
 // workgroup, dealt to workgroups by workgroup_tile.
 // Workgroup -> tile.  Cached case: XCD k takes the k-th contiguous eighth of the tiles,
 // so each XCD's L2 keeps its part of the data from step to step.  Streaming case (data
-// larger than the Infinity Cache, nothing survives to the next step): tiles in launch
-// order, so the workgroups running at any moment sweep one region of memory together
-// (measured: TP06 double shell 0.977 -> 0.918 ms, 300^3 CRN box 1.010 -> 0.959 ms, dense
-// stencil 635 -> 623 us; the cache-resident cases lose with it).
-template <bool NT, typename T>
+// larger than the Infinity Cache, nothing survives to the next step): the tiles go out in
+// rounds of 8 * SL, XCD k taking the k-th run of SL consecutive tiles of each round, so the
+// workgroups running at any moment sweep one region of memory together while each XCD
+// still shares some halo with itself.  SL = 1 is plain launch order.  Measured: launch
+// order for the tissue list (TP06 double shell 0.977 -> 0.918 ms, 300^3 CRN box 1.010 ->
+// 0.959 ms; runs of 4-64 were slower) and the isotropic register march (200 us; 210 with
+// runs of 64); runs of 64 for the LDS-ring stencil (635 -> 600 us; 623 in launch order,
+// 615 with runs of 256 or 1024).  The cache-resident cases lose with either.
+template <bool NT, int SL, typename T>
 __device__ __forceinline__ int workgroup_tile(const StepArgs<T> &a)
 {
-    if (NT) return (int)blockIdx.x;
-    return (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
+    const int x = (int)(blockIdx.x % kXcd), i = (int)(blockIdx.x / kXcd);
+    if (!NT) return x * a.per_xcd + i;
+    const int full = a.per_xcd / SL * SL;           // per XCD: blocks in complete rounds
+    if (i < full) return (i / SL) * (kXcd * SL) + x * SL + (i % SL);
+    const int rem = a.per_xcd - full;                // the last, shorter round
+    return full * kXcd + x * rem + (i - full);
 }
 
 template <typename T, class M, bool ANISO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step(const StepArgs<T> a)
 {
-    const int lb = workgroup_tile<NT>(a);
+    const int lb = workgroup_tile<NT, 1>(a);
     if (lb >= a.nblk) return;
     const int t = lb * kBlock + (int)threadIdx.x;
     if (t >= a.nact) return;
@@ -107,7 +115,7 @@ template <typename T, class M, bool ANISO, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
 {
     __shared__ T ring[3][kPlane];
-    const int lb = workgroup_tile<NT>(a);
+    const int lb = workgroup_tile<NT, 64>(a);
     if (lb >= a.nblk) return;                       // workgroup-uniform exit
     const int bx = lb % a.gx, r = lb / a.gx;
     const int by = r % a.gy, bz = r / a.gy;
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
 template <typename T, class M, bool NT>
 __global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
 {
-    const int lb = workgroup_tile<NT>(a);
+    const int lb = workgroup_tile<NT, 1>(a);
     if (lb >= a.nblk) return;
     const int bx = lb % a.gx, r = lb / a.gx;
     const int by = r % a.gy, bz = r / a.gy;
