@@ -16,9 +16,8 @@
 //
 // Memory: V lives in box layout (neighbour gathers; void entries stay 0 and are
 // never selected), everything else is structure-of-arrays over the tissue list
-// (coalesced, x-fastest order).  When the data fits the Infinity Cache,
-// workgroups are remapped so that each XCD works on one contiguous slab of the
-// tissue list, keeping neighbour planes in that XCD's L2 (workgroup_tile).
+// (coalesced, x-fastest order).  Workgroups are dealt to tiles in per-XCD runs
+// (workgroup_tile), so that neighbour rows and planes tend to stay in one XCD's L2.
 #include <type_traits>
 
 #include "step_device.h"
@@ -27,23 +26,25 @@ namespace bbx {
 
 // Tissue-list path: one thread per tissue voxel, 256 consecutive list entries per
 // workgroup, dealt to workgroups by workgroup_tile.
-// Workgroup -> tile.  Cached case: XCD k takes the k-th contiguous eighth of the tiles,
-// so each XCD's L2 keeps its part of the data from step to step.  Streaming case (data
-// larger than the Infinity Cache, nothing survives to the next step): the tiles go out in
-// rounds of 8 * SL, XCD k taking the k-th run of SL consecutive tiles of each round, so the
-// workgroups running at any moment sweep one region of memory together while each XCD
-// still shares some halo with itself.  SL = 1 is plain launch order.  Measured: launch
-// order for the tissue list (TP06 double shell 0.977 -> 0.918 ms, 300^3 CRN box 1.010 ->
-// 0.959 ms; runs of 4-64 were slower) and the isotropic register march (200 us; 210 with
-// runs of 64); runs of 64 for the LDS-ring stencil (635 -> 600 us; 623 in launch order,
-// 615 with runs of 256 or 1024).  The cache-resident cases lose with either.
+// Workgroup -> tile.  The tiles go out in rounds: XCD k takes the k-th run of S
+// consecutive tiles of each round of 8 * S (then a last, shorter round), so that each XCD
+// shares halos within its runs while the workgroups running at any moment stay within one
+// region of memory.  Data that fits the Infinity Cache: runs of 256 (for up to 256
+// workgroups per XCD this is one contiguous eighth of the tiles per XCD, so each XCD's L2
+// keeps its part from step to step; measured: thin CRN shell 59.3 -> 56.7 us against
+// eighths, CRN cup 14.2 us either way, 14.7 with runs of 16).  Streaming data (larger than
+// the cache): runs of SL, measured per kernel: launch order (SL = 1) for the tissue list
+// (TP06 double shell 0.977 -> 0.918 ms, 300^3 CRN box 1.010 -> 0.959 ms against eighths;
+// runs of 4-64 were slower) and for the isotropic register march (200 us; 210 with runs of
+// 64); runs of 64 for the LDS-ring stencil (635 -> 600 us; 623 in launch order, 615 with
+// runs of 256 or 1024).
 template <bool NT, int SL, typename T>
 __device__ __forceinline__ int workgroup_tile(const StepArgs<T> &a)
 {
+    constexpr int S = NT ? SL : 256;
     const int x = (int)(blockIdx.x % kXcd), i = (int)(blockIdx.x / kXcd);
-    if (!NT) return x * a.per_xcd + i;
-    const int full = a.per_xcd / SL * SL;           // per XCD: blocks in complete rounds
-    if (i < full) return (i / SL) * (kXcd * SL) + x * SL + (i % SL);
+    const int full = a.per_xcd / S * S;             // per XCD: blocks in complete rounds
+    if (i < full) return (i / S) * (kXcd * S) + x * S + (i % S);
     const int rem = a.per_xcd - full;                // the last, shorter round
     return full * kXcd + x * rem + (i - full);
 }
