@@ -234,7 +234,8 @@ StepArgs<T> make_args(const bbx_grid *g)
         a.nblk = a.gx * a.gy * ((g->nz + zc - 1) / zc);
     } else {
         a.zc = 0;
-        a.nblk = (int)((g->nact + kBlock - 1) / kBlock);
+        const int wg = a.nt ? kStreamBlock : kBlock;   // the tissue-list kernel's workgroup
+        a.nblk = (int)((g->nact + wg - 1) / wg);
     }
     a.per_xcd = (a.nblk + kXcd - 1) / kXcd;
     return a;

@@ -7,6 +7,7 @@
 namespace bbx {
 
 constexpr int kBlock = 256;      // threads per workgroup (4 wave64)
+constexpr int kStreamBlock = 512; // tissue-list step on data beyond the Infinity Cache
 constexpr int kMaxStim = 32;     // stimuli per grid (bit per stimulus in a uint32)
 constexpr int kMaxParams = 8;    // model parameters
 constexpr int kXcd = 8;          // MI355X: 8 XCDs, workgroups dealt round-robin
