@@ -33,13 +33,19 @@ PROFILE_DIR = os.path.join(ROOT, "profiles")
 STEP_SOURCES = [os.path.join(ROOT, "paper_1605_06015_amd", "csrc", f)
                 for f in ("step_kernels.hip", "step_device.h", "kinetics.h", "bbx_internal.h")]
 
-# Algorithmic HBM bytes per tissue-voxel update of the fused CRN step in FP32:
-# 21 state values read + 21 written (4 B each) + geometry (box index 4, neighbour
-# bits 4, unit fibre 12, tensor-gradient face coefficients 12) + status byte 1.
-CRN_BYTES_PER_VOXEL = 21 * 4 * 2 + 32 + 1
-# Pure-diffusion stencil, FP32, dense anisotropic box: V read + V written + fibre +
-# face coefficients (no index / bit arrays on a dense box).
-STENCIL_BYTES_PER_VOXEL = 4 + 4 + 12 + 12
+# Algorithmic HBM bytes per tissue-voxel update (what the method must move: state read
+# and written, the geometry the stencil needs at its floor, the recorder's status byte).
+# Fused CRN step, FP32: 21 values read + 21 written (4 B each) + the mask bit and unit
+# fibre (13 B) + status byte = 182 B.  The library's own layout moves more: a 4-byte box
+# index and 4-byte neighbour bits instead of the mask bit, and 12 B of precomputed face
+# coefficients of the tensor-gradient term beside the fibre: 201 B.
+CRN_BYTES_PER_VOXEL = 21 * 4 * 2 + 13 + 1
+CRN_LAYOUT_BYTES_PER_VOXEL = 21 * 4 * 2 + 32 + 1
+# Pure-diffusion stencil, FP32, dense anisotropic box: V read + V written + fibre (the
+# floor, every voxel tissue: no mask needed); the library streams 12 B of face
+# coefficients beside the fibre (32 B).
+STENCIL_BYTES_PER_VOXEL = 4 + 4 + 12
+STENCIL_LAYOUT_BYTES_PER_VOXEL = 4 + 4 + 12 + 12
 
 
 def source_hash(paths=STEP_SOURCES) -> str:
@@ -78,6 +84,27 @@ def time_steps(grid, stream, steps, warmup):
     return e0.elapsed_time(e1) / 1e3  # seconds
 
 
+def differenced(grid, stream, n1=100, n2=1000, reps=5):
+    """Per-step seconds by the paper's two-run differencing ("Parallel scaling
+    performance"): (T(n2) - T(n1)) / (n2 - n1), HIP events on the launch stream, median
+    of `reps` pairs.  Removes the fixed start and end cost of a timed region."""
+    import torch
+    out = []
+    for _ in range(reps):
+        ts = []
+        for n in (n1, n2):
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            grid.step(n)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        out.append((ts[1] - ts[0]) / (n2 - n1))
+    return float(np.median(out)), [float(x) for x in out]
+
+
 def crn_workload(precision, stream, tab_dv=0.0):
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import workloads as WL
@@ -94,9 +121,24 @@ def crn_workload(precision, stream, tab_dv=0.0):
     return grid, g
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo) and what nproc reports."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
 def cpu_baseline(seconds_target=12.0):
     """The FP64 oracle on the same workload, timed on this host's cores over a bounded
-    number of steps (per-step time by differencing two runs)."""
+    number of steps, per-step time by differencing two runs ("Parallel scaling
+    performance"), plus a few steps on one core.  Threads: the CPUs this process may run
+    on, up to 16 (the host's CPU share per GPU on the measurement machines)."""
     from oracle import oracle as O
     from paper_1605_06015_amd import workloads as WL
     c = WL.CRN_3D
@@ -112,27 +154,28 @@ def cpu_baseline(seconds_target=12.0):
     s.stimuli.append(O.Stimulus(g["stim"], c["stim_amp"], 0, int(round(c["stim_ms"] / c["dt"]))))
     t0 = time.perf_counter()
     s.step(2)
+    per = max((time.perf_counter() - t0) / 2, 1e-4)
+    n1 = max(2, int(0.2 * seconds_target / per))
+    n2 = n1 + max(4, int(0.8 * seconds_target / per))
     t1 = time.perf_counter()
-    per = max((t1 - t0) / 2, 1e-4)
-    n1 = 2
-    n2 = n1 + max(4, int(seconds_target / per))
+    s.step(n1)
     t2 = time.perf_counter()
-    s.step(n2 - n1)
+    s.step(n2)
     t3 = time.perf_counter()
-    per_step = (t3 - t2) / (n2 - n1)
+    per_step = ((t3 - t2) - (t2 - t1)) / (n2 - n1)
     nact = int(g["mask"].sum())
-    # the same oracle on one core, a few steps (context: the scalar reference rate)
     s1 = O.Sim(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], O.MODEL_CRN, [], c["dt"],
                nthreads=1)
     s1.state[:] = s.state
     t4 = time.perf_counter()
     s1.step(3)
     serial = nact * 3 / (time.perf_counter() - t4)
+    model, nproc = cpu_model()
     return {"value": nact / per_step, "unit": "voxel-updates/s", "cores": nthreads,
-            "kind": "oracle", "serial_value": serial,
-            "sample": f"CRN 128x128x64 cup ({nact} tissue voxels), FP64 oracle, {n2 - n1} steps "
-                      f"after 2 warm-up steps, {t3 - t2:.1f} s, OpenMP over voxels "
-                      f"(serial_value: 3 steps on one core)"}
+            "kind": "oracle", "serial_value": serial, "cpu_model": model, "nproc": nproc,
+            "sample": f"CRN 128x128x64 cup ({nact} tissue voxels), FP64 oracle (OpenMP over "
+                      f"voxels, {nthreads} threads), per-step time from runs of {n1} and {n2} "
+                      f"steps ({t3 - t1:.1f} s); serial_value: 3 steps on one core"}
 
 
 _SHELL = {}
@@ -144,7 +187,7 @@ def shell_geometry():
     if "g" not in _SHELL:
         c = WL.TP06_3D
         _SHELL["g"] = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"],
-                                  c["s1_radius"])
+                                  c["s1_strip"])
     return _SHELL["g"]
 
 
@@ -193,12 +236,14 @@ def paper_shape_line(stream, n=300, steps=200, warmup=20):
     nact = grid.nact
     grid.close()
     per = sec / steps
-    bpv = 21 * 4 * 2 + 24              # dense box: no index / neighbour-bit arrays, no recorder
+    bpv = 21 * 4 * 2 + 12              # state r/w + fibre: every voxel tissue, no recorder
     gbs = bpv * nact / per / 1e9
     return {"workload": f"CRN dense {n}^3 box, fibres rotating through z, FP32, {steps} steps",
             "value": nact / per, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bpv}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bpv,
+                         "layout_bytes_per_voxel": 21 * 4 * 2 + 24},
+            "error_vs_fp64": "not measured here"}
 
 
 def barkley_line(stream):
@@ -222,35 +267,81 @@ def barkley_line(stream):
 
 
 GOLDEN_MAPS = os.path.join(ROOT, "tests", "golden", "crn_cup128_at_apd.csv")
+GOLDEN_TRACES = os.path.join(ROOT, "tests", "golden", "crn_cup128_v_traces.npz")
 
 
-def headline_accuracy(stream):
-    """The headline workload run in FP32 for its full 500 ms, in the timed launch
-    configuration, against the FP64 oracle's activation times and APD90 at 4,000 seeded
-    tissue voxels (a file the oracle wrote)."""
+def headline_accuracy(stream, precision=None, timed=False):
+    """The headline workload run for its full 500 ms in the timed launch configuration,
+    against the FP64 oracle's stored results at 4,000 seeded tissue voxels (files the
+    oracle wrote): activation times, APD90, and V every 1 ms.  With timed=True also the
+    run's wall time on the GPU (HIP events)."""
+    import torch
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import workloads as WL
-    if not os.path.exists(GOLDEN_MAPS):
+    if not (os.path.exists(GOLDEN_MAPS) and os.path.exists(GOLDEN_TRACES)):
         return None
+    precision = B.BBX_FP32 if precision is None else precision
     d = np.loadtxt(GOLDEN_MAPS, delimiter=",", skiprows=2)
     idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
-    grid, _ = crn_workload(B.BBX_FP32, stream)
+    tr = np.load(GOLDEN_TRACES)
+    tidx, V_o = tr["idx"], tr["V"].astype(np.float64)
+    every = int(round((tr["t_ms"][1] - tr["t_ms"][0]) / WL.CRN_3D["dt"]))
+    grid, g = crn_workload(precision, stream)
+    grid.nan_check(0)
     n = int(round(WL.CRN_3D["t_end"] / WL.CRN_3D["dt"]))
-    grid.step(n)
+    buf = torch.empty(g["mask"].size, dtype=torch.float64, device="cuda")
+    sel = torch.from_numpy(tidx).cuda()
+    Vg = torch.empty(V_o.shape, dtype=torch.float64, device="cuda")
+    sec = 0.0
+    for k in range(n // every):
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        grid.step(every)
+        if timed:
+            e1.record(stream)
+        B.bbx_readout(grid.handle, B.BBX_READ_VAR, 0, None, buf.data_ptr(), buf.numel() * 8, 1)
+        Vg[k] = buf[sel]
+        if timed:
+            torch.cuda.synchronize()
+            sec += e0.elapsed_time(e1) / 1e3
     at = grid.read(B.BBX_READ_ACT_TIME).ravel()[idx]
     apd = grid.read(B.BBX_READ_APD90).ravel()[idx]
     grid.close()
+    dV = np.abs(Vg.cpu().numpy() - V_o)
     fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
 
     def fin(x):
         return float(x) if np.isfinite(x) else None
     ea, ep = np.abs(at[fa] - at_o[fa]), np.abs(apd[fp] - apd_o[fp])
-    return {"reference": "FP64 oracle, 500 ms, 4000 seeded tissue voxels",
-            "dt_ms": WL.CRN_3D["dt"],
-            "same_activated_set": bool(np.array_equal(np.isfinite(at), fa)),
-            "same_repolarised_set": bool(np.array_equal(np.isfinite(apd), fp)),
-            "at_max_err_ms": fin(ea.max()), "at_mean_err_ms": fin(ea.mean()),
-            "apd90_max_err_ms": fin(ep.max()), "apd90_mean_err_ms": fin(ep.mean())}
+    out = {"reference": "FP64 oracle, 500 ms, 4000 seeded tissue voxels (V every 1 ms)",
+           "dt_ms": WL.CRN_3D["dt"],
+           "same_activated_set": bool(np.array_equal(np.isfinite(at), fa)),
+           "same_repolarised_set": bool(np.array_equal(np.isfinite(apd), fp)),
+           "at_max_err_ms": fin(ea.max()), "at_mean_err_ms": fin(ea.mean()),
+           "apd90_max_err_ms": fin(ep.max()), "apd90_mean_err_ms": fin(ep.mean()),
+           "v_max_err_mV": float(dV.max()), "v_mean_err_mV": float(dV.mean()),
+           "v_samples": int(dV.size)}
+    if timed:
+        out["run_s"] = sec
+    return out
+
+
+def fp64_line(stream):
+    """The headline workload in FP64 (the parity mode): voxel-updates/s by differencing,
+    and the full 500 ms run against the oracle's stored results."""
+    from paper_1605_06015_amd import bbx as B
+    grid, _ = crn_workload(B.BBX_FP64, stream)
+    grid.nan_check(0)
+    grid.step(50)
+    per, reps = differenced(grid, stream, 100, 600, 3)
+    nact = grid.nact
+    grid.close()
+    acc = headline_accuracy(stream, B.BBX_FP64)
+    return {"workload": "CRN atrial 3D, 128x128x64 cup (the headline workload), FP64 state, stencil "
+                        "and kinetics", "value": nact / per, "unit": "voxel-updates/s",
+            "ms_per_step": per * 1e3, "timing": "differenced 600 - 100 steps, median of 3",
+            "error_vs_fp64_oracle": acc}
 
 
 def thin_shell_line(stream, steps=500, warmup=50):
@@ -268,11 +359,14 @@ def thin_shell_line(stream, steps=500, warmup=50):
     nact = grid.nact
     grid.close()
     per = sec / steps
-    gbs = 200 * nact / per / 1e9                       # 201 B/voxel without the recorder byte
+    bpv = CRN_BYTES_PER_VOXEL - 1                     # no recorder
+    gbs = bpv * nact / per / 1e9
     return {"workload": f"CRN thin double shell, 237x271x300 box, 8.3% active ({nact} tissue voxels), FP32",
             "value": nact / per, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": 200}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": bpv,
+                         "layout_bytes_per_voxel": CRN_LAYOUT_BYTES_PER_VOXEL - 1},
+            "error_vs_fp64": "not measured here"}
 
 
 def stencil_roofline(stream, steps=100, warmup=10):
@@ -295,6 +389,8 @@ def stencil_roofline(stream, steps=100, warmup=10):
     return {"workload": "pure diffusion, dense 512x512x384, 19-point, rotating fibres, FP32",
             "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": STENCIL_BYTES_PER_VOXEL,
+            "layout_bytes_per_voxel": STENCIL_LAYOUT_BYTES_PER_VOXEL,
+            "error_vs_fp64": "not measured here (FP64 parity of the stencil: tests)",
             "us_per_launch": round(per_launch * 1e6, 2),
             "voxel_updates_per_s": nact / per_launch,
             "device_copy_GBs": round(copy_bandwidth(stream), 1)}
@@ -319,11 +415,13 @@ def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / sec / 1e9
 
 
-def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000, v_hi=-81.0):
+def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000):
     """Surrogate-with-fallback on the 128x128x64 cup with `model` kinetics: train on paced
-    runs of the cup (outside the timed region), anchor the resting state, then time a full
-    run with the plain FP32 kinetics and with the surrogate accepting tissue below v_hi mV,
-    and compare activation-time and APD90 maps."""
+    runs of the cup (outside the timed region), anchor the resting state, choose the
+    acceptance threshold v_hi on a held-out cup (another geometry seed, 96x96x48), then time
+    the full run of the benchmark cup with the plain FP32 kinetics and with the surrogate,
+    and compare activation-time and APD90 maps (against the plain run, and for CRN against
+    the FP64 oracle's stored maps)."""
     import torch
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import surrogate as SU
@@ -338,50 +436,36 @@ def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000, v_hi=-81.0):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del S, S1
+    v_hi, sweep = SU.select_threshold(tr, model, stream=stream)
+    t3 = time.perf_counter()
+    out = {"workload": f"{model.upper()} cup 128x128x64, {t_ms:.0f} ms, FP32, surrogate {nv}-128-128-{nv} "
+                       "SiLU (BF16 MFMA, FP32 accumulate) with per-voxel fallback",
+           "unit": "voxel-updates/s",
+           "threshold_selection": {"held_out": "cup 96x96x48, geometry seed 11 (the benchmark cup: seed "
+                                               f"{c['seed']})", "rule": "largest share with AT within "
+                                               "0.5 dt of plain", "chosen_v_hi_mV": v_hi,
+                                   "sweep": {str(k): v for k, v in sweep.items()},
+                                   "seconds": round(t3 - t2, 2)},
+           "training": {"pairs": tr.npairs, "iters": iters, "batch": 4096,
+                        "final_loss": float(np.mean(tr.loss[-100:])), "gen_s": round(t1 - t0, 2),
+                        "train_s": round(t2 - t1, 2)}}
+    if v_hi is None:
+        out["value"] = None
+        out["note"] = "no threshold met the accuracy rule on the held-out cup"
+        return out
+    plain, res, dt = SU.run_pair(tr, model, c["seed"], 128, 128, 64, t_ms, (v_hi,), stream)
+    r = res[float(v_hi)]
     nsteps = int(round(t_ms / c["dt"]))
-    g = geo(128, 128, 64, seed=c["seed"], active=c["active"], h=c["h"])
-    m = g["mask"] == 1
-    res = {}
-    for name in ("plain", "surrogate"):
-        grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
-        grid.model(mid, [], c["dt"])
-        for v in range(nv):
-            grid.set(v, g["state"][v])
-        grid.stimulus(g["stim"], amp, 0.0, dur)
-        grid.record(-40.0)
-        grid.nan_check(0)
-        if name == "surrogate":
-            lo, hi, dv = SU.accepted_box(tr.stats, nvar=nv)
-            hi[0] = v_hi                      # the network handles tissue below v_hi only
-            grid.surrogate(tr.mlp, lo, hi, dv)
-        sec = time_steps(grid, stream, nsteps, 0)
-        res[name] = dict(sec=sec, at=grid.read(B.BBX_READ_ACT_TIME)[m], apd=grid.read(B.BBX_READ_APD90)[m],
-                         fb=int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]), nact=grid.nact)
-        grid.close()
-    p, q = res["plain"], res["surrogate"]
-    both = np.isfinite(p["at"]) & np.isfinite(q["at"])
-    dat = np.abs(p["at"][both] - q["at"][both])
-    bapd = np.isfinite(p["apd"]) & np.isfinite(q["apd"])
-    dapd = np.abs(p["apd"][bapd] - q["apd"][bapd])
-    value = q["nact"] * nsteps / q["sec"]
-    return {"workload": f"{model.upper()} cup 128x128x64, {t_ms:.0f} ms, FP32, surrogate {nv}-128-128-{nv} "
-                        "SiLU (BF16 MFMA, FP32 accumulate) with per-voxel fallback",
-            "value": value, "unit": "voxel-updates/s", "ms_per_step": q["sec"] / nsteps * 1e3,
-            "plain_ms_per_step": p["sec"] / nsteps * 1e3,
-            "accepted_v_below_mV": v_hi,
-            "speedup_vs_plain": p["sec"] / q["sec"],
-            "fallback_fraction": q["fb"] / (q["nact"] * nsteps),
-            "at_within_1dt": bool(dat.size and dat.max() <= c["dt"]),
-            "at_err_vs_plain_ms": {"max": float(dat.max()) if dat.size else None,
-                                   "mean": float(dat.mean()) if dat.size else None,
-                                   "dt": c["dt"], "activated_plain": int(np.isfinite(p["at"]).sum()),
-                                   "activated_surrogate": int(np.isfinite(q["at"]).sum())},
-            "apd90_err_vs_plain_ms": {"max": float(dapd.max()) if dapd.size else None,
-                                      "mean": float(dapd.mean()) if dapd.size else None,
-                                      "n": int(bapd.sum())},
-            "training": {"pairs": tr.npairs, "iters": iters, "batch": 4096,
-                         "final_loss": float(np.mean(tr.loss[-100:])), "gen_s": round(t1 - t0, 2),
-                         "train_s": round(t2 - t1, 2)}}
+    nact = int(plain["at"].size)
+    out.update({"value": nact * nsteps / r["sec"], "ms_per_step": r["sec"] / nsteps * 1e3,
+                "plain_ms_per_step": plain["sec"] / nsteps * 1e3, "accepted_v_below_mV": v_hi,
+                "speedup_vs_plain": r["speed_vs_plain"], "surrogate_share": r["share"],
+                "at_within_1dt": bool(r["at_max"] is not None and r["at_max"] <= dt and r["same_activated"]),
+                "at_err_vs_plain_ms": {"max": r["at_max"], "mean": r["at_mean"], "dt": dt,
+                                       "same_activated_set": r["same_activated"]},
+                "apd90_err_vs_plain_ms": {"max": r["apd_max"], "mean": r["apd_mean"],
+                                          "soft_bound_ms": 2.0}})
+    return out
 
 
 def tabulated_line(stream, dv, steps, warmup):
@@ -476,12 +560,13 @@ def ensemble_line(steps=None, chunk=1000):
 
 
 # Algorithmic HBM bytes per tissue-voxel update of the fused TP06 step in FP32: 19
-# state values read + written, geometry (index, neighbour bits, fibre, face
-# coefficients: 32 B) and the recorder status byte.
-TP06_BYTES_PER_VOXEL = 19 * 4 * 2 + 32 + 1
+# state values read + written, mask bit and fibre (13 B) and the recorder status byte;
+# the library's layout: box index, neighbour bits, fibre, face coefficients (32 B).
+TP06_BYTES_PER_VOXEL = 19 * 4 * 2 + 13 + 1
+TP06_LAYOUT_BYTES_PER_VOXEL = 19 * 4 * 2 + 32 + 1
 
 
-def tp06_workload(stream):
+def tp06_workload(stream, with_s2=True):
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import workloads as WL
     c = WL.TP06_3D
@@ -491,7 +576,8 @@ def tp06_workload(stream):
     for v, val in enumerate(WL.TP06_INITIAL):
         grid.fill(v, val)
     grid.stimulus(g3["s1"], c["s1_amp"], 0.0, c["s1_ms"])
-    grid.stimulus(g3["s2"], c["s2_amp"], c["s2_t"], c["s2_ms"])
+    if with_s2:
+        grid.stimulus(g3["s2"], c["s2_amp"], c["s2_t"], c["s2_ms"])
     grid.record(c["theta"])
     grid.nan_check(0)
     return grid, g3["electrodes"], c
@@ -519,10 +605,107 @@ def tp06_line(stream, steps=1000, warmup=100):
             "value": nact * steps / sec, "unit": "voxel-updates/s", "ms_per_step": per * 1e3,
             "steps": steps, "one_second_protocol_s_est": per * round(c["t_end"] / c["dt"]),
             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": TP06_BYTES_PER_VOXEL},
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": TP06_BYTES_PER_VOXEL,
+                         "layout_bytes_per_voxel": TP06_LAYOUT_BYTES_PER_VOXEL},
+            "error_vs_fp64": "not measured here (FP32 vs the FP64 oracle on the down-scaled shell "
+                             "protocol and on crops at full size: tests)",
             "pseudo_ecg": {"electrodes": int(len(E)), "every_steps": every, "samples": nsamp,
                            "ms_per_sample": (sec_ecg - sec) / max(nsamp, 1) * 1e3,
                            "overhead_frac": (sec_ecg - sec) / sec}}
+
+
+def slab_line(stream, nslab=8, steps=100):
+    """The one-GPU part of a z-sharded run: the TP06 double shell split into nslab
+    tissue-balanced z-slabs, each a grid of its own (the sub-domain one GPU would own, at
+    its real shape), timed alone; and the halo pack / unpack kernels of one exchange."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.TP06_3D
+    g3 = shell_geometry()
+    zb = B.bbx_slab_bounds(g3["mask"], nslab)
+    rows = []
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for k in range(nslab):
+        z0, z1 = int(zb[k]), int(zb[k + 1])
+        g = B.Grid.slab(g3["mask"], z0, z1, c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32,
+                        stream)
+        g.model(B.BBX_MODEL_TP06, [], c["dt"])
+        for v, val in enumerate(WL.TP06_INITIAL):
+            g.fill(v, val)
+        g.nan_check(0)
+        g.step(10)
+        per, _ = differenced(g, stream, 20, 20 + steps, 3)
+        slo, shi, rlo, rhi = g.halo_counts()
+        buf = torch.empty(max(slo, shi, rlo, rhi, 1), dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for _ in range(10):
+            g.pack(0, buf, slo)
+            g.pack(1, buf, shi)
+            g.unpack(0, buf, rlo)
+            g.unpack(1, buf, rhi)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        rows.append({"planes": [z0, z1], "tissue_voxels": g.nact, "box": list(g.shape),
+                     "ms_per_step": per * 1e3, "halo_values": [slo, shi, rlo, rhi],
+                     "halo_us_per_exchange": ev[0].elapsed_time(ev[1]) * 1e3 / 10})
+        g.close()
+    t = [r["ms_per_step"] for r in rows]
+    n = [r["tissue_voxels"] for r in rows]
+    return {"workload": f"TP06 512x512x384 double shell split into {nslab} tissue-balanced z-slabs, "
+                        "FP32, each slab stepped alone (one halo plane per side)",
+            "slabs": rows, "max_ms_per_step": max(t), "mean_ms_per_step": float(np.mean(t)),
+            "tissue_imbalance": max(n) / float(np.mean(n)),
+            "halo_bytes_per_step_per_side_max": 4 * max(max(r["halo_values"]) for r in rows)}
+
+
+def protocol_run(stream, out_path):
+    """The full 1 s of the TP06 workload (50,000 steps: S1 y-strip at 0 ms, S2 upper half at
+    360 ms) with the FP64 pseudo-ECG every 1 ms at eight electrodes and the share of tissue
+    above -40 mV every 5 ms, against S1 alone (no S2): sustained activity after the S1 wave
+    has died is the scroll wave's signature.  Writes a JSON summary to out_path."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.TP06_3D
+    g3 = shell_geometry()
+    mt = torch.from_numpy(g3["mask"]).cuda().bool()
+    buf = torch.empty(g3["mask"].shape, dtype=torch.float64, device="cuda")
+    res = {}
+    for name in ("s1_only", "s1_s2"):
+        grid, E, _ = tp06_workload(stream, with_s2=(name == "s1_s2"))
+        nact = grid.nact
+        every = int(round(c["ecg_every_ms"] / c["dt"]))
+        grid.ecg(E, every=every, max_samples=2000)
+        act, sec = [], 0.0
+        chunk = int(round(5.0 / c["dt"]))
+        for k in range(int(round(c["t_end"] / c["dt"])) // chunk):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            grid.step(chunk)
+            e1.record(stream)
+            B.bbx_readout(grid.handle, B.BBX_READ_VAR, 0, None, buf.data_ptr(), buf.numel() * 8, 1)
+            act.append(((buf > -40.0) & mt).sum().item() / nact)
+            sec += e0.elapsed_time(e1) / 1e3
+            if k % 20 == 19:
+                print(f"protocol {name}: t = {(k + 1) * 5} ms, active {act[-1]:.3f}", file=sys.stderr,
+                      flush=True)
+        ecg = grid.ecg_series()
+        if grid.read(B.BBX_READ_NAN_FLAG)[0]:
+            raise RuntimeError("non-finite state in the protocol run")
+        grid.close()
+        res[name] = {"active_every_5ms": [round(a, 4) for a in act], "gpu_s": sec,
+                     "ecg_every_1ms": ecg.tolist()}
+    late = lambda a: a[int(600 / 5):]
+    summary = {"workload": "TP06 512x512x384 double shell, 1 s, FP32, S1 y-strip 0 ms, S2 upper half "
+                           f"{c['s2_t']} ms", "s2_t_ms": c["s2_t"],
+               "s1_only_active_max_after_600ms": max(late(res["s1_only"]["active_every_5ms"])),
+               "s1_s2_active_min_after_600ms": min(late(res["s1_s2"]["active_every_5ms"])),
+               "s1_s2_gpu_s": res["s1_s2"]["gpu_s"], "runs": res}
+    with open(out_path, "w") as f:
+        json.dump(summary, f)
+    return {k: v for k, v in summary.items() if k != "runs"}
 
 
 def main():
@@ -540,6 +723,9 @@ def main():
     ap.add_argument("--ens-steps", type=int, default=0,
                     help="steps of the ensemble line (0: the full 20,000-step protocol)")
     ap.add_argument("--tp06-steps", type=int, default=1000, help="timed steps of the TP06 line")
+    ap.add_argument("--protocol", default=None, metavar="OUT.json",
+                    help="run the full 1 s TP06 scroll-wave protocol (and S1 alone) and write "
+                         "its summary to OUT.json, instead of the benchmark")
     ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "ensemble", "tp06"], default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
@@ -553,6 +739,10 @@ def main():
     from paper_1605_06015_amd import bbx as B
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+
+    if args.protocol:
+        print(json.dumps(protocol_run(stream, args.protocol)))
+        return
 
     if args.profile:
         if args.profile == "tp06":
@@ -591,17 +781,30 @@ def main():
         sys.exit(1)
     ms_per_step = sec / args.steps * 1e3
     value = nact * args.steps / sec
-    per_launch = sec / args.steps
-    achieved = CRN_BYTES_PER_VOXEL * nact / per_launch / 1e9
+    # the kernel's own per-step time: two-run differencing removes the fixed start and end
+    # cost of the K-step region (at K = 20 about a tenth of it)
+    per_launch, reps = differenced(grid, stream)
     ctr = measured_counters("step_crn_cup128_fp32_traffic.json")
     traffic = ctr.get("bytes_per_launch") if ctr else None
-    valu = None
+    gbs = CRN_BYTES_PER_VOXEL * nact / per_launch / 1e9
+    hbm = {"achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": CRN_BYTES_PER_VOXEL,
+           "layout_bytes_per_voxel": CRN_LAYOUT_BYTES_PER_VOXEL,
+           "note": "the step's 77 MB (layout) working set stays in the 256 MB Infinity Cache"}
     if ctr and ctr.get("valu_insts_per_launch"):
-        # VALU issue: one wave64 instruction per CU per cycle, 256 CUs at 2.4 GHz
+        # the binding resource: VALU issue (one wave64 instruction per CU per cycle, 256
+        # CUs at 2.4 GHz) and latency; the VALU instructions per launch come from the
+        # committed counters of this same kernel source
         gi = ctr["valu_insts_per_launch"] / per_launch / 1e9
-        valu = {"achieved": round(gi, 1), "peak": VALU_PEAK_GINST, "unit": "G wave-instructions/s",
-                "frac": round(gi / VALU_PEAK_GINST, 4),
-                "insts_per_launch": ctr["valu_insts_per_launch"]}
+        roof = {"bound": "alu", "achieved": round(gi, 1), "peak": VALU_PEAK_GINST,
+                "unit": "G wave-instructions/s", "frac": round(gi / VALU_PEAK_GINST, 4),
+                "traffic": traffic, "insts_per_launch": ctr["valu_insts_per_launch"]}
+    else:
+        roof = {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": hbm["frac"], "traffic": traffic,
+                "note": "VALU counters not taken on the current kernel source"}
+    roof.update({"kernel": "k_step<float, Crn, aniso>", "us_per_launch": round(per_launch * 1e6, 3),
+                 "timing": "differenced 1000 - 100 steps, median of 5", "hbm": hbm})
     out = {
         "metric": METRIC, "value": value, "unit": "voxel-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
@@ -611,15 +814,14 @@ def main():
                                f"({nact} tissue voxels), 19-point anisotropic no-flux stencil, "
                                "rotating fibres, dt 0.01 ms, apex stimulus, AT/APD90 recording, "
                                "FP32 plain ionic", "tissue_voxels": nact, "dt_ms": 0.01},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": "k_step<float, Crn, aniso>",
-                     "bytes_per_voxel": CRN_BYTES_PER_VOXEL,
-                     "us_per_launch": round(per_launch * 1e6, 2), "valu": valu},
+        "roofline": roof,
+        "differenced": {"value": nact / per_launch, "ms_per_step": per_launch * 1e3,
+                        "reps_ms_per_step": [r * 1e3 for r in reps]},
     }
     grid.close()
     out["accuracy"] = headline_accuracy(stream)
     if not args.no_extras:
+        out["fp64"] = fp64_line(stream)
         if args.tab > 0:
             out["tabulated"] = tabulated_line(stream, args.tab, args.steps, args.warmup)
             out["tabulated"]["speedup_vs_plain"] = round(ms_per_step / out["tabulated"]["ms_per_step"], 3)
@@ -630,10 +832,9 @@ def main():
         out["barkley_2d"] = barkley_line(stream)
         out["ensemble"] = ensemble_line(steps=args.ens_steps or None)
         out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
-        # acceptance thresholds at which the surrogate run's activation times stay within
-        # one time step of the plain run's (found by sweeping the threshold on this workload)
-        out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms, v_hi=-81.17)
-        out["surrogate_tp06"] = surrogate_line(stream, "tp06", t_ms=args.sur_ms, v_hi=-85.225)
+        out["slabs"] = slab_line(stream)
+        out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms)
+        out["surrogate_tp06"] = surrogate_line(stream, "tp06", t_ms=args.sur_ms)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

@@ -118,8 +118,10 @@ enum {
     BBX_READ_ECG_COUNT = 13       /* int64[1]: samples stored so far */
 };
 
-/* Info queries for bbx_info. */
-enum { BBX_INFO_NACTIVE = 0, BBX_INFO_NVAR = 1, BBX_INFO_NBOX = 2, BBX_INFO_DEVICE_BYTES = 3 };
+/* Info queries for bbx_info.  SEND_* / RECV_*: values a slab grid (bbx_slab_create)
+ * packs from its first / last own plane and unpacks into its lower / upper halo plane. */
+enum { BBX_INFO_NACTIVE = 0, BBX_INFO_NVAR = 1, BBX_INFO_NBOX = 2, BBX_INFO_DEVICE_BYTES = 3,
+       BBX_INFO_SEND_LO = 4, BBX_INFO_SEND_HI = 5, BBX_INFO_RECV_LO = 6, BBX_INFO_RECV_HI = 7 };
 
 /*
  * Create a grid (the paper's `state` sentence with a geometry; "Format of
@@ -139,6 +141,56 @@ enum { BBX_INFO_NACTIVE = 0, BBX_INFO_NVAR = 1, BBX_INFO_NBOX = 2, BBX_INFO_DEVI
 int bbx_grid_create(int nx, int ny, int nz, double h, const uint8_t *mask, const double *fibre,
                     double D_par, double D_perp, int precision, void *hip_stream,
                     bbx_grid **out);
+
+/* ------------------------------------------------------------------------
+ * z-slab sub-domains ("Complex geometries and domain partitioning": the paper
+ * splits the box into subdomains, one per process, that exchange boundary
+ * layers of the diffusing variable every step).  Here a box is split along z
+ * only: the only state a step reads from a neighbouring slab is V of the
+ * adjacent plane (the 19-point stencil reaches one plane up and down, faces and
+ * edges; every other variable is point-local), so one plane per side and step
+ * is the whole exchange, and the paper's corner ordering for multi-axis splits
+ * is not needed.  A slab grid is an ordinary grid (every other call works on
+ * it) whose box is the slab's own planes plus one halo plane on each side.
+ * ---------------------------------------------------------------------- */
+
+/* Tissue-balanced split of the nz planes of a box into nslab (1..nz) slabs of
+ * consecutive planes: z_bounds[nslab + 1] receives 0 = z_0 < z_1 < ... < z_nslab
+ * = nz, each boundary the plane boundary nearest to where the tissue below it
+ * reaches k/nslab of the total (every slab keeps at least one plane).  Host only;
+ * mask as in bbx_grid_create.  Errors: BBX_EINVAL. */
+int bbx_slab_bounds(int nx, int ny, int nz, const uint8_t *mask, int nslab, int *z_bounds);
+
+/* Create the grid of the slab of global planes [z0, z1) of an nx*ny*nz box
+ * (0 <= z0 < z1 <= nz): mask and fibre are the whole box's arrays (read, not
+ * kept).  The slab grid's box has nz_s = z1 - z0 + 2 planes: plane 0 is global
+ * plane z0 - 1, plane nz_s - 1 is global plane z1 (void where they lie outside
+ * the global box); its own, stepped, voxels are the tissue of planes 1..nz_s-2,
+ * and tissue in the two halo planes takes part in the stencil (geometry
+ * included) exactly as in the whole box, so a step of every slab, with halo
+ * planes holding the neighbours' V_n, gives bit for bit the whole box's step.
+ * Every other entry point then works on the slab's box (host arrays have
+ * nx*ny*nz_s entries; halo entries are never read as state, and read back as
+ * NaN); pseudo-ECG electrode positions stay global (the slab's plane 0 lies at
+ * z = (z0 - 1) h), so the slabs' ECGs sum to the whole box's.  Errors as
+ * bbx_grid_create, plus BBX_EINVAL for a bad plane range. */
+int bbx_slab_create(int nx, int ny, int nz, int z0, int z1, double h, const uint8_t *mask,
+                    const double *fibre, double D_par, double D_perp, int precision,
+                    void *hip_stream, bbx_grid **out);
+
+/* Halo exchange of a slab grid, on its stream.  Pack copies the current V of the
+ * tissue voxels of the first (side 0) or last (side 1) own plane, in increasing x
+ * (fastest) and y order, into buf_dev (device, count values of the grid's
+ * precision, count = bbx_info SEND_LO / SEND_HI).  Unpack writes count = RECV_LO
+ * / RECV_HI values from buf_dev into the tissue voxels of the lower (side 0) or
+ * upper (side 1) halo plane, same order.  Slab k's side-1 pack is slab k+1's
+ * side-0 unpack and vice versa (the counts agree: both are the tissue of one
+ * global plane).  Between two steps, every slab unpacks what its neighbours
+ * packed after the previous step; a readout that applies the stencil (the
+ * pseudo-ECG) needs the same exchange after the last step.  Errors: BBX_EINVAL
+ * (side, count, NULL buffer), BBX_ESTATE (not a slab grid). */
+int bbx_halo_pack(bbx_grid *g, int side, void *buf_dev, int64_t count);
+int bbx_halo_unpack(bbx_grid *g, int side, const void *buf_dev, int64_t count);
 
 /* Choose the cell model, its parameters (nparams must equal the model's count,
  * params may be NULL when it is 0), the time step dt > 0 and the scheme.
@@ -210,6 +262,22 @@ int bbx_ecg_set(bbx_grid *g, int nelec, const double *xyz_mm, int64_t every, int
  * rebuilt by bbx_model_set.  dv = 0 returns to direct evaluation.  Other
  * models or FP64 grids: BBX_ENOTSUP. */
 int bbx_tabulation_set(bbx_grid *g, double dv);
+
+/* Integrator of the kinetics ("Kinetics solvers"): EULER_RL (the default) advances
+ * concentrations and recovery variables by forward Euler (eq (Euler)) and gates by
+ * Rush-Larsen (eqs (RL), (RLcoeff)); RK4 is the classical fourth-order Runge-Kutta
+ * scheme (the paper's `rk4` solver for cases where accuracy matters) applied to every
+ * state variable of a voxel, gates included (dg/dt = (g_inf - g)/tau), with the
+ * stimulus current -- and in the additive scheme the diffusion term L V -- held at its
+ * step-n value through the four stages; in the split scheme it starts from V* = V +
+ * dt L V.  RK4 costs four evaluations of the kinetics per step and uses the tissue-list
+ * kernel with cached accesses on every grid; tabulated CRN terms are ignored under RK4.
+ * Like every explicit scheme it is only conditionally stable: a gate with time constant
+ * tau needs dt below about 2.8 tau (TP06's sodium activation, tau ~1e-3 ms near rest,
+ * diverges at dt = 0.005 ms), where Rush-Larsen is stable at any dt.  Kept until changed.  Errors: BBX_EINVAL (unknown integrator), BBX_ENOTSUP (RK4 with
+ * a surrogate attached). */
+enum { BBX_INTEGRATOR_EULER_RL = 0, BBX_INTEGRATOR_RK4 = 1 };
+int bbx_integrator_set(bbx_grid *g, int integrator);
 
 /* Set the step counter (t = step * dt), e.g. when resuming from a checkpoint
  * read with BBX_READ_VAR / BBX_READ_STEP; step >= 0. */
@@ -313,6 +381,27 @@ int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev);
  * network's weights are copied; it may be destroyed after. */
 int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi,
                       float dv_max);
+
+/* Phase singularities in z cross-sections (the `singz` device of "Input/output and
+ * visualization": intersections of isolines of two fields, the isolines' pieces in
+ * each grid cell from linear interpolation).  Fields: state variables var_u and var_v
+ * of the grid (0 = V), levels u_level and v_level.  A cell is the square of four
+ * tissue voxels (x..x+1, y..y+1) of one z plane; a corner is above a level when its
+ * value is >= the level; an isoline crosses a cell edge whose corners differ, at the
+ * linearly interpolated point; two crossed edges give one piece, four (a saddle) give
+ * two, which separate the corner pair whose class differs from that of the four
+ * corners' mean; each crossing of a u piece with a v piece is a point.
+ *   stats [7] (host): count, mean x, y, z, standard deviation (population) of x, y,
+ *         z, coordinates in mm (x_p = h (x, y, z)), from FP64 sums in a fixed order
+ *         (deterministic);
+ *   points (host, may be NULL): the first min(count, max_points) points, [k][3] mm,
+ *         in an order that varies from run to run (sort to compare);
+ *   npoints (may be NULL): the number of points found.
+ * Synchronises the stream; allocates temporaries (and, on a sparse grid's first
+ * call, a 4-byte-per-voxel box-to-tissue map kept with the grid).  Errors:
+ * BBX_EINVAL (variables, levels, max_points), BBX_ESTATE (no model). */
+int bbx_tips(bbx_grid *g, int var_u, double u_level, int var_v, double v_level, double *stats,
+             double *points, int64_t max_points, int64_t *npoints);
 
 /* Integer facts about a grid (BBX_INFO_*). */
 int bbx_info(const bbx_grid *g, int what, int64_t *out);

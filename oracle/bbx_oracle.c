@@ -43,6 +43,7 @@
 
 enum { M_NONE = 0, M_BARKLEY = 1, M_ZFK = 2, M_FHN = 3, M_CRN = 4, M_FK4 = 5, M_TP06 = 6 };
 enum { S_ADDITIVE = 0, S_SPLIT = 1 };
+enum { I_EULER_RL = 0, I_RK4 = 1 };
 
 #define NVAR_MAX 32
 
@@ -587,6 +588,39 @@ int orc_model_eval(int model, const double *p, const double *y,
 /* (external current term of eq (monodomain); reading G4: positive A         */
 /* depolarises; reading G12: windows in whole steps).                        */
 /* ------------------------------------------------------------------------- */
+/* Right-hand side of one voxel's kinetics at state y, with the forcing F (stimulus,
+ * plus L V in the additive scheme) added to dV/dt: out[0] = -I_ion + F; gates
+ * out[i] = (inf_i - y_i) / tau_i (eq (gate) written with y_inf and tau); the other
+ * variables out[i] = their rate. */
+static void kinetic_rhs(int model, const double *p, const double *y, double F, double *out)
+{
+    double rate[NVAR_MAX], inf[NVAR_MAX], tau[NVAR_MAX];
+    int nv = orc_nvar(model);
+    for (int i = 0; i < nv; i++) { rate[i] = 0.0; inf[i] = 0.0; tau[i] = 1.0; }
+    model_eval(model, p, y, rate, inf, tau);
+    out[0] = rate[0] + F;
+    for (int i = 1; i < nv; i++)
+        out[i] = is_gate(model, i) ? (inf[i] - y[i]) / tau[i] : rate[i];
+}
+
+/* One step of the classical fourth-order Runge-Kutta scheme ("Kinetics solvers",
+ * the `rk4` solver) for one voxel: y is the state at the step's start (y[0] = V, or V*
+ * in the split scheme) and is replaced by the state one step later; F is held
+ * constant through the four stages. */
+static void rk4_voxel(int model, const double *p, double *y, double F, double dt)
+{
+    int nv = orc_nvar(model);
+    double k1[NVAR_MAX], k2[NVAR_MAX], k3[NVAR_MAX], k4[NVAR_MAX], t[NVAR_MAX];
+    kinetic_rhs(model, p, y, F, k1);
+    for (int i = 0; i < nv; i++) t[i] = y[i] + 0.5 * dt * k1[i];
+    kinetic_rhs(model, p, t, F, k2);
+    for (int i = 0; i < nv; i++) t[i] = y[i] + 0.5 * dt * k2[i];
+    kinetic_rhs(model, p, t, F, k3);
+    for (int i = 0; i < nv; i++) t[i] = y[i] + dt * k3[i];
+    kinetic_rhs(model, p, t, F, k4);
+    for (int i = 0; i < nv; i++) y[i] += dt / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
 static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t count)
 {
     if (n < n0 || len <= 0) return 0;
@@ -607,7 +641,9 @@ static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t c
  *  additive scheme: V+ = V + dt(-I_ion(V,g) + I_stim + LV), kinetics at (V, g);
  *  split scheme:    V* = V + dt LV, then V+ = V* + dt(-I_ion(V*,g) + I_stim),
  *                   kinetics at (V*, g).
- * Non-gates use forward Euler; gates y+ = yinf + (y - yinf) exp(-dt/tau).
+ * Non-gates use forward Euler; gates y+ = yinf + (y - yinf) exp(-dt/tau).  With
+ * integrator = I_RK4 every variable instead takes one classical RK4 step of its ODE,
+ * with I_stim (additive: and LV) held constant through the stages.
  * If record != 0, activation time, peak and APD90 are detected from the pair
  * (V_n, V_{n+1}) per voxel (reading G23): status 0 -> 1 on the first upward
  * crossing of theta (AT linearly interpolated), 1 -> 2 at the first decrease
@@ -615,7 +651,7 @@ static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t c
  * vrest + 0.1 (vmax - vrest) (APD90 = interpolated time - AT).
  */
 int orc_run(int nx, int ny, int nz, int64_t nact, const int64_t *act, const double *W,
-            int model, const double *params, double dt, int scheme,
+            int model, const double *params, double dt, int scheme, int integrator,
             int nstim, const uint8_t *stim_region, const double *stim_amp,
             const int64_t *stim_n0, const int64_t *stim_len, const int64_t *stim_period,
             const int64_t *stim_count,
@@ -651,16 +687,23 @@ int orc_run(int nx, int ny, int nz, int64_t nact, const int64_t *act, const doub
             for (int i = 0; i < nv; i++) y[i] = state[(int64_t)i * nbox + p];
             double Vold = y[0];
             if (scheme == S_SPLIT) y[0] = Vold + dt * LV;
-            model_eval(model, params, y, rate, inf, tau);
-            double Vnew = (scheme == S_SPLIT) ? y[0] + dt * (rate[0] + Is)
-                                              : Vold + dt * (rate[0] + Is + LV);
-            for (int i = 1; i < nv; i++) {
-                double yi = y[i];
-                if (is_gate(model, i))
-                    yi = inf[i] + (yi - inf[i]) * exp(-dt / tau[i]);
-                else
-                    yi = yi + dt * rate[i];
-                state[(int64_t)i * nbox + p] = yi;
+            double Vnew;
+            if (integrator == I_RK4) {
+                rk4_voxel(model, params, y, scheme == S_SPLIT ? Is : Is + LV, dt);
+                Vnew = y[0];
+                for (int i = 1; i < nv; i++) state[(int64_t)i * nbox + p] = y[i];
+            } else {
+                model_eval(model, params, y, rate, inf, tau);
+                Vnew = (scheme == S_SPLIT) ? y[0] + dt * (rate[0] + Is)
+                                           : Vold + dt * (rate[0] + Is + LV);
+                for (int i = 1; i < nv; i++) {
+                    double yi = y[i];
+                    if (is_gate(model, i))
+                        yi = inf[i] + (yi - inf[i]) * exp(-dt / tau[i]);
+                    else
+                        yi = yi + dt * rate[i];
+                    state[(int64_t)i * nbox + p] = yi;
+                }
             }
             vnext[p] = Vnew;
 
@@ -687,4 +730,118 @@ int orc_run(int nx, int ny, int nz, int64_t nact, const int64_t *act, const doub
         for (int64_t a = 0; a < nact; a++) V[act[a]] = vnext[act[a]];
     }
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Phase singularities in z cross-sections (the `singz` device of "Input/output */
+/* and visualization"): points where an isoline of field u (u = u_level) and  */
+/* an isoline of field v (v = v_level) intersect inside a grid cell, the      */
+/* isolines' pieces in each cell obtained by linear interpolation along its   */
+/* edges.  Reading of the details the paper leaves open:                      */
+/*  - a cell is the square of four tissue voxels (x..x+1, y..y+1) of one plane;*/
+/*  - a corner counts as "above" when its value is >= the level; an edge is   */
+/*    crossed where its two corners differ, at the linearly interpolated      */
+/*    point; 2 crossed edges give one segment; 4 (a saddle) give two segments,*/
+/*    which separate the corner pair whose class differs from that of the     */
+/*    average of the four corner values;                                     */
+/*  - every intersection of a u segment with a v segment (both parameters in  */
+/*    [0, 1]) is a point; statistics are the count and the mean and standard  */
+/*    deviation (population) of the points' coordinates (mm, x_p = h (x,y,z)).*/
+/* ------------------------------------------------------------------------- */
+
+/* Isoline segments of the cell with corner values c[4] = (00, 10, 01, 11) (x, y)
+ * relative to the level; seg[k] = {x1, y1, x2, y2} in cell coordinates [0,1]^2.
+ * Returns the number of segments (0, 1 or 2). */
+static int cell_segments(const double c[4], double seg[2][4])
+{
+    /* edges: bottom 00-10, right 10-11, top 01-11, left 00-01 */
+    static const int ea[4] = {0, 1, 2, 0}, eb[4] = {1, 3, 3, 2};
+    static const double ox[4] = {0, 1, 0, 0}, oy[4] = {0, 0, 1, 0};   /* edge start */
+    static const double dx[4] = {1, 0, 1, 0}, dy[4] = {0, 1, 0, 1};   /* edge direction */
+    double px[4], py[4];
+    int cut[4], ncut = 0;
+    for (int e = 0; e < 4; e++) {
+        double a = c[ea[e]], b = c[eb[e]];
+        cut[e] = (a >= 0.0) != (b >= 0.0);
+        if (cut[e]) {
+            double t = a / (a - b);
+            px[e] = ox[e] + t * dx[e];
+            py[e] = oy[e] + t * dy[e];
+            ncut++;
+        }
+    }
+    if (ncut == 2) {
+        int k = 0, q[2];
+        for (int e = 0; e < 4; e++) if (cut[e]) q[k++] = e;
+        seg[0][0] = px[q[0]]; seg[0][1] = py[q[0]]; seg[0][2] = px[q[1]]; seg[0][3] = py[q[1]];
+        return 1;
+    }
+    if (ncut == 4) {
+        double centre = 0.25 * (c[0] + c[1] + c[2] + c[3]);
+        int pair[2][2];
+        if ((centre >= 0.0) == (c[0] >= 0.0)) {
+            /* 00 and 11 joined through the centre: cut off corners 10 and 01 */
+            pair[0][0] = 0; pair[0][1] = 1;    /* bottom, right: around 10 */
+            pair[1][0] = 2; pair[1][1] = 3;    /* top, left: around 01 */
+        } else {
+            pair[0][0] = 0; pair[0][1] = 3;    /* bottom, left: around 00 */
+            pair[1][0] = 1; pair[1][1] = 2;    /* right, top: around 11 */
+        }
+        for (int k = 0; k < 2; k++) {
+            seg[k][0] = px[pair[k][0]]; seg[k][1] = py[pair[k][0]];
+            seg[k][2] = px[pair[k][1]]; seg[k][3] = py[pair[k][1]];
+        }
+        return 2;
+    }
+    return 0;
+}
+
+/* Intersection of segments p and q; returns 1 and the point if they cross. */
+static int seg_cross(const double p[4], const double q[4], double *x, double *y)
+{
+    double rx = p[2] - p[0], ry = p[3] - p[1], sx = q[2] - q[0], sy = q[3] - q[1];
+    double den = rx * sy - ry * sx;
+    if (den == 0.0) return 0;
+    double wx = q[0] - p[0], wy = q[1] - p[1];
+    double s = (wx * sy - wy * sx) / den, t = (wx * ry - wy * rx) / den;
+    if (s < 0.0 || s > 1.0 || t < 0.0 || t > 1.0) return 0;
+    *x = p[0] + s * rx;
+    *y = p[1] + s * ry;
+    return 1;
+}
+
+/* u, v: fields in box layout; mask: tissue.  sums[7] = count, sum x, y, z, sum x^2,
+ * y^2, z^2 (mm).  Points (x, y, z in mm) are written to pts[3*k] for k < max_pts.
+ * Returns the number of points. */
+int64_t orc_tips(int nx, int ny, int nz, double h, const uint8_t *mask, const double *u,
+                 double ul, const double *v, double vl, double *sums, double *pts,
+                 int64_t max_pts)
+{
+    int64_t n = 0;
+    for (int i = 0; i < 7; i++) sums[i] = 0.0;
+    for (int z = 0; z < nz; z++)
+        for (int y = 0; y + 1 < ny; y++)
+            for (int x = 0; x + 1 < nx; x++) {
+                int64_t b[4];
+                b[0] = (int64_t)x + (int64_t)nx * ((int64_t)y + (int64_t)ny * z);
+                b[1] = b[0] + 1;
+                b[2] = b[0] + nx;
+                b[3] = b[2] + 1;
+                if (!mask[b[0]] || !mask[b[1]] || !mask[b[2]] || !mask[b[3]]) continue;
+                double cu[4], cv[4], su[2][4], sv[2][4];
+                for (int k = 0; k < 4; k++) { cu[k] = u[b[k]] - ul; cv[k] = v[b[k]] - vl; }
+                int nu = cell_segments(cu, su), nv = cell_segments(cv, sv);
+                for (int i = 0; i < nu; i++)
+                    for (int j = 0; j < nv; j++) {
+                        double px, py;
+                        if (!seg_cross(su[i], sv[j], &px, &py)) continue;
+                        double X = h * (x + px), Y = h * (y + py), Z = h * z;
+                        sums[0] += 1.0;
+                        sums[1] += X; sums[2] += Y; sums[3] += Z;
+                        sums[4] += X * X; sums[5] += Y * Y; sums[6] += Z * Z;
+                        if (n < max_pts && pts) { pts[3 * n] = X; pts[3 * n + 1] = Y; pts[3 * n + 2] = Z; }
+                        n++;
+                    }
+            }
+    return n;
 }

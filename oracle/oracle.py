@@ -24,6 +24,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 MODEL_NONE, MODEL_BARKLEY, MODEL_ZFK, MODEL_FHN, MODEL_CRN, MODEL_FK4, MODEL_TP06 = \
     0, 1, 2, 3, 4, 5, 6
 SCHEME_ADDITIVE, SCHEME_SPLIT = 0, 1
+INTEGRATOR_EULER_RL, INTEGRATOR_RK4 = 0, 1
 
 
 def build(force: bool = False) -> str:
@@ -58,11 +59,14 @@ def lib():
         L.orc_model_eval.argtypes = [C.c_int, P, P, P, P, P]
         L.orc_model_eval.restype = C.c_int
         L.orc_run.argtypes = [C.c_int, C.c_int, C.c_int, i64, P, P,
-                              C.c_int, P, C.c_double, C.c_int,
+                              C.c_int, P, C.c_double, C.c_int, C.c_int,
                               C.c_int, P, P, P, P, P, P,
                               P, P, i64, i64,
                               C.c_int, C.c_double, P, P, P, P, P, C.c_int]
         L.orc_run.restype = C.c_int
+        L.orc_tips.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, P, P, C.c_double, P,
+                               C.c_double, P, P, i64]
+        L.orc_tips.restype = i64
         _lib = L
     return _lib
 
@@ -149,6 +153,28 @@ def pseudo_ecg(mask: np.ndarray, h: float, fibre, Dpar: float, Dperp: float, V: 
     return out * h ** 3
 
 
+def tips(mask, h, u, u_level, v, v_level, max_points=100000):
+    """Phase singularities in z cross-sections: intersections of the isolines
+    u = u_level and v = v_level inside cells of four tissue voxels (the `singz` device).
+    Returns (stats, points): stats = [count, mean x, mean y, mean z, std x, std y, std z]
+    (mm, population standard deviation), points (n, 3) in mm in cell order."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    nz, ny, nx = mask.shape
+    uu = np.ascontiguousarray(u, dtype=np.float64)
+    vv = np.ascontiguousarray(v, dtype=np.float64)
+    sums = np.zeros(7)
+    pts = np.zeros((max_points, 3))
+    n = lib().orc_tips(nx, ny, nz, float(h), _p(mask), _p(uu), float(u_level), _p(vv),
+                       float(v_level), _p(sums), _p(pts), int(max_points))
+    stats = np.zeros(7)
+    stats[0] = sums[0]
+    if n > 0:
+        mean = sums[1:4] / n
+        stats[1:4] = mean
+        stats[4:7] = np.sqrt(np.maximum(sums[4:7] / n - mean * mean, 0.0))
+    return stats, pts[:min(n, max_points)].copy()
+
+
 def model_eval(model: int, params, y):
     """Kinetic rates of one cell: (rate, inf, tau), each of length nvar."""
     nv = nvar(model)
@@ -196,6 +222,7 @@ class Sim:
     scheme: int = SCHEME_ADDITIVE
     stimuli: list = field(default_factory=list)
     nthreads: int = 0
+    integrator: int = INTEGRATOR_EULER_RL
 
     def __post_init__(self):
         self.mask = np.ascontiguousarray(self.mask, dtype=np.uint8)
@@ -232,6 +259,7 @@ class Sim:
         r = self.rec
         rc = lib().orc_run(nx, ny, nz, self.act.size, _p(self.act), _p(self.W),
                            self.model, _p(p), float(self.dt), int(self.scheme),
+                           int(self.integrator),
                            ns, _p(reg), _p(amp), _p(sn0), _p(sl), _p(sp), _p(sc),
                            _p(self.state), _p(self.vnext), int(self.n), int(nsteps),
                            1 if r is not None else 0, r.theta if r else 0.0,

@@ -21,13 +21,15 @@ BBX_OK, BBX_EINVAL, BBX_ENOMEM, BBX_EDEVICE, BBX_ESTATE, BBX_EUNSTABLE, BBX_ENUM
     0, -1, -2, -3, -4, -5, -6, -7
 BBX_FP32, BBX_FP64 = 0, 1
 BBX_SCHEME_ADDITIVE, BBX_SCHEME_SPLIT = 0, 1
+BBX_INTEGRATOR_EULER_RL, BBX_INTEGRATOR_RK4 = 0, 1
 BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, BBX_MODEL_FK4, \
     BBX_MODEL_TP06 = 0, 1, 2, 3, 4, 5, 6
 (BBX_READ_VAR, BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX, BBX_READ_STATUS,
  BBX_READ_REDUCE_MAX, BBX_READ_REDUCE_SUM, BBX_READ_NAN_FLAG, BBX_READ_STEP,
  BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT, BBX_READ_ECG, BBX_READ_ECG_SERIES,
  BBX_READ_ECG_COUNT) = range(14)
-BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
+(BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES, BBX_INFO_SEND_LO,
+ BBX_INFO_SEND_HI, BBX_INFO_RECV_LO, BBX_INFO_RECV_HI) = range(8)
 (BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_MARCH_64x32,
  BBX_ENS_MARCH_64x128, BBX_ENS_NVARIANT) = range(7)
 (BBX_ENS_INFO_VOXELS, BBX_ENS_INFO_TILES, BBX_ENS_INFO_VARIANT, BBX_ENS_INFO_DEVICE_BYTES,
@@ -37,6 +39,10 @@ BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES = range(4)
 _P, _I, _D, _I64, _SZ = C.c_void_p, C.c_int, C.c_double, C.c_int64, C.c_size_t
 SIGNATURES = {
     "bbx_grid_create": (_I, [_I, _I, _I, _D, _P, _P, _D, _D, _I, _P, C.POINTER(_P)]),
+    "bbx_slab_bounds": (_I, [_I, _I, _I, _P, _I, _P]),
+    "bbx_slab_create": (_I, [_I, _I, _I, _I, _I, _D, _P, _P, _D, _D, _I, _P, C.POINTER(_P)]),
+    "bbx_halo_pack": (_I, [_P, _I, _P, _I64]),
+    "bbx_halo_unpack": (_I, [_P, _I, _P, _I64]),
     "bbx_model_set": (_I, [_P, _I, _P, _I, _D, _I]),
     "bbx_state_set": (_I, [_P, _I, _P]),
     "bbx_state_fill": (_I, [_P, _I, _D]),
@@ -45,11 +51,13 @@ SIGNATURES = {
     "bbx_recording_set": (_I, [_P, _D]),
     "bbx_nan_check_set": (_I, [_P, _I64]),
     "bbx_clock_set": (_I, [_P, _I64]),
+    "bbx_integrator_set": (_I, [_P, _I]),
     "bbx_tabulation_set": (_I, [_P, _D]),
     "bbx_ecg_set": (_I, [_P, _I, _P, _I64, _I64]),
     "bbx_step": (_I, [_P, _I64]),
     "bbx_readout": (_I, [_P, _I, _I, _P, _P, _SZ, _I]),
     "bbx_info": (_I, [_P, _I, C.POINTER(_I64)]),
+    "bbx_tips": (_I, [_P, _I, _D, _I, _D, _P, _P, _I64, C.POINTER(_I64)]),
     "bbx_grid_destroy": (None, [_P]),
     "bbx_last_error": (C.c_char_p, []),
     "bbx_mlp_create": (_I, [_I, _I, C.c_uint64, _P, C.POINTER(_P)]),
@@ -182,6 +190,10 @@ def bbx_tabulation_set(g, dv):
     _check(_lib.bbx_tabulation_set(g, float(dv)))
 
 
+def bbx_integrator_set(g, integrator):
+    _check(_lib.bbx_integrator_set(g, int(integrator)))
+
+
 def bbx_clock_set(g, step):
     _check(_lib.bbx_clock_set(g, int(step)))
 
@@ -214,6 +226,46 @@ def bbx_grid_destroy(g):
     _lib.bbx_grid_destroy(g)
 
 
+def bbx_tips(g, var_u, u_level, var_v, v_level, max_points=100000):
+    """Phase singularities: (stats[7], points (n, 3) mm)."""
+    stats = np.zeros(7)
+    pts = np.zeros((max(int(max_points), 0), 3))
+    n = C.c_int64()
+    _check(_lib.bbx_tips(g, int(var_u), float(u_level), int(var_v), float(v_level), _ptr(stats),
+                         _ptr(pts) if max_points else None, int(max_points), C.byref(n)))
+    return stats, pts[:min(n.value, int(max_points))].copy()
+
+
+def bbx_slab_bounds(mask, nslab):
+    """Tissue-balanced z boundaries (nslab + 1 ints) of a (nz, ny, nx) mask."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    nz, ny, nx = mask.shape
+    out = np.zeros(int(nslab) + 1, np.int32)
+    _check(_lib.bbx_slab_bounds(nx, ny, nz, _ptr(mask), int(nslab), _ptr(out)))
+    return out
+
+
+def bbx_slab_create(mask, z0, z1, h, fibre, D_par, D_perp, precision, hip_stream=None):
+    """Handle of the grid of global planes [z0, z1) of the whole box's mask / fibre."""
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    nz, ny, nx = mask.shape
+    fib = None if fibre is None else np.ascontiguousarray(fibre, dtype=np.float64)
+    out = C.c_void_p()
+    _check(_lib.bbx_slab_create(nx, ny, nz, int(z0), int(z1), float(h), _ptr(mask), _ptr(fib),
+                                float(D_par), float(D_perp), int(precision),
+                                _stream_handle(hip_stream), C.byref(out)))
+    return out
+
+
+def bbx_halo_pack(g, side, buf, count):
+    """buf: device tensor or address."""
+    _check(_lib.bbx_halo_pack(g, int(side), _dptr(buf), int(count)))
+
+
+def bbx_halo_unpack(g, side, buf, count):
+    _check(_lib.bbx_halo_unpack(g, int(side), _dptr(buf), int(count)))
+
+
 # ---------------------------------------------------------------- convenience
 class Grid:
     """Owning wrapper: a grid on the GPU with its model, stimuli and recorder."""
@@ -227,6 +279,33 @@ class Grid:
         nz, ny, nx = mask.shape
         self.handle = bbx_grid_create(nx, ny, nz, h, mask, fibre, Dpar, Dperp, precision, stream)
         self.mask = mask
+
+    @classmethod
+    def slab(cls, mask, z0, z1, h, fibre=None, Dpar=1.0, Dperp=1.0, precision=BBX_FP32,
+             stream=None):
+        """The grid of global planes [z0, z1) of a box, with one halo plane each side;
+        its box (self.shape) has z1 - z0 + 2 planes, plane 0 = global plane z0 - 1."""
+        mask = np.asarray(mask, dtype=np.uint8)
+        g = cls.__new__(cls)
+        g.handle = bbx_slab_create(mask, z0, z1, h, fibre, Dpar, Dperp, precision, stream)
+        nz, ny, nx = mask.shape
+        g.shape = (z1 - z0 + 2, ny, nx)
+        sl = np.zeros(g.shape, np.uint8)
+        lo, hi = max(z0 - 1, 0), min(z1 + 1, nz)
+        sl[lo - (z0 - 1):hi - (z0 - 1)] = mask[lo:hi]
+        g.mask = sl
+        return g
+
+    def halo_counts(self):
+        """(send lo, send hi, recv lo, recv hi) value counts of a slab grid."""
+        return tuple(bbx_info(self.handle, w) for w in (BBX_INFO_SEND_LO, BBX_INFO_SEND_HI,
+                                                         BBX_INFO_RECV_LO, BBX_INFO_RECV_HI))
+
+    def pack(self, side, buf, count):
+        bbx_halo_pack(self.handle, side, buf, count)
+
+    def unpack(self, side, buf, count):
+        bbx_halo_unpack(self.handle, side, buf, count)
 
     def close(self):
         if self.handle is not None:
@@ -263,6 +342,12 @@ class Grid:
 
     def clock(self, step):
         bbx_clock_set(self.handle, step)
+
+    def tips(self, var_u, u_level, var_v, v_level, max_points=100000):
+        return bbx_tips(self.handle, var_u, u_level, var_v, v_level, max_points)
+
+    def integrator(self, integrator):
+        bbx_integrator_set(self.handle, integrator)
 
     def fill(self, var, value):
         bbx_state_fill(self.handle, var, value)

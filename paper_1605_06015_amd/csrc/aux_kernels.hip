@@ -109,6 +109,22 @@ hipError_t launch_gather(const T *box, const int32_t *idx, int dense, int64_t na
     return hipGetLastError();
 }
 
+// box[idx[i]] = src[i]: writes received halo values into a slab's halo plane.
+template <typename T>
+__global__ void k_scatter(const T *src, const int32_t *idx, int64_t n, T *box)
+{
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n) box[idx[i]] = src[i];
+}
+
+template <typename T>
+hipError_t launch_scatter(const T *src, const int32_t *idx, int64_t n, T *box, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks_for(n)), dim3(kBlock), 0, s, src, idx, n, box);
+    return hipGetLastError();
+}
+
 // Reduction over tissue voxels (optionally restricted to a region) in FP64.
 // Pass 1: part p reduces the contiguous slice [p*chunk, (p+1)*chunk) of the
 // tissue list, each thread a strided subsequence, then a fixed-shape tree in
@@ -276,7 +292,7 @@ __global__ void k_crn_table(double vmin, double dv, int n, double dt, float *tab
     }
     if (k >= n) return;
     double c[kin::CRN_V];
-    kin::crn_vterms<double>(vmin + k * dv, dt, c);
+    kin::crn_vterms<kin::Step>(vmin + k * dv, dt, c);
     for (int q = 0; q < kin::CRN_V; q++) tab[kin::CRN_V * (1 + k) + q] = (float)c[q];
 }
 
@@ -300,7 +316,8 @@ hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab
                                             int64_t, int64_t, int *, hipStream_t);            \
     template hipError_t launch_weights<T>(const StepArgs<T> &, int, double *, hipStream_t);   \
     template hipError_t launch_gather<T>(const T *, const int32_t *, int, int64_t, T *,       \
-                                         hipStream_t);
+                                         hipStream_t);                                        \
+    template hipError_t launch_scatter<T>(const T *, const int32_t *, int64_t, T *, hipStream_t);
 BBX_INST(float)
 BBX_INST(double)
 template hipError_t launch_fill<uint8_t>(uint8_t *, uint8_t, int64_t, hipStream_t);

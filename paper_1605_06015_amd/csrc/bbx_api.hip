@@ -104,6 +104,7 @@ struct bbx_grid {
     int st_alloc = 0;  // variables allocated in d_st
 
     int model = -1, nvar = 1, scheme = 0;
+    int integrator = 0;                // BBX_INTEGRATOR_*
     double dt = 0, prm[kMaxParams] = {};
 
     std::vector<StimDef> stims;
@@ -135,6 +136,12 @@ struct bbx_grid {
     double *d_ecg_series = nullptr, *d_ecg_parts = nullptr, *d_ecg_now = nullptr;
     int nparts = 1024;
     size_t bytes = 0;
+    // z-slab sub-domain (bbx_slab_create): box planes 0 and nz-1 are halo planes of the
+    // neighbouring slabs; zoff = global z of plane 0.  side 0 = lower, 1 = upper.
+    int slab = 0, zoff = 0;
+    int64_t send_n[2] = {0, 0}, recv_n[2] = {0, 0};
+    int32_t *d_send[2] = {nullptr, nullptr}, *d_recv[2] = {nullptr, nullptr};
+    int32_t *d_map = nullptr;          // box -> tissue index (-1 void), built on first use
 };
 
 namespace {
@@ -162,7 +169,8 @@ void free_all(bbx_grid *g)
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
                   g->d_acc_list, g->d_acc_cnt, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
-                  g->snet.bias, g->snet.norm};
+                  g->snet.bias, g->snet.norm, g->d_send[0], g->d_send[1], g->d_recv[0],
+                  g->d_recv[1], g->d_map};
     for (void *p : ps) dfree(p);
 }
 
@@ -203,6 +211,7 @@ StepArgs<T> make_args(const bbx_grid *g)
     for (int i = 0; i < kMaxParams; i++) a.prm[i] = (T)g->prm[i];
     a.dt = (T)g->dt;
     a.split = g->scheme == BBX_SCHEME_SPLIT;
+    a.rk4 = g->integrator == BBX_INTEGRATOR_RK4;
     a.tab = (g->tab_dv > 0 && g->model == BBX_MODEL_CRN && g->prec == BBX_FP32) ? g->d_tab : nullptr;
     a.nstim = (int)g->stims.size();
     a.stimbits = g->d_stimbits;
@@ -220,10 +229,11 @@ StepArgs<T> make_args(const bbx_grid *g)
     // (CRN cup: 4 MB box, 31 MB state; thin shell: 77 MB box, 128 MB state).
     a.nt = (double)g->nbox * sizeof(T) > kInfinityCacheBytes ||
            (double)g->nact * (g->nvar - 1) * sizeof(T) > kInfinityCacheBytes;
+    if (a.rk4) a.nt = 0;               // the RK4 kernels use cached accesses only
     // Dense boxes with light kinetics (<= 4 variables) use the z-marching LDS kernel;
     // with the 19/21-variable models the one-voxel-per-thread kernel is faster
     // (measured on a 300^3 CRN box: 1.02 vs 1.12 ms per step), and a.zc = 0 selects it.
-    if (g->dense && g->nvar <= 4) {
+    if (g->dense && g->nvar <= 4 && !a.rk4) {
         a.gx = (g->nx + kTileX - 1) / kTileX;
         a.gy = (g->ny + kTileY - 1) / kTileY;
         // z-chunk: long enough to amortise the two extra halo planes, short enough
@@ -393,15 +403,20 @@ int download_mask(const bbx_grid *g, std::vector<uint8_t> &mask)
     return BBX_OK;
 }
 
+// Geometry preprocessing.  Tissue voxels of the box planes [own0, own1) are the grid's
+// own (stepped) voxels; tissue in other planes (a slab's halo planes) only takes part as
+// neighbours.
 template <typename T>
-int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre)
+int create_impl(bbx_grid *g, const uint8_t *mask, const double *fibre, int own0, int own1)
 {
     // tissue list (increasing box order)
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    const int64_t b0 = own0 * nxy, b1 = own1 * nxy;
     int64_t count = 0;
-    for (int64_t b = 0; b < g->nbox; b++) count += mask[b] != 0;
+    for (int64_t b = b0; b < b1; b++) count += mask[b] != 0;
     std::vector<int32_t> idx;
     idx.reserve((size_t)count);
-    for (int64_t b = 0; b < g->nbox; b++)
+    for (int64_t b = b0; b < b1; b++)
         if (mask[b]) idx.push_back((int32_t)b);
     g->nact = (int64_t)idx.size();
     g->dense = g->nact == g->nbox;
@@ -740,54 +755,202 @@ extern "C" {
 
 const char *bbx_last_error(void) { return g_err.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+// Shared by bbx_grid_create and bbx_slab_create: validate, build, and on success hand
+// the grid to *out.  Box planes [own0, own1) hold the grid's own voxels.
+int grid_create_common(int nx, int ny, int nz, double h, const uint8_t *mask, const double *fibre,
+                       double D_par, double D_perp, int precision, void *hip_stream, int own0,
+                       int own1, bbx_grid **out)
+{
+    if (!out) return fail(BBX_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (nx < 1 || ny < 1 || nz < 1) return fail(BBX_EINVAL, "box sizes must be >= 1");
+    const int64_t nbox = (int64_t)nx * ny * nz;
+    if (nbox > 2147483647LL) return fail(BBX_EINVAL, "box has more than 2^31-1 voxels");
+    if (!(h > 0) || !isfinite(h)) return fail(BBX_EINVAL, "h must be positive");
+    if (!(D_par > 0) || !(D_perp > 0) || !isfinite(D_par) || !isfinite(D_perp))
+        return fail(BBX_EINVAL, "D_par and D_perp must be positive");
+    if (precision != BBX_FP32 && precision != BBX_FP64) return fail(BBX_EINVAL, "bad precision");
+    if (!mask) return fail(BBX_EINVAL, "mask is NULL");
+    if (fibre) {
+        for (int64_t b = 0; b < nbox; b++) {
+            if (!mask[b]) continue;
+            const double *v = fibre + 3 * b;
+            const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(n >= 1e-12) || !isfinite(n))
+                return fail(BBX_EINVAL, "tissue voxel %lld has a non-normalisable fibre", (long long)b);
+        }
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BBX_EDEVICE, "no HIP device");
+
+    bbx_grid *g = new bbx_grid();
+    g->nx = nx; g->ny = ny; g->nz = nz; g->nbox = nbox;
+    g->h = h; g->Dpar = D_par; g->Dperp = D_perp;
+    g->prec = precision; g->es = precision == BBX_FP64 ? 8 : 4;
+    g->aniso = fibre != nullptr && D_par != D_perp;
+    g->stream = (hipStream_t)hip_stream;
+    int rc = precision == BBX_FP64 ? create_impl<double>(g, mask, fibre, own0, own1)
+                                   : create_impl<float>(g, mask, fibre, own0, own1);
+    if (rc != BBX_OK) {
+        std::string keep = g_err;
+        free_all(g);
+        delete g;
+        g_err = keep;
+        return rc;
+    }
+    g->h_stimbits.assign((size_t)g->nact, 0u);
+    *out = g;
+    return BBX_OK;
+}
+
+// Box indices of the tissue voxels of box plane z, x fastest.
+std::vector<int32_t> plane_tissue(const bbx_grid *g, const uint8_t *mask, int z)
+{
+    std::vector<int32_t> v;
+    const int64_t nxy = (int64_t)g->nx * g->ny;
+    for (int64_t i = 0; i < nxy; i++)
+        if (mask[z * nxy + i]) v.push_back((int32_t)(z * nxy + i));
+    return v;
+}
+
+}  // namespace
+
+extern "C" {
+
 int bbx_grid_create(int nx, int ny, int nz, double h, const uint8_t *mask, const double *fibre,
                     double D_par, double D_perp, int precision, void *hip_stream, bbx_grid **out)
 {
     try {
         g_err.clear();
-        if (!out) return fail(BBX_EINVAL, "out is NULL");
-        *out = nullptr;
+        return grid_create_common(nx, ny, nz, h, mask, fibre, D_par, D_perp, precision, hip_stream,
+                                  0, nz, out);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_slab_bounds(int nx, int ny, int nz, const uint8_t *mask, int nslab, int *z_bounds)
+{
+    try {
+        g_err.clear();
         if (nx < 1 || ny < 1 || nz < 1) return fail(BBX_EINVAL, "box sizes must be >= 1");
-        const int64_t nbox = (int64_t)nx * ny * nz;
-        if (nbox > 2147483647LL) return fail(BBX_EINVAL, "box has more than 2^31-1 voxels");
-        if (!(h > 0) || !isfinite(h)) return fail(BBX_EINVAL, "h must be positive");
-        if (!(D_par > 0) || !(D_perp > 0) || !isfinite(D_par) || !isfinite(D_perp))
-            return fail(BBX_EINVAL, "D_par and D_perp must be positive");
-        if (precision != BBX_FP32 && precision != BBX_FP64) return fail(BBX_EINVAL, "bad precision");
+        if (!mask || !z_bounds) return fail(BBX_EINVAL, "NULL argument");
+        if (nslab < 1 || nslab > nz) return fail(BBX_EINVAL, "nslab must be in [1, nz]");
+        const int64_t nxy = (int64_t)nx * ny;
+        std::vector<int64_t> cum((size_t)nz + 1, 0);      // tissue in planes [0, z)
+        for (int z = 0; z < nz; z++) {
+            int64_t c = 0;
+            for (int64_t i = 0; i < nxy; i++) c += mask[z * nxy + i] != 0;
+            cum[z + 1] = cum[z] + c;
+        }
+        const int64_t total = cum[nz];
+        z_bounds[0] = 0;
+        for (int k = 1; k < nslab; k++) {
+            // the first plane boundary at which the tissue below reaches k/nslab of the
+            // total, kept at least one plane above the previous boundary and leaving at
+            // least one plane for each slab still to come
+            const double target = (double)total * k / nslab;
+            int z = z_bounds[k - 1] + 1;
+            while (z < nz - (nslab - k) && (double)cum[z] < target) z++;
+            // the nearer of z - 1 and z to the target
+            if (z - 1 > z_bounds[k - 1] && target - (double)cum[z - 1] < (double)cum[z] - target) z--;
+            z_bounds[k] = z;
+        }
+        z_bounds[nslab] = nz;
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
+int bbx_slab_create(int nx, int ny, int nz, int z0, int z1, double h, const uint8_t *mask,
+                    const double *fibre, double D_par, double D_perp, int precision,
+                    void *hip_stream, bbx_grid **out)
+{
+    try {
+        g_err.clear();
+        if (out) *out = nullptr;
+        if (nx < 1 || ny < 1 || nz < 1) return fail(BBX_EINVAL, "box sizes must be >= 1");
         if (!mask) return fail(BBX_EINVAL, "mask is NULL");
-        if (fibre) {
-            for (int64_t b = 0; b < nbox; b++) {
-                if (!mask[b]) continue;
-                const double *v = fibre + 3 * b;
-                const double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-                if (!(n >= 1e-12) || !isfinite(n))
-                    return fail(BBX_EINVAL, "tissue voxel %lld has a non-normalisable fibre", (long long)b);
+        if (z0 < 0 || z1 > nz || z0 >= z1) return fail(BBX_EINVAL, "need 0 <= z0 < z1 <= nz");
+        const int L = z1 - z0, ns = L + 2;
+        const int64_t nxy = (int64_t)nx * ny;
+        if (nxy * ns > 2147483647LL) return fail(BBX_EINVAL, "slab has more than 2^31-1 voxels");
+        // the slab's box: global planes z0-1 .. z1 (planes outside the global box are void)
+        std::vector<uint8_t> m((size_t)(nxy * ns), 0);
+        std::vector<double> f(fibre ? (size_t)(3 * nxy * ns) : 0, 0.0);
+        for (int zs = 0; zs < ns; zs++) {
+            const int zg = z0 - 1 + zs;
+            if (zg < 0 || zg >= nz) continue;
+            memcpy(&m[zs * nxy], mask + zg * nxy, (size_t)nxy);
+            if (fibre) memcpy(&f[3 * zs * nxy], fibre + 3 * zg * nxy, (size_t)(3 * nxy) * sizeof(double));
+        }
+        bbx_grid *g = nullptr;
+        int rc = grid_create_common(nx, ny, ns, h, m.data(), fibre ? f.data() : nullptr, D_par,
+                                    D_perp, precision, hip_stream, 1, L + 1, &g);
+        if (rc) return rc;
+        g->slab = 1;
+        g->zoff = z0 - 1;
+        const std::vector<int32_t> lists[4] = {plane_tissue(g, m.data(), 1), plane_tissue(g, m.data(), L),
+                                               plane_tissue(g, m.data(), 0), plane_tissue(g, m.data(), L + 1)};
+        int32_t **dst[4] = {&g->d_send[0], &g->d_send[1], &g->d_recv[0], &g->d_recv[1]};
+        int64_t *cnt[4] = {&g->send_n[0], &g->send_n[1], &g->recv_n[0], &g->recv_n[1]};
+        for (int k = 0; k < 4; k++) {
+            *cnt[k] = (int64_t)lists[k].size();
+            hipError_t e = dalloc(g, dst[k], lists[k].size() * sizeof(int32_t));
+            if (e == hipSuccess && !lists[k].empty())
+                e = hipMemcpy(*dst[k], lists[k].data(), lists[k].size() * sizeof(int32_t), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                std::string keep = hipGetErrorString(e);
+                bbx_grid_destroy(g);
+                return fail(BBX_ENOMEM, "halo lists: %s", keep.c_str());
             }
         }
-        int ndev = 0;
-        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(BBX_EDEVICE, "no HIP device");
-
-        bbx_grid *g = new bbx_grid();
-        g->nx = nx; g->ny = ny; g->nz = nz; g->nbox = nbox;
-        g->h = h; g->Dpar = D_par; g->Dperp = D_perp;
-        g->prec = precision; g->es = precision == BBX_FP64 ? 8 : 4;
-        g->aniso = fibre != nullptr && D_par != D_perp;
-        g->stream = (hipStream_t)hip_stream;
-        int rc = precision == BBX_FP64 ? create_impl<double>(g, mask, fibre)
-                                       : create_impl<float>(g, mask, fibre);
-        if (rc != BBX_OK) {
-            std::string keep = g_err;
-            free_all(g);
-            delete g;
-            g_err = keep;
-            return rc;
-        }
-        g->h_stimbits.assign((size_t)g->nact, 0u);
         *out = g;
         return BBX_OK;
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
     }
+}
+
+int bbx_halo_pack(bbx_grid *g, int side, void *buf_dev, int64_t count)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (!g->slab) return fail(BBX_ESTATE, "not a slab grid (bbx_slab_create)");
+    if (side != 0 && side != 1) return fail(BBX_EINVAL, "side must be 0 (lower) or 1 (upper)");
+    if (count != g->send_n[side])
+        return fail(BBX_EINVAL, "side %d sends %lld values, got count %lld", side,
+                    (long long)g->send_n[side], (long long)count);
+    if (count > 0 && !buf_dev) return fail(BBX_EINVAL, "buffer is NULL");
+    hipError_t e = g->prec ? launch_gather<double>((const double *)g->d_V[g->cur], g->d_send[side], 0,
+                                                   count, (double *)buf_dev, g->stream)
+                           : launch_gather<float>((const float *)g->d_V[g->cur], g->d_send[side], 0,
+                                                  count, (float *)buf_dev, g->stream);
+    if (e != hipSuccess) return hip_fail(e, "halo pack");
+    return BBX_OK;
+}
+
+int bbx_halo_unpack(bbx_grid *g, int side, const void *buf_dev, int64_t count)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (!g->slab) return fail(BBX_ESTATE, "not a slab grid (bbx_slab_create)");
+    if (side != 0 && side != 1) return fail(BBX_EINVAL, "side must be 0 (lower) or 1 (upper)");
+    if (count != g->recv_n[side])
+        return fail(BBX_EINVAL, "side %d receives %lld values, got count %lld", side,
+                    (long long)g->recv_n[side], (long long)count);
+    if (count > 0 && !buf_dev) return fail(BBX_EINVAL, "buffer is NULL");
+    hipError_t e = g->prec ? launch_scatter<double>((const double *)buf_dev, g->d_recv[side], count,
+                                                    (double *)g->d_V[g->cur], g->stream)
+                           : launch_scatter<float>((const float *)buf_dev, g->d_recv[side], count,
+                                                   (float *)g->d_V[g->cur], g->stream);
+    if (e != hipSuccess) return hip_fail(e, "halo unpack");
+    return BBX_OK;
 }
 
 int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, double dt, int scheme)
@@ -937,7 +1100,7 @@ int bbx_ecg_set(bbx_grid *g, int nelec, const double *xyz_mm, int64_t every, int
             const double x = xyz_mm[3 * e], y = xyz_mm[3 * e + 1], z = xyz_mm[3 * e + 2];
             if (!isfinite(x) || !isfinite(y) || !isfinite(z)) return fail(BBX_EINVAL, "electrode %d not finite", e);
             // an electrode on a tissue voxel centre would divide by zero
-            const double fx = x / g->h, fy = y / g->h, fz = z / g->h;
+            const double fx = x / g->h, fy = y / g->h, fz = z / g->h - g->zoff;
             if (fx == floor(fx) && fy == floor(fy) && fz == floor(fz) && fx >= 0 && fy >= 0 && fz >= 0 &&
                 fx < g->nx && fy < g->ny && fz < g->nz) {
                 if (mask.empty()) {
@@ -949,7 +1112,7 @@ int bbx_ecg_set(bbx_grid *g, int nelec, const double *xyz_mm, int64_t every, int
             }
             el.x[e] = x;
             el.y[e] = y;
-            el.z[e] = z;
+            el.z[e] = z - g->zoff * g->h;   // a slab's box starts at global plane zoff
         }
         HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
         dfree(g->d_ecg_series);
@@ -990,6 +1153,18 @@ int bbx_tabulation_set(bbx_grid *g, double dv)
     return build_table(g);
 }
 
+int bbx_integrator_set(bbx_grid *g, int integrator)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (integrator != BBX_INTEGRATOR_EULER_RL && integrator != BBX_INTEGRATOR_RK4)
+        return fail(BBX_EINVAL, "unknown integrator %d", integrator);
+    if (integrator == BBX_INTEGRATOR_RK4 && g->sur)
+        return fail(BBX_ENOTSUP, "the surrogate stands in for the Euler / Rush-Larsen step");
+    g->integrator = integrator;
+    return BBX_OK;
+}
+
 int bbx_clock_set(bbx_grid *g, int64_t step)
 {
     g_err.clear();
@@ -1028,6 +1203,94 @@ int bbx_readout(bbx_grid *g, int what, int var, const uint8_t *region, void *out
     }
 }
 
+}  // extern "C"
+
+namespace {
+
+template <typename T>
+int tips_impl(bbx_grid *g, int vu, double ul, int vv, double vl, double *stats, double *points,
+              int64_t max_points, int64_t *npoints)
+{
+    if (!g->dense && !g->d_map) {
+        hipError_t e = dalloc(g, &g->d_map, (size_t)g->nbox * sizeof(int32_t));
+        if (e != hipSuccess) return hip_fail(e, "hipMalloc");
+        e = launch_box_map(g->d_map, g->nbox, g->d_idx, g->nact, g->stream);
+        if (e != hipSuccess) {
+            dfree(g->d_map);
+            g->d_map = nullptr;
+            return hip_fail(e, "box map");
+        }
+    }
+    const int64_t cap = points ? max_points : 0;
+    DevBuf part, pts;
+    HIP_TRY(hipMalloc(&part.p, kTipPartBytes + 8 * sizeof(double) + sizeof(unsigned long long)), "hipMalloc");
+    if (cap > 0) HIP_TRY(hipMalloc(&pts.p, (size_t)cap * 3 * sizeof(double)), "hipMalloc");
+    double *out = (double *)((char *)part.p + kTipPartBytes);
+    unsigned long long *cnt = (unsigned long long *)(out + 8);
+    HIP_TRY(launch_fill<int>((int *)cnt, 0, 2, g->stream), "fill");
+    TipLaunch<T> L = {};
+    L.nx = g->nx; L.ny = g->ny; L.nz = g->nz; L.dense = g->dense;
+    L.h = g->h; L.ul = ul; L.vl = vl;
+    L.map = g->d_map;
+    const T *V = (const T *)g->d_V[g->cur], *st = (const T *)g->d_st;
+    if (vu == 0) L.u_box = V; else L.u_list = st + (int64_t)(vu - 1) * g->pitch;
+    if (vv == 0) L.v_box = V; else L.v_list = st + (int64_t)(vv - 1) * g->pitch;
+    L.part = (double *)part.p;
+    L.out = out;
+    L.pts = (double *)pts.p;
+    L.max_pts = cap;
+    L.count = cnt;
+    if (g->nx >= 2 && g->ny >= 2 && g->nact > 0) {
+        HIP_TRY(launch_tips<T>(L, g->stream), "tips");
+    } else {
+        HIP_TRY(launch_fill<double>(out, 0.0, 7, g->stream), "fill");
+    }
+    double sums[7];
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(sums, out, sizeof sums, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+    HIP_TRY(hipMemcpyAsync(&n, cnt, sizeof n, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+    HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    const int64_t nw = (int64_t)n < cap ? (int64_t)n : cap;
+    if (nw > 0) {
+        HIP_TRY(hipMemcpyAsync(points, pts.p, (size_t)nw * 3 * sizeof(double), hipMemcpyDeviceToHost,
+                               g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+    }
+    stats[0] = sums[0];
+    for (int i = 1; i < 7; i++) stats[i] = 0.0;
+    if (sums[0] > 0) {
+        for (int i = 0; i < 3; i++) {
+            const double mean = sums[1 + i] / sums[0];
+            stats[1 + i] = mean;
+            stats[4 + i] = sqrt(fmax(sums[4 + i] / sums[0] - mean * mean, 0.0));
+        }
+    }
+    if (npoints) *npoints = (int64_t)n;
+    return BBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbx_tips(bbx_grid *g, int var_u, double u_level, int var_v, double v_level, double *stats,
+             double *points, int64_t max_points, int64_t *npoints)
+{
+    try {
+        g_err.clear();
+        if (!g || !stats) return fail(BBX_EINVAL, "NULL argument");
+        if (g->model < 0) return fail(BBX_ESTATE, "set a model first");
+        if (var_u < 0 || var_u >= g->nvar || var_v < 0 || var_v >= g->nvar)
+            return fail(BBX_EINVAL, "variables must be in [0, %d)", g->nvar);
+        if (!isfinite(u_level) || !isfinite(v_level)) return fail(BBX_EINVAL, "levels must be finite");
+        if (max_points < 0 || max_points > ((int64_t)1 << 28)) return fail(BBX_EINVAL, "max_points out of range");
+        return g->prec ? tips_impl<double>(g, var_u, u_level, var_v, v_level, stats, points, max_points, npoints)
+                       : tips_impl<float>(g, var_u, u_level, var_v, v_level, stats, points, max_points, npoints);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
 int bbx_info(const bbx_grid *g, int what, int64_t *out)
 {
     g_err.clear();
@@ -1037,6 +1300,10 @@ int bbx_info(const bbx_grid *g, int what, int64_t *out)
     case BBX_INFO_NVAR: *out = g->nvar; return BBX_OK;
     case BBX_INFO_NBOX: *out = g->nbox; return BBX_OK;
     case BBX_INFO_DEVICE_BYTES: *out = (int64_t)g->bytes; return BBX_OK;
+    case BBX_INFO_SEND_LO: *out = g->send_n[0]; return BBX_OK;
+    case BBX_INFO_SEND_HI: *out = g->send_n[1]; return BBX_OK;
+    case BBX_INFO_RECV_LO: *out = g->recv_n[0]; return BBX_OK;
+    case BBX_INFO_RECV_HI: *out = g->recv_n[1]; return BBX_OK;
     default: return fail(BBX_EINVAL, "unknown info %d", what);
     }
 }
@@ -1378,6 +1645,8 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
             return BBX_OK;
         }
         if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the surrogate runs on FP32 grids");
+        if (g->integrator != BBX_INTEGRATOR_EULER_RL)
+            return fail(BBX_ENOTSUP, "the surrogate stands in for the Euler / Rush-Larsen step");
         if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN &&
             g->model != BBX_MODEL_TP06)
             return fail(BBX_ENOTSUP, "no surrogate step for model %d", g->model);

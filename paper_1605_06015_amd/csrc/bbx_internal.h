@@ -48,6 +48,7 @@ struct StepArgs {
     T prm[kMaxParams];
     T dt;
     int split;
+    int rk4;                   // 1: kinetics by the classical RK4 integrator
     const float *tab;          // tabulated voltage-only kinetic terms (FP32 CRN) or null
     // stimulus
     int nstim;
@@ -80,6 +81,25 @@ void api_clear_error();
 // Launchers (step_kernels.hip).  Return hipSuccess or the launch error.
 template <typename T>
 hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s);
+
+// Phase-singularity finder (tips_kernels.hip).  u_box / v_box: a field in box layout
+// (V), else u_list / v_list over the tissue list (indexed through map unless dense).
+template <typename T>
+struct TipLaunch {
+    int nx, ny, nz, dense;
+    double h, ul, vl;
+    const int32_t *map;
+    const T *u_box, *u_list, *v_box, *v_list;
+    double *part;                // [1024][7] workgroup sums
+    double *out;                 // [7] count, sum x, y, z, sum x^2, y^2, z^2 (mm)
+    double *pts;                 // [max_pts][3] or null
+    int64_t max_pts;
+    unsigned long long *count;   // points found (zeroed by the caller)
+};
+constexpr int kTipPartBytes = 1024 * 7 * 8;
+template <typename T>
+hipError_t launch_tips(const TipLaunch<T> &L, hipStream_t s);
+hipError_t launch_box_map(int32_t *map, int64_t nbox, const int32_t *idx, int64_t nact, hipStream_t s);
 
 // Pseudo-ECG electrodes (ecg_kernels.hip): positions in mm, grid step h.
 constexpr int kMaxElectrodes = 16;
@@ -120,5 +140,8 @@ constexpr int kTabWidth = 32;                           // floats per table node
 template <typename T>
 hipError_t launch_gather(const T *box, const int32_t *idx, int dense, int64_t nact, T *dst,
                          hipStream_t s);
+// box[idx[i]] = src[i] for i < n (a slab's halo unpack).
+template <typename T>
+hipError_t launch_scatter(const T *src, const int32_t *idx, int64_t n, T *box, hipStream_t s);
 
 }  // namespace bbx

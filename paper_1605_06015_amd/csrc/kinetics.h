@@ -10,7 +10,9 @@
 // Rush-Larsen for gates -- y+ = y_inf + (y - y_inf) exp(-dt/tau), the exact
 // solution of y' = (y_inf - y)/tau with the voltage frozen (eqs (gate), (RL),
 // (RLcoeff), with the two coefficients in the order that makes it exact).
-// `tab` is the optional table of voltage-only terms (CrnTab), else unused.
+// `tab` is the optional table of voltage-only terms (CrnTab), else unused.  With
+// the policy U = Rate (below) advance() instead leaves dy/dt of every variable in g
+// (same return value): the right-hand side the RK4 integrator needs.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -80,10 +82,38 @@ __device__ __forceinline__ T lgs(T x)
     return rcp(T(1) + ex(x));
 }
 
+// How advance() treats each variable it updates.  Step: one step of the explicit
+// scheme -- forward Euler y + dt r for concentrations and recovery variables (eq
+// (Euler)), Rush-Larsen y_inf + (y - y_inf) e^{-dt k} for gates (k = 1/tau).  Rate:
+// the right-hand side itself, dy/dt = r or k (y_inf - y), which the classical
+// fourth-order Runge-Kutta integrator evaluates at its four stages (the `rk4` solver
+// of "Kinetics solvers").  The Step forms keep the operand order of each model's
+// update (y + dt r, y + dt s e, e^{-dt k}, e^{-dt m k}).
+struct Step {
+    static constexpr bool kRate = false;
+    template <typename T> __device__ static T eu(T y, T r, T dt) { return y + dt * r; }
+    template <typename T> __device__ static T eus(T y, T s, T e, T dt) { return y + dt * s * e; }
+    template <typename T> __device__ static T rl(T y, T yinf, T k, T dt) { return rl_rate(y, yinf, k, dt); }
+    // CRN voltage terms: the one-step factor e^{-dt k} (e^{-dt m k}) and its use
+    template <typename T> __device__ static T fac(T k, T dt) { return ex(-dt * k); }
+    template <typename T> __device__ static T facm(T m, T k, T dt) { return ex(-dt * m * k); }
+    template <typename T> __device__ static T rlf(T y, T yinf, T f) { return yinf + (y - yinf) * f; }
+};
+struct Rate {
+    static constexpr bool kRate = true;
+    template <typename T> __device__ static T eu(T, T r, T) { return r; }
+    template <typename T> __device__ static T eus(T, T s, T e, T) { return s * e; }
+    template <typename T> __device__ static T rl(T y, T yinf, T k, T) { return k * (yinf - y); }
+    template <typename T> __device__ static T fac(T k, T) { return k; }
+    template <typename T> __device__ static T facm(T m, T k, T) { return m * k; }
+    template <typename T> __device__ static T rlf(T y, T yinf, T k) { return k * (yinf - y); }
+};
+
 // ---------------------------------------------------------------- pure diffusion
 template <typename T>
 struct None {
     static constexpr int NV = 1, GATE0 = 1;
+    template <class U = Step>
     __device__ static T advance(const T *, T, T *, T, const float *) { return T(0); }
 };
 
@@ -92,11 +122,12 @@ struct None {
 template <typename T>
 struct Barkley {
     static constexpr int NV = 2, GATE0 = 2;
+    template <class U = Step>
     __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
     {
         T v = g[0];
         T uth = (v + p[1]) / p[0];
-        g[0] = v + dt * (u - v);
+        g[0] = U::eu(v, (u - v), dt);
         return u * (T(1) - u) * (u - uth) / p[2];
     }
 };
@@ -106,6 +137,7 @@ struct Barkley {
 template <typename T>
 struct Zfk {
     static constexpr int NV = 1, GATE0 = 1;
+    template <class U = Step>
     __device__ static T advance(const T *p, T V, T *, T, const float *)
     {
         return V * (V - p[0]) * (T(1) - V);
@@ -117,10 +149,11 @@ struct Zfk {
 template <typename T>
 struct Fhn {
     static constexpr int NV = 2, GATE0 = 2;
+    template <class U = Step>
     __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
     {
         T v = g[0];
-        g[0] = v + dt * p[0] * (u + p[1] - p[2] * v);
+        g[0] = U::eus(v, p[0], (u + p[1] - p[2] * v), dt);
         return (u - u * u * u * T(1.0 / 3.0) - v) / p[0];
     }
 };
@@ -142,6 +175,7 @@ struct Fhn {
 template <typename T>
 struct Fk4 {
     static constexpr int NV = 4, GATE0 = 1;
+    template <class U = Step>
     __device__ static T advance(const T *p, T u, T *g, T dt, const float *)
     {
         const T thv = T(0.3), thw = T(0.13), thvm = T(0.006), tho = T(0.006);
@@ -158,12 +192,12 @@ struct Fk4 {
         // selected first (one exponential per gate)
         const T vinf = u < thvm ? T(1) : T(0);
         const T kvm = Hvm ? T(1.0 / 1150.0) : T(1.0 / 60.0);
-        g[0] = rl_rate(v, Hv ? T(0) : vinf, Hv ? T(1.0 / 1.4506) : kvm, dt);
+        g[0] = U::rl(v, Hv ? T(0) : vinf, Hv ? T(1.0 / 1.4506) : kvm, dt);
         const T twm = T(60) + (T(15) - T(60)) * (T(1) + th(T(65) * (u - T(0.03)))) * T(0.5);
         const T winf = Ho ? T(0.94) : T(1) - dv(u, T(0.07));
-        g[1] = rl_rate(w, Hw ? T(0) : winf, rcp(Hw ? p[3] : twm), dt);
+        g[1] = U::rl(w, Hw ? T(0) : winf, rcp(Hw ? p[3] : twm), dt);
         const T sinf = (T(1) + th(T(2.0994) * (u - T(0.9087)))) * T(0.5);
-        g[2] = rl_rate(s, sinf, Hw ? T(1.0 / 16.0) : T(1.0 / 2.7342), dt);
+        g[2] = U::rl(s, sinf, Hw ? T(1.0 / 16.0) : T(1.0 / 2.7342), dt);
         return -(Jfi + Jso + Jsi);
     }
 };
@@ -187,6 +221,7 @@ constexpr double kNaCaDen = (87.5 * 87.5 * 87.5 + 140.0 * 140.0 * 140.0) * (1.38
 template <typename T>
 struct Tp06 {
     static constexpr int NV = 19, GATE0 = 7;
+    template <class U = Step>
     __device__ static T advance(const T *, T V, T *g, T dt, const float *)
     {
         using namespace tp;
@@ -234,24 +269,24 @@ struct Tp06 {
         const T bsr = rcp(T(1) + dv(T(10.0 * 0.3), (CaSR + T(0.3)) * (CaSR + T(0.3))));
         const T bss = rcp(T(1) + dv(T(0.4 * 0.00025), (Cass + T(0.00025)) * (Cass + T(0.00025))));
         const T c2f = T(kCm / (kVc * kF));
-        g[0] = Ki + dt * (-(IK1 + Ito + IKr + IKs - T(2) * INaK + IpK) * c2f);
-        g[1] = Nai + dt * (-(INa + IbNa + T(3) * INaK + T(3) * INaCa) * c2f);
-        g[2] = Cai + dt * (bc * ((Ileak - Iup) * T(kVsr / kVc) + Ixfer
-                                 - (IbCa + IpCa - T(2) * INaCa) * T(kCm / (2.0 * kVc * kF))));
-        g[3] = Cass + dt * (bss * (-ICaL * T(kCm / (2.0 * kVss * kF)) + Irel * T(kVsr / kVss)
-                                   - Ixfer * T(kVc / kVss)));
-        g[4] = CaSR + dt * (bsr * (Iup - Irel - Ileak));
-        g[5] = Rb + dt * (-k2 * Cass * Rb + T(0.005) * (T(1) - Rb));
+        g[0] = U::eu(Ki, (-(IK1 + Ito + IKr + IKs - T(2) * INaK + IpK) * c2f), dt);
+        g[1] = U::eu(Nai, (-(INa + IbNa + T(3) * INaK + T(3) * INaCa) * c2f), dt);
+        g[2] = U::eu(Cai, (bc * ((Ileak - Iup) * T(kVsr / kVc) + Ixfer
+                                 - (IbCa + IpCa - T(2) * INaCa) * T(kCm / (2.0 * kVc * kF)))), dt);
+        g[3] = U::eu(Cass, (bss * (-ICaL * T(kCm / (2.0 * kVss * kF)) + Irel * T(kVsr / kVss)
+                                   - Ixfer * T(kVc / kVss))), dt);
+        g[4] = U::eu(CaSR, (bsr * (Iup - Irel - Ileak)), dt);
+        g[5] = U::eu(Rb, (-k2 * Cass * Rb + T(0.005) * (T(1) - Rb)), dt);
 
         // gates
-        g[6] = rl_rate(g[6], lgs((T(-26) - V) * T(1.0 / 7.0)),
+        g[6] = U::rl(g[6], lgs((T(-26) - V) * T(1.0 / 7.0)),
                        rcp(dv(T(450), T(1) + ex((T(-45) - V) * T(0.1))) * dv(T(6), T(1) + ex((V + T(30)) * T(1.0 / 11.5)))), dt);
-        g[7] = rl_rate(g[7], lgs((V + T(88)) * T(1.0 / 24.0)),
+        g[7] = U::rl(g[7], lgs((V + T(88)) * T(1.0 / 24.0)),
                        rcp(dv(T(3), T(1) + ex((T(-60) - V) * T(0.05))) * dv(T(1.12), T(1) + ex((V - T(60)) * T(0.05)))), dt);
-        g[8] = rl_rate(g[8], lgs((T(-5) - V) * T(1.0 / 14.0)),
+        g[8] = U::rl(g[8], lgs((T(-5) - V) * T(1.0 / 14.0)),
                        rcp(dv(T(1400), sq(T(1) + ex((T(5) - V) * T(1.0 / 6.0)))) * rcp(T(1) + ex((V - T(35)) * T(1.0 / 15.0))) + T(80)), dt);
         const T mi = lgs((T(-56.86) - V) * T(1.0 / 9.03));
-        g[9] = rl_rate(m, mi * mi,
+        g[9] = U::rl(m, mi * mi,
                        rcp(rcp(T(1) + ex((T(-60) - V) * T(0.2)))
                            * (dv(T(0.1), T(1) + ex((V + T(35)) * T(0.2))) + dv(T(0.10), T(1) + ex((V - T(50)) * T(1.0 / 200.0))))), dt);
         const T hi = lgs((V + T(71.55)) * T(1.0 / 7.43));
@@ -268,25 +303,25 @@ struct Tp06 {
                     T(1) + ex(T(0.311) * (V + T(79.23))));
             bj = dv(T(0.02424) * ex(T(-0.01052) * V), T(1) + ex(T(-0.1378) * (V + T(40.14))));
         }
-        g[10] = rl_rate(h, hi * hi, ah + bh, dt);
-        g[11] = rl_rate(j, hi * hi, aj + bj, dt);
-        g[12] = rl_rate(g[12], lgs((T(-8) - V) * T(1.0 / 7.5)),
+        g[10] = U::rl(h, hi * hi, ah + bh, dt);
+        g[11] = U::rl(j, hi * hi, aj + bj, dt);
+        g[12] = U::rl(g[12], lgs((T(-8) - V) * T(1.0 / 7.5)),
                         rcp((dv(T(1.4), T(1) + ex((T(-35) - V) * T(1.0 / 13.0))) + T(0.25))
                                 * dv(T(1.4), T(1) + ex((V + T(5)) * T(0.2)))
                             + rcp(T(1) + ex((T(50) - V) * T(0.05)))), dt);
         const T v27 = V + T(27);
-        g[13] = rl_rate(g[13], lgs((V + T(20)) * T(1.0 / 7.0)),
+        g[13] = U::rl(g[13], lgs((V + T(20)) * T(1.0 / 7.0)),
                         rcp(T(1102.5) * ex(-v27 * v27 * T(1.0 / 225.0)) + dv(T(200), T(1) + ex((T(13) - V) * T(0.1)))
                             + dv(T(180), T(1) + ex((V + T(30)) * T(0.1))) + T(20)), dt);
-        g[14] = rl_rate(g[14], T(0.67) * lgs((V + T(35)) * T(1.0 / 7.0)) + T(0.33),
+        g[14] = U::rl(g[14], T(0.67) * lgs((V + T(35)) * T(1.0 / 7.0)) + T(0.33),
                         rcp(T(562) * ex(-v27 * v27 * T(1.0 / 240.0)) + dv(T(31), T(1) + ex((T(25) - V) * T(0.1)))
                             + dv(T(80), T(1) + ex((V + T(30)) * T(0.1)))), dt);
         const T cq = (Cass * T(20)) * (Cass * T(20));
-        g[15] = rl_rate(g[15], dv(T(0.6), T(1) + cq) + T(0.4), rcp(dv(T(80), T(1) + cq) + T(2)), dt);
+        g[15] = U::rl(g[15], dv(T(0.6), T(1) + cq) + T(0.4), rcp(dv(T(80), T(1) + cq) + T(2)), dt);
         const T v45 = V + T(45), v40 = V + T(40);
-        g[16] = rl_rate(g[16], lgs((V + T(20)) * T(0.2)),
+        g[16] = U::rl(g[16], lgs((V + T(20)) * T(0.2)),
                         rcp(T(85) * ex(-v45 * v45 * T(1.0 / 320.0)) + dv(T(5), T(1) + ex((V - T(20)) * T(0.2))) + T(3)), dt);
-        g[17] = rl_rate(g[17], lgs((T(20) - V) * T(1.0 / 6.0)),
+        g[17] = U::rl(g[17], lgs((T(20) - V) * T(1.0 / 6.0)),
                         rcp(T(9.5) * ex(-v40 * v40 * T(1.0 / 1800.0)) + T(0.8)), dt);
 
         return -(INa + ICaL + Ito + IKr + IKs + IK1 + INaCa + INaK + IpCa + IpK + IbNa + IbCa);
@@ -321,7 +356,7 @@ constexpr double kNaCa = 1600.0 / ((87.5 * 87.5 * 87.5 + kNao * kNao * kNao) * (
 }  // namespace crn
 
 // Voltage-only terms at V for time step dt.
-template <typename T>
+template <class U, typename T>
 __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
 {
     using namespace crn;
@@ -344,20 +379,20 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
         }
         T k = am + bm;
         c[CV_M] = am * rcp(k);
-        c[CV_MA] = ex(-dt * k);
+        c[CV_MA] = U::fac(k, dt);
         k = ah + bh;
         c[CV_H] = ah * rcp(k);
-        c[CV_HA] = ex(-dt * k);
+        c[CV_HA] = U::fac(k, dt);
         k = aj + bj;
         c[CV_J] = aj * rcp(k);
-        c[CV_JA] = ex(-dt * k);
+        c[CV_JA] = U::fac(k, dt);
     }
     // transient outward (oa, oi) and ultrarapid (ua, ui) potassium gates; the
     // activation rates of oa and ua share one form; Q10 factor 3
     {
         T a_act = T(0.65) * rcp(ex((V + T(10)) * T(-1.0 / 8.5)) + ex((V - T(30)) * T(-1.0 / 59.0)));
         T b_act = T(0.65) * rcp(T(2.5) + ex((V + T(82)) * T(1.0 / 17.0)));
-        const T ea = ex(-dt * T(3) * (a_act + b_act));
+        const T ea = U::facm(T(3), (a_act + b_act), dt);
         c[CV_OA] = lgs((V + T(20.47)) * T(-1.0 / 17.54));
         c[CV_OAA] = ea;
         c[CV_UA] = lgs((V + T(30.3)) * T(-1.0 / 9.6));
@@ -365,22 +400,22 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
         T aoi = rcp(T(18.53) + ex((V + T(113.7)) * T(1.0 / 10.95)));
         T boi = rcp(T(35.56) + ex((V + T(1.26)) * T(-1.0 / 7.44)));
         c[CV_OI] = lgs((V + T(43.1)) * T(1.0 / 5.3));
-        c[CV_OIA] = ex(-dt * T(3) * (aoi + boi));
+        c[CV_OIA] = U::facm(T(3), (aoi + boi), dt);
         T aui = rcp(T(21) + ex((V - T(185)) * T(-1.0 / 28.0)));
         T bui = ex((V - T(158)) * T(1.0 / 16.0));
         c[CV_UI] = lgs((V - T(99.45)) * T(1.0 / 27.48));
-        c[CV_UIA] = ex(-dt * T(3) * (aui + bui));
+        c[CV_UIA] = U::facm(T(3), (aui + bui), dt);
     }
     // rapid and slow delayed rectifier gates
     {
         T axr = T(0.0015) * bern(-(V + T(14.1)) * T(0.2));
         T bxr = T(7.3898e-5 * 5.1237) * bern((V - T(3.3328)) * T(1.0 / 5.1237));
         c[CV_XR] = lgs((V + T(14.1)) * T(-1.0 / 6.5));
-        c[CV_XRA] = ex(-dt * (axr + bxr));
+        c[CV_XRA] = U::fac((axr + bxr), dt);
         T axs = T(4e-5 * 17.0) * bern((V - T(19.9)) * T(-1.0 / 17.0));
         T bxs = T(3.5e-5 * 9.0) * bern((V - T(19.9)) * T(1.0 / 9.0));
         c[CV_XS] = rcp(sq(T(1) + ex((V - T(19.9)) * T(-1.0 / 12.7))));
-        c[CV_XSA] = ex(-dt * T(2) * (axs + bxs));
+        c[CV_XSA] = U::facm(T(2), (axs + bxs), dt);
     }
     // L-type calcium gates d, f
     {
@@ -388,11 +423,11 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
         // 1/tau_d = 0.035 (V+10)(1 + e^{-zd}) / (1 - e^{-zd}) = 0.035*6.24 bern(-zd)(1 + e^{-zd})
         T kd = T(0.035 * 6.24) * bern(-zd) * (T(1) + ex(-zd));
         c[CV_D] = lgs((V + T(10)) * T(-1.0 / 8.0));
-        c[CV_DA] = ex(-dt * kd);
+        c[CV_DA] = U::fac(kd, dt);
         T vv = V + T(10);
         T kf = (T(0.0197) * ex(T(-0.0337 * 0.0337) * vv * vv) + T(0.02)) * T(1.0 / 9.0);
         c[CV_F] = lgs((V + T(28)) * T(1.0 / 6.9));
-        c[CV_FA] = ex(-dt * kf);
+        c[CV_FA] = U::fac(kf, dt);
     }
     // release gate w
     {
@@ -400,7 +435,7 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
         // 1/tau_w = (1 + 0.3 e^{-zw}) (V - 7.9) / (6 (1 - e^{-zw})) = 5 bern(-zw)(1 + 0.3 e^{-zw}) / 6
         T kw = T(5.0 / 6.0) * bern(-zw) * (T(1) + T(0.3) * ex(-zw));
         c[CV_W] = T(1) - lgs((V - T(40)) * T(-1.0 / 17.0));
-        c[CV_WA] = ex(-dt * kw);
+        c[CV_WA] = U::fac(kw, dt);
     }
     // voltage factors of currents
     {
@@ -419,7 +454,7 @@ __device__ __forceinline__ void crn_vterms(T V, T dt, T *c)
 }
 
 // Everything that is not univariate in V, given the voltage-only terms c.
-template <typename T>
+template <class U, typename T>
 __device__ __forceinline__ T crn_rest(T V, T *g, T dt, const T *c)
 {
     using namespace crn;
@@ -435,31 +470,31 @@ __device__ __forceinline__ T crn_rest(T V, T *g, T dt, const T *c)
     // currents from the state at step n, then the Rush-Larsen gate updates
     T m = g[5], h = g[6], j = g[7];
     const T INa = T(7.8) * m * m * m * h * j * (V - ENa);
-    g[5] = c[CV_M] + (m - c[CV_M]) * c[CV_MA];
-    g[6] = c[CV_H] + (h - c[CV_H]) * c[CV_HA];
-    g[7] = c[CV_J] + (j - c[CV_J]) * c[CV_JA];
+    g[5] = U::rlf(m, c[CV_M], c[CV_MA]);
+    g[6] = U::rlf(h, c[CV_H], c[CV_HA]);
+    g[7] = U::rlf(j, c[CV_J], c[CV_JA]);
 
     T oa = g[8], oi = g[9], ua = g[10], ui = g[11];
     const T Ito = T(0.1652) * oa * oa * oa * oi * dK;
     const T IKur = c[CV_GKUR] * ua * ua * ua * ui * dK;
-    g[8] = c[CV_OA] + (oa - c[CV_OA]) * c[CV_OAA];
-    g[9] = c[CV_OI] + (oi - c[CV_OI]) * c[CV_OIA];
-    g[10] = c[CV_UA] + (ua - c[CV_UA]) * c[CV_UAA];
-    g[11] = c[CV_UI] + (ui - c[CV_UI]) * c[CV_UIA];
+    g[8] = U::rlf(oa, c[CV_OA], c[CV_OAA]);
+    g[9] = U::rlf(oi, c[CV_OI], c[CV_OIA]);
+    g[10] = U::rlf(ua, c[CV_UA], c[CV_UAA]);
+    g[11] = U::rlf(ui, c[CV_UI], c[CV_UIA]);
 
     T xr = g[12], xs = g[13];
     const T IKr = T(0.029411765) * xr * dK * c[CV_KR];
     const T IKs = T(0.12941176) * xs * xs * dK;
-    g[12] = c[CV_XR] + (xr - c[CV_XR]) * c[CV_XRA];
-    g[13] = c[CV_XS] + (xs - c[CV_XS]) * c[CV_XSA];
+    g[12] = U::rlf(xr, c[CV_XR], c[CV_XRA]);
+    g[13] = U::rlf(xs, c[CV_XS], c[CV_XSA]);
 
     const T IK1 = T(0.09) * dK * c[CV_K1];
 
     T d = g[14], f = g[15], fCa = g[16];
     const T ICaL = T(0.12375) * d * f * fCa * (V - T(65));
-    g[14] = c[CV_D] + (d - c[CV_D]) * c[CV_DA];
-    g[15] = c[CV_F] + (f - c[CV_F]) * c[CV_FA];
-    g[16] = rl_rate(fCa, rcp(T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
+    g[14] = U::rlf(d, c[CV_D], c[CV_DA]);
+    g[15] = U::rlf(f, c[CV_F], c[CV_FA]);
+    g[16] = U::rl(fCa, rcp(T(1) + Cai * T(1.0 / 0.00035)), T(0.5), dt);
 
     // pumps, exchanger and background currents
     const T rNa = dv(T(10), Nai);
@@ -479,27 +514,27 @@ __device__ __forceinline__ T crn_rest(T V, T *g, T dt, const T *c)
         // release trigger from SR release and sarcolemmal Ca entry (currents in pA)
         T Fn = T(1e-12 * kVrel) * Irel - T(5e-13 / kF * kCm) * (T(0.5) * ICaL - T(0.2) * INaCa);
         T s1 = lgs(-(Fn - T(3.4175e-13)) * T(1.0 / 13.67e-16));
-        g[17] = rl_rate(u, s1, T(1.0 / 8.0), dt);
-        g[18] = rl_rate(v, T(1) - lgs(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16)),
+        g[17] = U::rl(u, s1, T(1.0 / 8.0), dt);
+        g[18] = U::rl(v, T(1) - lgs(-(Fn - T(6.835e-14)) * T(1.0 / 13.67e-16)),
                         rcp(T(1.91) + T(2.09) * s1), dt);
-        g[19] = c[CV_W] + (w - c[CV_W]) * c[CV_WA];
+        g[19] = U::rlf(w, c[CV_W], c[CV_WA]);
     }
 
     // concentrations (forward Euler); current-to-flux factor Cm / (F Vi)
     const T c2f = T(kCm / (kF * kVi));
-    g[0] = Nai + dt * c2f * (T(-3) * (INaK + INaCa) - IbNa - INa);
-    g[1] = Ki + dt * c2f * (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs);
+    g[0] = U::eus(Nai, c2f, (T(-3) * (INaK + INaCa) - IbNa - INa), dt);
+    g[1] = U::eus(Ki, c2f, (T(2) * INaK - IK1 - Ito - IKur - IKr - IKs), dt);
     {
         T ct = Cai + T(0.0005), cc = Cai + T(0.00238);
         T bt = T(0.07 * 0.0005) * rcp(ct * ct);
         T bc = T(0.05 * 0.00238) * rcp(cc * cc);
         T src = T(0.5) * c2f * (T(2) * INaCa - IpCa - ICaL - IbCa)
                 + (T(kVup) * (Ileak - Iup) + T(kVrel) * Irel) * T(1.0 / kVi);
-        g[2] = Cai + dt * src * rcp(T(1) + bt + bc);
-        g[3] = Caup + dt * (Iup - Ileak - Itr * T(kVrel / kVup));
+        g[2] = U::eus(Cai, src, rcp(T(1) + bt + bc), dt);
+        g[3] = U::eu(Caup, (Iup - Ileak - Itr * T(kVrel / kVup)), dt);
         T cq = Carel + T(0.8);
         T bq = T(10.0 * 0.8) * rcp(cq * cq);
-        g[4] = Carel + dt * (Itr - Irel) * rcp(T(1) + bq);
+        g[4] = U::eus(Carel, (Itr - Irel), rcp(T(1) + bq), dt);
     }
 
     return -(INa + IK1 + Ito + IKur + IKr + IKs + IbNa + IbCa + INaK + IpCa + INaCa + ICaL);
@@ -508,11 +543,12 @@ __device__ __forceinline__ T crn_rest(T V, T *g, T dt, const T *c)
 template <typename T>
 struct Crn {
     static constexpr int NV = 21, GATE0 = 6;  // variables GATE0.. are gates in [0, 1]
+    template <class U = Step>
     __device__ static T advance(const T *, T V, T *g, T dt, const float *)
     {
         T c[CRN_V];
-        crn_vterms(V, dt, c);
-        return crn_rest(V, g, dt, c);
+        crn_vterms<U>(V, dt, c);
+        return crn_rest<U>(V, g, dt, c);
     }
 };
 
@@ -542,11 +578,14 @@ __device__ __forceinline__ void crn_lookup(const float *tab, float V, float *c)
 // CRN with tabulated voltage-only terms (FP32 only).
 struct CrnTab {
     static constexpr int NV = 21, GATE0 = 6;
+    // the table holds the Step forms (e^{-dt/tau}): one scheme step only
+    template <class U = Step>
     __device__ static float advance(const float *, float V, float *g, float dt, const float *tab)
     {
+        static_assert(!U::kRate, "tabulated terms are one-step factors");
         float c[CRN_V];
         crn_lookup(tab, V, c);
-        return crn_rest(V, g, dt, c);
+        return crn_rest<Step>(V, g, dt, c);
     }
 };
 

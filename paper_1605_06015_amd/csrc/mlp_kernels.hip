@@ -369,17 +369,21 @@ __global__ __launch_bounds__(256) void k_fwd_bwd(MlpDev d, const __bf16 *Xb, con
     if (l == 0) pp[kPart - 1] = lsum;
 }
 
-// Weight gradients dW = sum_b dZ[:, b] A[:, b]^T as MFMA GEMMs over the batch:
-// one 16 x 16 output tile per wave, deterministic (no atomics).  Tiles
-// 0..15: dW1 (8 x 2); 16..79: dW2 (8 x 8); 80..95: dW3 (2 x 8).
-__global__ __launch_bounds__(256) void k_wgrad(MlpDev d, int64_t Bp, const __bf16 *Xf,
-                                               const __bf16 *H1, const __bf16 *H2,
-                                               const __bf16 *DZ1, const __bf16 *DZ2,
-                                               const __bf16 *DO, float *grad)
+// Weight gradients dW = sum_b dZ[:, b] A[:, b]^T as MFMA GEMMs over the batch.
+// One workgroup per 16 x 16 output tile (tiles 0..15: dW1 (8 x 2); 16..79: dW2
+// (8 x 8); 80..95: dW3 (2 x 8)); its kWgWaves waves split the batch, wave w
+// taking the 32-sample blocks w, w + kWgWaves, ...; the wave partials are summed
+// through LDS in wave order.  Deterministic (no atomics), and 96 x kWgWaves waves
+// keep the MFMA pipes of many CUs busy where one wave per tile left them idle.
+constexpr int kWgWaves = 16;
+__global__ __launch_bounds__(64 * kWgWaves) void k_wgrad(MlpDev d, int64_t Bp, const __bf16 *Xf,
+                                                         const __bf16 *H1, const __bf16 *H2,
+                                                         const __bf16 *DZ1, const __bf16 *DZ2,
+                                                         const __bf16 *DO, float *grad)
 {
-    const int w = blockIdx.x * 4 + threadIdx.x / 64;
-    if (w >= 96) return;
-    const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+    __shared__ f4v part[kWgWaves][64];
+    const int w = blockIdx.x;                   // output tile, 0..95 (grid = 96)
+    const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
     const POff o = poff(d.nin, d.nout);
     const __bf16 *Am, *Bm;
     int mt, nt, rows, cols, base, ld;
@@ -389,11 +393,16 @@ __global__ __launch_bounds__(256) void k_wgrad(MlpDev d, int64_t Bp, const __bf1
     f4v acc = {0.f, 0.f, 0.f, 0.f};
     const __bf16 *ap = Am + (int64_t)(16 * mt + j) * Bp + 8 * g;
     const __bf16 *bp = Bm + (int64_t)(16 * nt + j) * Bp + 8 * g;
-    for (int64_t k = 0; k < Bp; k += 32) acc = mfma(ld8(ap + k), ld8(bp + k), acc);
+    for (int64_t k = 32 * wv; k < Bp; k += 32 * kWgWaves) acc = mfma(ld8(ap + k), ld8(bp + k), acc);
+    part[wv][l] = acc;
+    __syncthreads();
+    if (wv != 0) return;
+    f4v s = part[0][l];
+    for (int i = 1; i < kWgWaves; i++) s += part[i][l];
 #pragma unroll
     for (int i = 0; i < 4; i++) {
         const int r = 16 * mt + 4 * g + i, c = 16 * nt + j;
-        if (r < rows && c < cols) grad[base + r * ld + c] = acc[i];
+        if (r < rows && c < cols) grad[base + r * ld + c] = s[i];
     }
 }
 
@@ -517,7 +526,7 @@ hipError_t mlp_grad(const MlpDev &d, const MlpScratch &w, int mode, const float 
     hipLaunchKernelGGL(k_fwd_bwd, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, s, d, w.xb, w.tt, B,
                        Bp, inv, w.xf, w.h1, w.h2, w.dz1, w.dz2, w.dO, w.part);
     if ((err = hipGetLastError()) != hipSuccess) return err;
-    hipLaunchKernelGGL(k_wgrad, dim3(24), dim3(256), 0, s, d, Bp, w.xf, w.h1, w.h2, w.dz1, w.dz2, w.dO,
+    hipLaunchKernelGGL(k_wgrad, dim3(96), dim3(64 * kWgWaves), 0, s, d, Bp, w.xf, w.h1, w.h2, w.dz1, w.dz2, w.dO,
                        grad);
     if ((err = hipGetLastError()) != hipSuccess) return err;
     hipLaunchKernelGGL(k_reduce_part, dim3(kPart), dim3(256), 0, s, d, w.part, tiles, grad, loss,

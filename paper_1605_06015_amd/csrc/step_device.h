@@ -119,9 +119,58 @@ __device__ __forceinline__ void voxel_of(const StepArgs<T> &a, int t, int &idx, 
     bits |= (py & pz) << 14 | (my & mz) << 15 | (py & mz) << 16 | (my & pz) << 17;
 }
 
+// Classical fourth-order Runge-Kutta step of one voxel's kinetics (the `rk4` solver of
+// "Kinetics solvers") for dV/dt = -I_ion(V, g) + F, dg/dt = G(V, g), with the forcing F
+// (stimulus, plus the Laplacian in the additive scheme) held at its step-n value
+// through the four stages, as the Euler update holds it: k_i are the right-hand sides
+// at y0, y0 + dt/2 k1, y0 + dt/2 k2, y0 + dt k3, and y+ = y0 + dt/6 (k1 + 2k2 + 2k3 + k4).
+// Every variable, gates included (dg/dt = (g_inf - g)/tau), takes the same stages.
+// g holds g0 on entry and g+ on return; returns V+.
+template <typename T, class M>
+__device__ __forceinline__ T rk4_voxel(const StepArgs<T> &a, T V0, T *g, T F)
+{
+    constexpr int NG = M::NV > 1 ? M::NV - 1 : 1;
+    const T dt = a.dt, hdt = T(0.5) * a.dt;
+    T y0[NG], k[NG], acc[NG];
+#pragma unroll
+    for (int i = 0; i < M::NV - 1; i++) y0[i] = k[i] = g[i];
+    // k1
+    T kV = M::template advance<kin::Rate>(a.prm, V0, k, dt, nullptr) + F;
+    T accV = kV;
+#pragma unroll
+    for (int i = 0; i < M::NV - 1; i++) {
+        acc[i] = k[i];
+        k[i] = y0[i] + hdt * k[i];
+    }
+    // k2
+    kV = M::template advance<kin::Rate>(a.prm, V0 + hdt * kV, k, dt, nullptr) + F;
+    accV += T(2) * kV;
+#pragma unroll
+    for (int i = 0; i < M::NV - 1; i++) {
+        acc[i] += T(2) * k[i];
+        k[i] = y0[i] + hdt * k[i];
+    }
+    // k3
+    kV = M::template advance<kin::Rate>(a.prm, V0 + hdt * kV, k, dt, nullptr) + F;
+    accV += T(2) * kV;
+#pragma unroll
+    for (int i = 0; i < M::NV - 1; i++) {
+        acc[i] += T(2) * k[i];
+        k[i] = y0[i] + dt * k[i];
+    }
+    // k4
+    kV = M::template advance<kin::Rate>(a.prm, V0 + dt * kV, k, dt, nullptr) + F;
+    accV += kV;
+    const T w = dt * T(1.0 / 6.0);
+#pragma unroll
+    for (int i = 0; i < M::NV - 1; i++) g[i] = y0[i] + w * (acc[i] + k[i]);
+    return V0 + w * accV;
+}
+
 // Everything after the Laplacian for one voxel: stimulus, kinetics, stores and
-// the recorder.
-template <typename T, class M, bool NT = false>
+// the recorder.  RK4: the kinetics take the fourth-order Runge-Kutta step instead of
+// forward Euler / Rush-Larsen.
+template <typename T, class M, bool NT = false, bool RK4 = false>
 __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int idx, T Vp, T LV)
 {
     const T Is = stim_current(a, t);
@@ -136,8 +185,13 @@ __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int id
         else g[i] = a.st[i * a.pitch + t];
     }
     const T Vin = a.split ? Vp + a.dt * LV : Vp;
-    const T r = M::advance(a.prm, Vin, g, a.dt, a.tab);
-    const T Vn = a.split ? Vin + a.dt * (r + Is) : Vp + a.dt * (r + Is + LV);
+    T Vn;
+    if constexpr (RK4) {
+        Vn = rk4_voxel<T, M>(a, Vin, g, a.split ? Is : Is + LV);
+    } else {
+        const T r = M::advance(a.prm, Vin, g, a.dt, a.tab);
+        Vn = a.split ? Vin + a.dt * (r + Is) : Vp + a.dt * (r + Is + LV);
+    }
 #pragma unroll
     for (int i = 0; i < M::NV - 1; i++) a.st[i * a.pitch + t] = g[i];
     if constexpr (NT)

@@ -49,7 +49,7 @@ __device__ __forceinline__ int workgroup_tile(const StepArgs<T> &a)
     return full * kXcd + x * rem + (i - full);
 }
 
-template <typename T, class M, bool ANISO, bool NT>
+template <typename T, class M, bool ANISO, bool NT, bool RK4 = false>
 __global__ __launch_bounds__(NT ? kStreamBlock : kBlock) void k_step(const StepArgs<T> a)
 {
     const int lb = workgroup_tile<NT, 1>(a);
@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT ? kStreamBlock : kBlock) void k_step(const StepA
     voxel_of(a, t, idx, bits);         // dense boxes keep no index / bit arrays
     const T Vp = a.Vin[idx];
     const T LV = laplacian<T, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-    update_voxel<T, M, NT>(a, t, idx, Vp, LV);
+    update_voxel<T, M, NT, RK4>(a, t, idx, Vp, LV);
 }
 
 // Dense-box path (every voxel is tissue): a workgroup owns a 64 x 4 column tile
@@ -237,8 +237,21 @@ static void launch_kernel(int aniso, const StepArgs<T> &a, hipStream_t s)
 template <typename T, class M>
 static hipError_t launch_m(int aniso, const StepArgs<T> &a, hipStream_t s)
 {
-    if (a.nt) launch_kernel<T, M, true>(aniso, a, s);
-    else launch_kernel<T, M, false>(aniso, a, s);
+    constexpr bool kTab = std::is_same<M, kin::CrnTab>::value;   // one-step factors only
+    if (a.rk4) {
+        // the RK4 integrator: tissue-list kernel, cached accesses (make_args)
+        if constexpr (!kTab) {
+            const dim3 grid(a.per_xcd * kXcd), block(kBlock);
+            if (aniso) hipLaunchKernelGGL((k_step<T, M, true, false, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_step<T, M, false, false, true>), grid, block, 0, s, a);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    } else if (a.nt) {
+        launch_kernel<T, M, true>(aniso, a, s);
+    } else {
+        launch_kernel<T, M, false>(aniso, a, s);
+    }
     return hipGetLastError();
 }
 
@@ -252,7 +265,7 @@ hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s
     case 3: return launch_m<T, kin::Fhn<T>>(aniso, a, s);
     case 4:
         if constexpr (std::is_same<T, float>::value)
-            if (a.tab) return launch_m<float, kin::CrnTab>(aniso, a, s);
+            if (a.tab && !a.rk4) return launch_m<float, kin::CrnTab>(aniso, a, s);
         return launch_m<T, kin::Crn<T>>(aniso, a, s);
     case 5: return launch_m<T, kin::Fk4<T>>(aniso, a, s);
     case 6: return launch_m<T, kin::Tp06<T>>(aniso, a, s);

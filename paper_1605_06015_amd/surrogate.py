@@ -109,3 +109,73 @@ def attach(grid, trained, margin=0.02, dv_cap=None):
     lo, hi, dv = accepted_box(trained.stats, margin, dv_cap, trained.mlp.nin)
     grid.surrogate(trained.mlp, lo, hi, dv)
     return lo, hi, dv
+
+
+def run_pair(trained, model, geo_seed, nx=96, ny=96, nz=48, t_ms=500.0, v_his=(), stream=None):
+    """The plain FP32 run and one surrogate run per acceptance threshold v_hi on a cup of
+    the workload's shape (geometry seed geo_seed), t_ms long.  Returns the plain run's
+    activation times and seconds and, per threshold, a dict of share, activation-time and
+    APD90 errors against the plain run, and seconds."""
+    import torch
+    mid, nv, c, geo, _, amp, dur = _model_setup(model)
+    g = geo(nx, ny, nz, seed=geo_seed, active=c["active"], h=c["h"])
+    m = g["mask"] == 1
+    nsteps = int(round(t_ms / c["dt"]))
+
+    def one(v_hi):
+        grid = B.Grid(g["mask"], c["h"], g["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
+        grid.model(mid, [], c["dt"])
+        for v in range(nv):
+            grid.set(v, g["state"][v])
+        grid.stimulus(g["stim"], amp, 0.0, dur)
+        grid.record(-40.0)
+        grid.nan_check(0)
+        if v_hi is not None:
+            lo, hi, dv = accepted_box(trained.stats, nvar=nv)
+            hi[0] = v_hi
+            grid.surrogate(trained.mlp, lo, hi, dv)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        s = stream or torch.cuda.current_stream()
+        torch.cuda.synchronize()
+        ev[0].record(s)
+        grid.step(nsteps)
+        ev[1].record(s)
+        torch.cuda.synchronize()
+        sec = ev[0].elapsed_time(ev[1]) / 1e3
+        out = dict(at=grid.read(B.BBX_READ_ACT_TIME)[m], apd=grid.read(B.BBX_READ_APD90)[m], sec=sec,
+                   fb=int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]) if v_hi is not None else 0,
+                   nact=grid.nact)
+        grid.close()
+        return out
+
+    plain = one(None)
+    res = {}
+    for v_hi in v_his:
+        q = one(v_hi)
+        both = np.isfinite(plain["at"]) & np.isfinite(q["at"])
+        bapd = np.isfinite(plain["apd"]) & np.isfinite(q["apd"])
+        dat = np.abs(plain["at"][both] - q["at"][both])
+        dapd = np.abs(plain["apd"][bapd] - q["apd"][bapd])
+        res[float(v_hi)] = dict(
+            share=1.0 - q["fb"] / (q["nact"] * nsteps),
+            same_activated=bool(np.array_equal(np.isfinite(plain["at"]), np.isfinite(q["at"]))),
+            at_max=float(dat.max()) if dat.size else None, at_mean=float(dat.mean()) if dat.size else None,
+            apd_max=float(dapd.max()) if dapd.size else None,
+            apd_mean=float(dapd.mean()) if dapd.size else None,
+            sec=q["sec"], speed_vs_plain=plain["sec"] / q["sec"])
+    return plain, res, c["dt"]
+
+
+def select_threshold(trained, model, geo_seed=11, margin=0.5, offsets=(-0.2, -0.1, -0.05, -0.02,
+                     -0.01, 0.0, 0.01), stream=None):
+    """Acceptance threshold v_hi chosen on a held-out cup (geometry seed geo_seed, not the
+    benchmark's): among rest + offsets (mV), the one with the largest surrogate share whose
+    activation times stay within margin * dt of the plain run's on every voxel, with the
+    same activated set.  Returns (v_hi or None, the sweep)."""
+    rest = _model_setup(model)[4][0]
+    cands = [round(rest + o, 4) for o in offsets]
+    _, sweep, dt = run_pair(trained, model, geo_seed, v_his=cands, stream=stream)
+    ok = [v for v in cands if sweep[v]["same_activated"] and sweep[v]["at_max"] is not None
+          and sweep[v]["at_max"] <= margin * dt]
+    best = max(ok, key=lambda v: (sweep[v]["share"], -v)) if ok else None
+    return best, sweep

@@ -313,25 +313,40 @@ def region_near_slabs(mask, h, point_mm, radius_mm):
 
 
 # The 3D TP06 workload: 512x512x384 biventricular-like double shell at 25% active,
-# h 0.2 mm, dt 0.02 ms, D_par 0.3 / D_perp 0.03 mm^2/ms, 1 s.  Scroll-wave
-# initiation: S1 within 3 mm of the left shell's apex at t = 0; S2 on the tissue of
-# the half y < Ly/2 above mid-height at t = 320 ms (after the S1 wave back has passed
-# through most of the walls).  Eight pseudo-ECG electrodes 20 mm outside the box.
+# h 0.2 mm, dt 0.02 ms, D_par 0.3 / D_perp 0.03 mm^2/ms, 1 s.  Scroll-wave initiation
+# by a cross-field S1-S2 protocol: S1 on the tissue within the first s1_strip of the box's
+# y extent (counted from the tissue's smallest y) at t = 0, a wave that crosses the shells
+# along y; S2 on the upper half of the box (z >= nz/2) at t = s2_t, when the S1 wave back
+# has passed about half of the y extent, so that S2 excites only the recovered side and
+# its front gets a free end at the refractory side.  Eight pseudo-ECG electrodes 20 mm
+# outside the box.  (Measured on the full-size shell: S1 alone leaves the tissue at rest
+# by 420 ms; with S2 at 346, 361 or 376 ms 57-87% of the tissue is still depolarised at
+# every 100 ms sample up to 1 s.)
 TP06_3D = dict(nx=512, ny=512, nz=384, h=0.2, dt=0.02, Dpar=0.3, Dperp=0.03, active=0.25,
-               seed=5, theta=-40.0, s1_amp=60.0, s1_ms=2.0, s1_radius=3.0, s2_amp=60.0,
-               s2_t=320.0, s2_ms=2.0, t_end=1000.0, ecg_every_ms=1.0)
+               seed=5, theta=-40.0, s1_amp=60.0, s1_ms=2.0, s1_strip=0.1, s2_amp=60.0,
+               s2_t=360.0, s2_ms=2.0, t_end=1000.0, ecg_every_ms=1.0)
+# The same protocol on a down-scaled shell (128x128x96 at the same h: 25.6 x 25.6 x 19.2 mm)
+# for parity runs against the oracle.  Its S1 wave crosses the shell in 33 ms, so S2 comes
+# earlier (310 ms: part of the upper half has recovered), and too little tissue remains to
+# sustain re-entry: the S2 wave dies out by about 500 ms, and the run ends at 600 ms.
+TP06_3D_SMALL = dict(TP06_3D, nx=128, ny=128, nz=96, s2_t=310.0, t_end=600.0)
 
 
-def tp06_biv(nx=512, ny=512, nz=384, h=0.2, seed=5, active=0.25, s1_radius=3.0,
+def tp06_biv(nx=512, ny=512, nz=384, h=0.2, seed=5, active=0.25, s1_strip=0.1,
              with_fibres=True):
-    """Geometry, stimulus regions and electrodes of the 3D TP06 workload."""
+    """Geometry, stimulus regions (S1 y-strip, S2 upper half) and electrodes of the 3D
+    TP06 workload."""
     g = double_shell(nx, ny, nz, h, active, seed, with_fibres=with_fibres)
     mask = g["mask"]
-    s1 = region_near_slabs(mask, h, g["apex"], s1_radius)
+    ys = np.nonzero(mask.any(axis=(0, 2)))[0]
+    y0 = int(ys.min())
+    w = max(1, int(round(s1_strip * ny)))
+    s1 = np.zeros_like(mask)
+    s1[:, y0:y0 + w, :] = mask[:, y0:y0 + w, :]
     if s1.sum() == 0:
         raise RuntimeError("tp06_biv: empty S1 region")
     s2 = np.zeros_like(mask)
-    s2[nz // 2:, : ny // 2, :] = mask[nz // 2:, : ny // 2, :]
+    s2[nz // 2:] = mask[nz // 2:]
     L = np.array([nx, ny, nz]) * h
     c = 0.5 * L
     d = 20.0

@@ -33,11 +33,12 @@ class Problem:
     state: np.ndarray = None          # (nvar, nz, ny, nx)
     stims: list = field(default_factory=list)   # (region, amp, t0_ms, dur_ms, period_ms, count)
     theta: float = None
+    integrator: int = 0               # O.INTEGRATOR_EULER_RL or O.INTEGRATOR_RK4
 
 
 def run_oracle(p: Problem, nsteps: int, nthreads: int = 0):
     s = O.Sim(p.mask, p.h, p.fibre, p.Dpar, p.Dperp, p.model, list(p.params), p.dt,
-              scheme=p.scheme, nthreads=nthreads)
+              scheme=p.scheme, nthreads=nthreads, integrator=p.integrator)
     s.state[:] = p.state
     for (reg, amp, t0, dur, per, cnt) in p.stims:
         s.stimuli.append(O.Stimulus(reg, amp, round_half_away(t0 / p.dt),
@@ -54,6 +55,8 @@ def make_gpu(p: Problem, precision: int, stream=None):
     from paper_1605_06015_amd import bbx as B
     g = B.Grid(p.mask, p.h, p.fibre, p.Dpar, p.Dperp, precision, stream)
     g.model(p.model, p.params, p.dt, p.scheme)
+    if p.integrator:
+        g.integrator(p.integrator)
     for v in range(p.state.shape[0]):
         g.set(v, p.state[v])
     for (reg, amp, t0, dur, per, cnt) in p.stims:

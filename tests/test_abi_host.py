@@ -117,3 +117,37 @@ def test_ensemble_validation_before_device(bbx):
     v = C.c_int64()
     assert lib.bbx_ensemble_info(None, 0, C.byref(v)) == E
     lib.bbx_ensemble_destroy(None)
+
+
+def test_slab_bounds_tissue_balanced(bbx):
+    """bbx_slab_bounds (host only): strictly increasing plane boundaries from 0 to nz,
+    each at the plane boundary nearest to k/nslab of the tissue (brute force over all
+    boundaries), on an uneven mask."""
+    from paper_1605_06015_amd import workloads as WL
+    g = WL.cup_shell(40, 36, 20, 0.25, 0.35, seed=2)
+    mask = g["mask"]
+    per_plane = mask.reshape(mask.shape[0], -1).sum(axis=1)
+    cum = np.concatenate([[0], np.cumsum(per_plane)])
+    for nslab in (1, 2, 3, 5, 8, 20):
+        zb = bbx.bbx_slab_bounds(mask, nslab)
+        assert zb[0] == 0 and zb[-1] == mask.shape[0]
+        assert np.all(np.diff(zb) >= 1)
+        for k in range(1, nslab):
+            target = cum[-1] * k / nslab
+            lo, hi = zb[k - 1] + 1, mask.shape[0] - (nslab - k)
+            best = min(range(lo, hi + 1), key=lambda z: (abs(cum[z] - target), z))
+            assert abs(cum[zb[k]] - target) <= abs(cum[best] - target) + 1e-9, (nslab, k)
+    E = bbx.BBX_EINVAL
+    assert _err(bbx.bbx_slab_bounds, mask, 0) == E
+    assert _err(bbx.bbx_slab_bounds, mask, mask.shape[0] + 1) == E
+
+
+def test_slab_validation_before_device(bbx):
+    m = np.ones((6, 3, 4), np.uint8)
+    E = bbx.BBX_EINVAL
+    assert _err(bbx.bbx_slab_create, m, 3, 3, 0.1, None, 1, 1, bbx.BBX_FP32) == E
+    assert _err(bbx.bbx_slab_create, m, -1, 3, 0.1, None, 1, 1, bbx.BBX_FP32) == E
+    assert _err(bbx.bbx_slab_create, m, 2, 7, 0.1, None, 1, 1, bbx.BBX_FP32) == E
+    lib = bbx._lib
+    assert lib.bbx_halo_pack(None, 0, None, 0) == E
+    assert lib.bbx_halo_unpack(None, 1, None, 0) == E

@@ -20,6 +20,12 @@ from paper_1605_06015_amd import workloads as WL
 pytestmark = pytest.mark.gpu
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crn_cup128_at_apd.csv")
+TRACES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "crn_cup128_v_traces.npz")
+
+
+def load_traces():
+    d = np.load(TRACES)
+    return d["idx"], d["t_ms"], d["V"].astype(np.float64)
 
 
 def load_golden():
@@ -27,7 +33,10 @@ def load_golden():
     return d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
 
 
-def run_headline(prec):
+def run_headline(prec, traces=None):
+    """The workload for 500 ms; with traces = (box indices, every), also V at those
+    voxels after every `every` steps (read on the device, gathered there)."""
+    import torch
     from paper_1605_06015_amd import bbx as B
     c = WL.CRN_3D
     g = WL.crn_cup(c["nx"], c["ny"], c["nz"], seed=c["seed"], active=c["active"], h=c["h"])
@@ -38,17 +47,38 @@ def run_headline(prec):
     grid.stimulus(g["stim"], c["stim_amp"], 0.0, c["stim_ms"])
     grid.record(c["theta"])
     n = int(round(c["t_end"] / c["dt"]))
-    for _ in range(10):
-        grid.step(n // 10)
+    V = []
+    if traces is None:
+        for _ in range(10):
+            grid.step(n // 10)
+    else:
+        idx, every = traces
+        buf = torch.empty(g["mask"].size, dtype=torch.float64, device="cuda")
+        sel = torch.from_numpy(idx).cuda()
+        for _ in range(n // every):
+            grid.step(every)
+            B.bbx_readout(grid.handle, B.BBX_READ_VAR, 0, None, buf.data_ptr(), buf.numel() * 8, 1)
+            V.append(buf[sel].cpu().numpy())
     assert grid.read(B.BBX_READ_STEP) == n
     return (grid.read(B.BBX_READ_ACT_TIME).ravel(), grid.read(B.BBX_READ_APD90).ravel(),
-            g["mask"].ravel())
+            g["mask"].ravel(), np.array(V))
 
 
 @pytest.mark.parametrize("prec", [1, 0])
 def test_crn_headline_500ms_against_oracle_maps(prec):
+    """Activation times and APD90 at 4,000 voxels, and V at the same voxels every 1 ms
+    (the oracle's V stored as float32: 1e-5 mV resolution).  FP64: |dV| <= 1e-4 mV;
+    FP32: |dV| <= 0.5 mV at every sample, the headline metric's voltage bar."""
     idx, at_o, apd_o = load_golden()
-    at, apd, mask = run_headline(prec)
+    tidx, t_ms, V_o = load_traces()
+    every = int(round((t_ms[1] - t_ms[0]) / WL.CRN_3D["dt"]))
+    at, apd, mask, V_g = run_headline(prec, (tidx, every))
+    assert V_g.shape == V_o.shape
+    dV = np.abs(V_g - V_o)
+    worst = np.unravel_index(np.argmax(dV), dV.shape)
+    print(f"prec {prec}: max |dV| over {dV.size} samples {dV.max():.3g} mV at t = "
+          f"{t_ms[worst[0]]:.0f} ms (V_oracle {V_o[worst]:.2f} mV), mean {dV.mean():.3g} mV")
+    assert dV.max() <= (1e-4 if prec == 1 else 0.5), dV.max()
     assert np.all(mask[idx] == 1)
     assert np.isfinite(at_o).mean() > 0.9                  # the wave covers the cup
     assert np.isfinite(apd_o).mean() > 0.9                 # and it repolarises

@@ -223,21 +223,37 @@ def test_training_pipeline_and_gain(env):
     first = float(np.mean(tr.loss[:5]))
     print("training loss first", first, "final", final)
     assert final < 0.02 and final < first / 20
+    # held-out pairs (another seed), normalised with the trained network's normalisation:
+    # the loss of the trained network, the untrained one (same normalisation) and the
+    # no-network predictor of the mean increment (normalised target 0: loss = mean T^2)
+    Sv, S1v = SU.generate_pairs(nx=40, ny=40, nz=20, runs=1, t_ms=200.0, per_sample=512, seed=9)
+    norm = torch.from_numpy(tr.mlp.get_norm()).cuda()
+    untrained.set_norm(tr.mlp.get_norm())
+    X = ((Sv - norm[0, :21]) * norm[1, :21]).contiguous()
+    sig = norm[3, :21]
+    T = torch.where(sig > 0, ((S1v - Sv) - norm[2, :21]) / torch.where(sig > 0, sig, 1.0),
+                    torch.zeros_like(Sv)).contiguous()
+    n = min(X.shape[0], 65536)
+    loss_tr, _ = tr.mlp.grad(X[:n].contiguous(), T[:n].contiguous(), with_host=False)
+    loss_un, _ = untrained.grad(X[:n].contiguous(), T[:n].contiguous(), with_host=False)
+    loss_mean = float((T[:n] ** 2).mean())
+    print("held-out loss: trained", loss_tr, "untrained", loss_un, "mean-increment predictor", loss_mean)
+    assert loss_tr < 0.05 * loss_un and loss_tr < 0.05 * loss_mean
     # the surrogate on a fresh cup, 60 ms
     c = WL.CRN_3D
     g0 = WL.crn_cup(40, 40, 20, seed=c["seed"])
     runs = {}
-    for name in ("plain", "surrogate"):
+    for name in ("plain", "surrogate", "untrained"):
         g = B.Grid(g0["mask"], c["h"], g0["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32)
         g.model(B.BBX_MODEL_CRN, [], c["dt"])
         for v in range(21):
             g.set(v, g0["state"][v])
         g.stimulus(g0["stim"], 40.0, 0.0, 2.0)
         g.record(-40.0)
-        if name == "surrogate":
+        if name != "plain":
             lo, hi, dv = SU.accepted_box(tr.stats)
             hi[0] = -75.0
-            g.surrogate(tr.mlp, lo, hi, dv)
+            g.surrogate(tr.mlp if name == "surrogate" else untrained, lo, hi, dv)
         g.step(6000)
         runs[name] = (g.read(B.BBX_READ_ACT_TIME), g.read(B.BBX_READ_FALLBACK_COUNT)[0], g.nact)
     at_p, _, nact = runs["plain"]
@@ -250,6 +266,13 @@ def test_training_pipeline_and_gain(env):
     print("surrogate share of voxel updates", share, "AT err mean/max (ms)", err.mean(), err.max())
     assert 0.05 < share < 1.0
     assert err.max() < 2.0
+    # the untrained network in the same place: activation times far off (or never reached)
+    at_u = runs["untrained"][0]
+    bu = np.isfinite(at_p) & np.isfinite(at_u) & m
+    err_u = np.abs(at_p[bu] - at_u[bu]).max() if bu.any() else np.inf
+    missed = int((np.isfinite(at_p) & ~np.isfinite(at_u) & m).sum())
+    print("untrained: AT err max", err_u, "voxels never activated", missed)
+    assert missed > 0 or err_u > 10 * err.max()
 
 
 def test_tp06_surrogate_pipeline(env):
@@ -296,19 +319,22 @@ def test_tp06_surrogate_pipeline(env):
     assert err.max() < 2.0
 
 
-@pytest.mark.parametrize("model,v_hi", [("crn", -81.17), ("tp06", -85.225)])
-def test_benchmark_surrogate_setting_within_1dt(model, v_hi):
-    """The benchmark's surrogate measurement (training from paced cup runs, then the
-    full 500 ms cup run with the network accepting tissue below v_hi): activation times
-    within one time step of the plain run's on every voxel, the same activated set, and
-    the network taking part of the work.  This guards the accuracy claim that goes with
-    the benchmark's surrogate speed: the margin belongs to the trained network, so a
-    change of the kinetics' FP32 arithmetic can move it."""
+@pytest.mark.parametrize("model", ["crn", "tp06"])
+def test_benchmark_surrogate_threshold_held_out(model):
+    """The benchmark's surrogate measurement: the acceptance threshold is chosen on a
+    held-out cup (another geometry seed) as the largest-share threshold whose activation
+    times stay within 0.5 dt of the plain run's; on the benchmark's own cup the surrogate
+    must then keep the same activated set and activation times within 1 dt of the plain
+    run, with the network taking part of the work."""
     import torch
     import bench
-    r = bench.surrogate_line(torch.cuda.current_stream(), model, t_ms=500.0, v_hi=v_hi)
+    r = bench.surrogate_line(torch.cuda.current_stream(), model, t_ms=500.0)
+    sel = r["threshold_selection"]
+    print(model, "chosen v_hi", sel["chosen_v_hi_mV"], "sweep", sel["sweep"])
+    assert sel["chosen_v_hi_mV"] is not None
     e = r["at_err_vs_plain_ms"]
-    print(model, "surrogate", r["speedup_vs_plain"], "x plain, AT err max", e["max"], "ms")
-    assert e["activated_plain"] == e["activated_surrogate"]
+    print(model, "surrogate", r["speedup_vs_plain"], "x plain, share", r["surrogate_share"],
+          "AT err max", e["max"], "ms, APD90 err max", r["apd90_err_vs_plain_ms"]["max"])
+    assert e["same_activated_set"]
     assert r["at_within_1dt"], e
-    assert r["fallback_fraction"] < 0.995
+    assert r["surrogate_share"] > 0.005

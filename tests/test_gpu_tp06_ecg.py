@@ -150,7 +150,7 @@ def test_tp06_full_size_sampled(B):
     <= 1e-5, concentrations <= 1e-5 relative); the pseudo-ECG of the resulting field
     matches the oracle's (chunked over the whole tissue) within 2e-6 of the term size."""
     c = WL.TP06_3D
-    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_radius"])
+    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_strip"])
     g = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32)
     g.model(B.BBX_MODEL_TP06, [], c["dt"])
     for v, val in enumerate(WL.TP06_INITIAL):
