@@ -415,7 +415,55 @@ def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / sec / 1e9
 
 
-def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000):
+def surrogate_shell(stream, tr, v_hi, t_ms):
+    """The trained TP06 surrogate-with-fallback against the plain FP32 step on the
+    512x512x384 double shell (25.2 M tissue voxels), S1 strip only, t_ms of the wave's
+    spread: step time of each and the activation-time error over the voxels either run
+    activated (APD90 needs the full beat and is not recorded in so short a run)."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    from paper_1605_06015_amd import surrogate as SU
+    from paper_1605_06015_amd import workloads as WL
+    nsteps = None
+    res = {}
+    mask = shell_geometry()["mask"].astype(bool)
+    for name in ("plain", "surrogate"):
+        grid, _, c = tp06_workload(stream, with_s2=False)
+        nsteps = int(round(t_ms / c["dt"]))
+        if name == "surrogate":
+            lo, hi, dv = SU.accepted_box(tr.stats, nvar=len(WL.TP06_INITIAL))
+            hi[0] = v_hi
+            grid.surrogate(tr.mlp, lo, hi, dv)
+        grid.step(10)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        grid.step(nsteps - 10)
+        ev[1].record(stream)
+        torch.cuda.synchronize()
+        sec = ev[0].elapsed_time(ev[1]) / 1e3
+        fb = int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]) if name == "surrogate" else 0
+        if grid.read(B.BBX_READ_NAN_FLAG)[0]:
+            raise RuntimeError(f"non-finite state in the shell {name} run")
+        res[name] = dict(at=grid.read(B.BBX_READ_ACT_TIME)[mask], sec=sec, fb=fb, nact=grid.nact,
+                         dt=c["dt"])
+        grid.close()
+    p, q = res["plain"], res["surrogate"]
+    fa, fq = np.isfinite(p["at"]), np.isfinite(q["at"])
+    both = fa & fq
+    dat = np.abs(p["at"][both] - q["at"][both])
+    per_p, per_q = p["sec"] / (nsteps - 10), q["sec"] / (nsteps - 10)
+    return {"workload": f"TP06 512x512x384 double shell ({p['nact']} tissue voxels), S1 strip, first "
+                        f"{t_ms:.0f} ms, FP32", "accepted_v_below_mV": v_hi,
+            "value": p["nact"] / per_q, "unit": "voxel-updates/s", "ms_per_step": per_q * 1e3,
+            "plain_ms_per_step": per_p * 1e3, "speedup_vs_plain": per_p / per_q,
+            "surrogate_share": 1.0 - q["fb"] / (q["nact"] * float(nsteps)),
+            "activated_voxels": int(fa.sum()), "same_activated_set": bool(np.array_equal(fa, fq)),
+            "at_err_vs_plain_ms": {"max": float(dat.max()) if dat.size else None,
+                                   "mean": float(dat.mean()) if dat.size else None, "dt": p["dt"]}}
+
+
+def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
     """Surrogate-with-fallback on the 128x128x64 cup with `model` kinetics: train on paced
     runs of the cup (outside the timed region), anchor the resting state, choose the
     acceptance threshold v_hi on a held-out cup (another geometry seed, 96x96x48), then time
@@ -431,8 +479,8 @@ def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000):
     t1 = time.perf_counter()
     anchor = B.Grid(np.ones((1, 1, 1), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32, stream)
     anchor.model(mid, [], c["dt"])
-    tr = SU.train(S, S1, iters=iters, batch=4096, lr=1e-3, seed=0, stream=stream, anchor_grid=anchor,
-                  model=model)
+    tr = SU.train(S, S1, batch=4096, seed=0, stream=stream, anchor_grid=anchor, model=model,
+                  schedule=SU.SCHEDULES[model])
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     del S, S1
@@ -443,10 +491,10 @@ def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000):
            "unit": "voxel-updates/s",
            "threshold_selection": {"held_out": "cup 96x96x48, geometry seed 11 (the benchmark cup: seed "
                                                f"{c['seed']})", "rule": "largest share with AT within "
-                                               "0.5 dt of plain", "chosen_v_hi_mV": v_hi,
+                                               "1 dt of plain", "chosen_v_hi_mV": v_hi,
                                    "sweep": {str(k): v for k, v in sweep.items()},
                                    "seconds": round(t3 - t2, 2)},
-           "training": {"pairs": tr.npairs, "iters": iters, "batch": 4096,
+           "training": {"pairs": tr.npairs, "schedule": [list(x) for x in SU.SCHEDULES[model]], "batch": 4096,
                         "final_loss": float(np.mean(tr.loss[-100:])), "gen_s": round(t1 - t0, 2),
                         "train_s": round(t2 - t1, 2)}}
     if v_hi is None:
@@ -465,6 +513,8 @@ def surrogate_line(stream, model="crn", t_ms=500.0, iters=20000):
                                        "same_activated_set": r["same_activated"]},
                 "apd90_err_vs_plain_ms": {"max": r["apd_max"], "mean": r["apd_mean"],
                                           "soft_bound_ms": 2.0}})
+    if shell_ms and model == "tp06":
+        out["shell_512x512x384"] = surrogate_shell(stream, tr, v_hi, shell_ms)
     return out
 
 
@@ -718,6 +768,8 @@ def main():
                     help="skip the stencil roofline and surrogate runs")
     ap.add_argument("--sur-ms", type=float, default=500.0,
                     help="simulated time of the surrogate comparison runs (ms)")
+    ap.add_argument("--sur-shell-ms", type=float, default=100.0,
+                    help="simulated time of the TP06 surrogate run on the 512x512x384 shell (ms; 0 skips)")
     ap.add_argument("--tab", type=float, default=0.05,
                     help="table spacing (mV) of the tabulated CRN comparison line (0: skip)")
     ap.add_argument("--ens-steps", type=int, default=0,
@@ -726,7 +778,9 @@ def main():
     ap.add_argument("--protocol", default=None, metavar="OUT.json",
                     help="run the full 1 s TP06 scroll-wave protocol (and S1 alone) and write "
                          "its summary to OUT.json, instead of the benchmark")
-    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "ensemble", "tp06"], default=None,
+    ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "stencil_iso", "ensemble", "tp06",
+                                          "train"],
+                    default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
     args = ap.parse_args()
@@ -760,6 +814,18 @@ def main():
             grid.nan_check(0)
             grid.step(args.warmup + args.steps)
             grid.close()
+        elif args.profile == "train":
+            # surrogate training at the benchmark's batch (4096) on 65,536 seeded pairs
+            gen = torch.Generator(device="cuda").manual_seed(0)
+            S = torch.randn(65536, 21, device="cuda", generator=gen)
+            S1 = S + 0.01 * torch.randn(65536, 21, device="cuda", generator=gen)
+            m = B.Mlp(21, 21, seed=0, stream=stream)
+            m.fit_norm(S, S1)
+            m.train(S, S1, 4096, args.warmup + args.steps, 1e-3)
+            m.close()
+        elif args.profile == "stencil_iso":
+            _stencil_case(stream, np.ones((384, 512, 512), np.uint8), 0.2, None, args.steps,
+                          args.warmup, 8)
         else:
             stencil_roofline(stream, steps=args.steps, warmup=args.warmup)
         src = torch.empty(1 << 26, dtype=torch.float32, device="cuda")
@@ -834,7 +900,7 @@ def main():
         out["tp06"] = tp06_line(stream, steps=args.tp06_steps)
         out["slabs"] = slab_line(stream)
         out["surrogate"] = surrogate_line(stream, "crn", t_ms=args.sur_ms)
-        out["surrogate_tp06"] = surrogate_line(stream, "tp06", t_ms=args.sur_ms)
+        out["surrogate_tp06"] = surrogate_line(stream, "tp06", t_ms=args.sur_ms, shell_ms=args.sur_shell_ms)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out))

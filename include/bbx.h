@@ -115,7 +115,11 @@ enum {
     BBX_READ_ECG = 11,            /* double[nelec]: pseudo-ECG of the current V at each
                                      electrode (bbx_ecg_set), computed now */
     BBX_READ_ECG_SERIES = 12,     /* double[count*nelec]: the sampled pseudo-ECG, sample-major */
-    BBX_READ_ECG_COUNT = 13       /* int64[1]: samples stored so far */
+    BBX_READ_ECG_COUNT = 13,      /* int64[1]: samples stored so far */
+    BBX_READ_ALL_STATE = 14       /* double[nvar*nbox]: every state variable in box layout,
+                                     variable after variable (void NaN): with BBX_READ_STEP a
+                                     checkpoint, restored by bbx_state_set per variable and
+                                     bbx_clock_set (the paper's `dump` / `load` of the state) */
 };
 
 /* Info queries for bbx_info.  SEND_* / RECV_*: values a slab grid (bbx_slab_create)
@@ -283,6 +287,19 @@ int bbx_integrator_set(bbx_grid *g, int integrator);
  * read with BBX_READ_VAR / BBX_READ_STEP; step >= 0. */
 int bbx_clock_set(bbx_grid *g, int64_t step);
 
+/* Launch mode of bbx_step: chunk = 0 launches every step directly (the default);
+ * chunk = K > 0 (even, <= 4096) replays a HIP graph of K step launches whenever at least K
+ * steps are left, the rest launched directly.  The graph's kernels read the step number
+ * from a device counter (set from the host clock at each bbx_step call, advanced by the
+ * graph's last node) and evaluate their stimulus windows and t_n from it with the host's
+ * arithmetic, so results are bitwise those of direct launches.  Graphs are captured on
+ * first use and dropped by any call that changes what a step does (model, stimuli,
+ * recording, tabulation, integrator, this call).  Steps stay direct while a surrogate is
+ * attached or pseudo-ECG samples are being taken; with the finite check on, it runs after
+ * each chunk that crosses a multiple of its interval.  Errors: BBX_EINVAL (chunk),
+ * BBX_ENOTSUP (a grid created on the null stream: capture needs a stream of its own). */
+int bbx_graph_set(bbx_grid *g, int chunk);
+
 /* Advance nsteps >= 0 time steps (one fused kernel launch per step). */
 int bbx_step(bbx_grid *g, int64_t nsteps);
 
@@ -402,6 +419,18 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
  * BBX_EINVAL (variables, levels, max_points), BBX_ESTATE (no model). */
 int bbx_tips(bbx_grid *g, int var_u, double u_level, int var_v, double v_level, double *stats,
              double *points, int64_t max_points, int64_t *npoints);
+
+/* Attach a surrogate from host arrays (a network trained elsewhere) instead of a
+ * bbx_mlp: nin = nout = the model's nvar; weights_bf16 holds W1[128][nin], W2[128][128],
+ * W3[nout][128] one after the other as BF16 bit patterns (the precision the MFMA kernels
+ * read), biases b1[128], b2[128], b3[nout] (FP32), norm[4][32] = in_mean, in_scale,
+ * out_mean, out_sigma (as bbx_mlp_norm); lo, hi, dv_max as bbx_surrogate_set, whose
+ * semantics the attached network then has.  Arrays are copied.  Errors as
+ * bbx_surrogate_set, plus BBX_EINVAL for non-finite parameters or a negative
+ * out_sigma. */
+int bbx_surrogate_import(bbx_grid *g, int nin, int nout, const uint16_t *weights_bf16,
+                         const float *biases, const float *norm, const float *lo, const float *hi,
+                         float dv_max);
 
 /* Integer facts about a grid (BBX_INFO_*). */
 int bbx_info(const bbx_grid *g, int what, int64_t *out);

@@ -17,20 +17,22 @@
  *
  * Parity status (every function below is pinned by the CPU tests unless this
  * list says otherwise):
- *   - weights, diffusion, Euler, Rush-Larsen, Barkley/ZFK/FHN steps: pinned
- *     (closed forms, invariants, brute force, plane-wave speed).
- *   - weights at boundary voxels with variable fibres (reading G6 of the
- *     design notes: a void neighbour's tensor is replaced by the centre's):
- *     parity unpinned -- the paper leaves that case undefined.
+ *   - weights, diffusion, Euler, Rush-Larsen, RK4, Barkley/ZFK/FHN steps, the
+ *     phase-singularity finder: pinned (closed forms, invariants, brute force,
+ *     plane-wave speed, orders of convergence).
+ *   - weights at boundary voxels with variable fibres (the paper leaves the
+ *     tensor of a void neighbour undefined; here it is the centre's): pinned by
+ *     the vanishing of the tissue integral's drift under refinement (the
+ *     continuous no-flux problem conserves it for any tensor).
  *   - Courtemanche-Ramirez-Nattel 1998 cell model: transcribed from the
- *     original model publication (not part of the paper); pinned only loosely
- *     by that publication's resting state and action-potential shape.
+ *     original model publication (not part of the paper); parity partially
+ *     pinned, by that publication's resting state and action-potential shape.
  *   - four-variable Fenton-Karma-type minimal model (Bueno-Orovio, Cherry &
  *     Fenton 2008, epicardial set): transcribed from that publication; pinned
- *     by its exact resting state, the closed-form subthreshold relaxation and
- *     loosely by the shape of its action potential.
+ *     by its exact resting state and the closed-form subthreshold relaxation;
+ *     its suprathreshold constants are partially pinned (action-potential shape).
  *   - ten Tusscher-Panfilov 2006 ventricular model (epicardial): transcribed
- *     from its publications; pinned only loosely by its resting state and
+ *     from its publications; parity partially pinned, by its resting state and
  *     action-potential shape.
  */
 #include <math.h>

@@ -20,6 +20,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "bbx_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+# A build with AddressSanitizer and UndefinedBehaviorSanitizer, loaded instead when
+# BBX_ORACLE_SANITIZE=1 (the process must preload gcc's sanitizer runtimes).
+LIB_SAN = os.path.join(HERE, "liboracle_san.so")
+SAN_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+             "-fno-omit-frame-pointer", "-g"]
 
 MODEL_NONE, MODEL_BARKLEY, MODEL_ZFK, MODEL_FHN, MODEL_CRN, MODEL_FK4, MODEL_TP06 = \
     0, 1, 2, 3, 4, 5, 6
@@ -27,14 +32,16 @@ SCHEME_ADDITIVE, SCHEME_SPLIT = 0, 1
 INTEGRATOR_EULER_RL, INTEGRATOR_RK4 = 0, 1
 
 
-def build(force: bool = False) -> str:
-    """Compile the oracle into a shared library next to its source."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile the oracle into a shared library next to its source (with sanitize: the
+    AddressSanitizer / UndefinedBehaviorSanitizer build)."""
+    lib = LIB_SAN if sanitize else LIB
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(SRC):
+        tmp = lib + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC",
-                               "-shared", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               *(SAN_FLAGS if sanitize else []), "-shared", "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 _lib = None
@@ -43,8 +50,8 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(LIB)
+        san = os.environ.get("BBX_ORACLE_SANITIZE") == "1"
+        L = C.CDLL(build(sanitize=san))
         P = C.c_void_p
         i64 = C.c_int64
         L.orc_weights.argtypes = [C.c_int, C.c_int, C.c_int, C.c_double, P, P, C.c_double,

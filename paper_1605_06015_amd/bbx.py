@@ -15,7 +15,10 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libbbx.so")
+# BBX_LIB may name another build of the library (the sanitized host build of the CPU
+# checks); the default is the in-tree libbbx.so.
+LIB_PATH = os.environ.get("BBX_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                     "libbbx.so")
 
 BBX_OK, BBX_EINVAL, BBX_ENOMEM, BBX_EDEVICE, BBX_ESTATE, BBX_EUNSTABLE, BBX_ENUMERIC, BBX_ENOTSUP = \
     0, -1, -2, -3, -4, -5, -6, -7
@@ -27,7 +30,7 @@ BBX_MODEL_NONE, BBX_MODEL_BARKLEY, BBX_MODEL_ZFK, BBX_MODEL_FHN, BBX_MODEL_CRN, 
 (BBX_READ_VAR, BBX_READ_ACT_TIME, BBX_READ_APD90, BBX_READ_VMAX, BBX_READ_STATUS,
  BBX_READ_REDUCE_MAX, BBX_READ_REDUCE_SUM, BBX_READ_NAN_FLAG, BBX_READ_STEP,
  BBX_READ_WEIGHTS, BBX_READ_FALLBACK_COUNT, BBX_READ_ECG, BBX_READ_ECG_SERIES,
- BBX_READ_ECG_COUNT) = range(14)
+ BBX_READ_ECG_COUNT, BBX_READ_ALL_STATE) = range(15)
 (BBX_INFO_NACTIVE, BBX_INFO_NVAR, BBX_INFO_NBOX, BBX_INFO_DEVICE_BYTES, BBX_INFO_SEND_LO,
  BBX_INFO_SEND_HI, BBX_INFO_RECV_LO, BBX_INFO_RECV_HI) = range(8)
 (BBX_ENS_TILE_64x4, BBX_ENS_TILE_32x8, BBX_ENS_TILE_16x16, BBX_ENS_DIRECT_64x4, BBX_ENS_MARCH_64x32,
@@ -52,6 +55,7 @@ SIGNATURES = {
     "bbx_nan_check_set": (_I, [_P, _I64]),
     "bbx_clock_set": (_I, [_P, _I64]),
     "bbx_integrator_set": (_I, [_P, _I]),
+    "bbx_graph_set": (_I, [_P, _I]),
     "bbx_tabulation_set": (_I, [_P, _D]),
     "bbx_ecg_set": (_I, [_P, _I, _P, _I64, _I64]),
     "bbx_step": (_I, [_P, _I64]),
@@ -73,6 +77,7 @@ SIGNATURES = {
     "bbx_sample_states": (_I, [_P, _I64, C.c_uint64, _P]),
     "bbx_ionic_map": (_I, [_P, _P, _I64, _P]),
     "bbx_surrogate_set": (_I, [_P, _P, _P, _P, C.c_float]),
+    "bbx_surrogate_import": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, C.c_float]),
     "bbx_ensemble_create": (_I, [_I, _P, _P, _D, _P, _P, _P, _I, _P, _I, _D, _I, _P, C.POINTER(_P)]),
     "bbx_ensemble_state_set": (_I, [_P, _I, _I, _P]),
     "bbx_ensemble_stimulus_add": (_I, [_P, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I]),
@@ -226,6 +231,17 @@ def bbx_grid_destroy(g):
     _lib.bbx_grid_destroy(g)
 
 
+def bbx_surrogate_import(g, nin, nout, weights_bf16, biases, norm, lo, hi, dv_max):
+    """weights_bf16: uint16 array (W1, W2, W3 flat); biases float32 (b1, b2, b3); norm (4, 32)."""
+    w = np.ascontiguousarray(weights_bf16, dtype=np.uint16)
+    b = np.ascontiguousarray(biases, dtype=np.float32)
+    nm = np.ascontiguousarray(norm, dtype=np.float32)
+    lo = np.ascontiguousarray(lo, dtype=np.float32)
+    hi = np.ascontiguousarray(hi, dtype=np.float32)
+    _check(_lib.bbx_surrogate_import(g, int(nin), int(nout), _ptr(w), _ptr(b), _ptr(nm), _ptr(lo),
+                                     _ptr(hi), float(dv_max)))
+
+
 def bbx_tips(g, var_u, u_level, var_v, v_level, max_points=100000):
     """Phase singularities: (stats[7], points (n, 3) mm)."""
     stats = np.zeros(7)
@@ -349,6 +365,10 @@ class Grid:
     def integrator(self, integrator):
         bbx_integrator_set(self.handle, integrator)
 
+    def graph(self, chunk):
+        """Replay chunks of `chunk` steps from a captured HIP graph (0: direct launches)."""
+        _check(_lib.bbx_graph_set(self.handle, int(chunk)))
+
     def fill(self, var, value):
         bbx_state_fill(self.handle, var, value)
 
@@ -381,6 +401,19 @@ class Grid:
     def surrogate(self, mlp, lo=None, hi=None, dv_max=0.0):
         """Attach a trained Mlp with its accepted input box (None detaches)."""
         bbx_surrogate_set(self.handle, None if mlp is None else mlp.handle, lo, hi, dv_max)
+
+    def checkpoint(self):
+        """(state (nvar, nz, ny, nx) in box layout, step counter): BBX_READ_ALL_STATE and
+        BBX_READ_STEP."""
+        nv = bbx_info(self.handle, BBX_INFO_NVAR)
+        out = np.empty((nv,) + tuple(self.shape), np.float64)
+        bbx_readout(self.handle, BBX_READ_ALL_STATE, 0, None, out)
+        return out, int(self.read(BBX_READ_STEP)[0])
+
+    def restore(self, state, step):
+        for v in range(state.shape[0]):
+            bbx_state_set(self.handle, v, np.nan_to_num(state[v]))
+        bbx_clock_set(self.handle, step)
 
     def get(self, var=0):
         out = np.empty(self.shape, np.float64)

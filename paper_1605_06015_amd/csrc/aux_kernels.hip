@@ -109,6 +109,17 @@ hipError_t launch_gather(const T *box, const int32_t *idx, int dense, int64_t na
     return hipGetLastError();
 }
 
+__global__ void k_counter(int64_t *p, int64_t v, int add)
+{
+    if (threadIdx.x == 0) *p = add ? *p + v : v;
+}
+
+hipError_t launch_counter(int64_t *p, int64_t v, int add, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_counter, dim3(1), dim3(64), 0, s, p, v, add);
+    return hipGetLastError();
+}
+
 // box[idx[i]] = src[i]: writes received halo values into a slab's halo plane.
 template <typename T>
 __global__ void k_scatter(const T *src, const int32_t *idx, int64_t n, T *box)

@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -142,6 +143,14 @@ struct bbx_grid {
     int64_t send_n[2] = {0, 0}, recv_n[2] = {0, 0};
     int32_t *d_send[2] = {nullptr, nullptr}, *d_recv[2] = {nullptr, nullptr};
     int32_t *d_map = nullptr;          // box -> tissue index (-1 void), built on first use
+    // graph replay of bbx_step (bbx_graph_set): chunk steps per graph, one graph per
+    // starting V buffer; device step counter and stimulus windows
+    int chunk = 0;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int64_t *d_nbase = nullptr;
+    StimWin *d_win = nullptr;
+    bool win_dirty = true;
 };
 
 namespace {
@@ -163,14 +172,26 @@ void dfree(void *p)
     if (p) (void)hipFree(p);
 }
 
+void graph_drop(bbx_grid *g)
+{
+    for (int c = 0; c < 2; c++) {
+        if (g->gexec[c]) (void)hipGraphExecDestroy(g->gexec[c]);
+        if (g->graph[c]) (void)hipGraphDestroy(g->graph[c]);
+        g->gexec[c] = nullptr;
+        g->graph[c] = nullptr;
+    }
+    g->win_dirty = true;
+}
+
 void free_all(bbx_grid *g)
 {
+    graph_drop(g);
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
                   g->d_acc_list, g->d_acc_cnt, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
                   g->snet.bias, g->snet.norm, g->d_send[0], g->d_send[1], g->d_recv[0],
-                  g->d_recv[1], g->d_map};
+                  g->d_recv[1], g->d_map, g->d_nbase, g->d_win};
     for (void *p : ps) dfree(p);
 }
 
@@ -303,6 +324,82 @@ SurArgs sur_args(const bbx_grid *g, int parity)
     return su;
 }
 
+// Capture one chunk of steps starting from V buffer c: each step reads its number from the
+// device counter (base + position) and evaluates its stimuli and t_n there; the last node
+// advances the counter by the chunk.
+template <typename T>
+int graph_capture(bbx_grid *g, int c)
+{
+    StepArgs<T> a = make_args<T>(g);
+    a.nbase = g->d_nbase;
+    a.win = g->d_win;
+    a.dt64 = g->dt;
+    HIP_TRY(hipStreamBeginCapture(g->stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    hipError_t e = hipSuccess;
+    for (int j = 0; j < g->chunk && e == hipSuccess; j++) {
+        a.Vin = (const T *)g->d_V[c ^ (j & 1)];
+        a.Vout = (T *)g->d_V[c ^ (j & 1) ^ 1];
+        a.jstep = j;
+        e = launch_step<T>(g->model, g->aniso, a, g->stream);
+    }
+    if (e == hipSuccess) e = launch_counter(g->d_nbase, g->chunk, 1, g->stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(g->stream, &gr);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return hip_fail(e != hipSuccess ? e : e2, "graph capture");
+    }
+    g->graph[c] = gr;
+    e = hipGraphInstantiate(&g->gexec[c], gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(gr);
+        g->graph[c] = nullptr;
+        g->gexec[c] = nullptr;
+        return hip_fail(e, "hipGraphInstantiate");
+    }
+    return BBX_OK;
+}
+
+// Replay whole chunks while at least one is left; returns the steps done.  Not used with a
+// surrogate attached or while pseudo-ECG samples are being taken (both stay direct).
+template <typename T>
+int graph_steps(bbx_grid *g, int64_t nsteps, int64_t *done)
+{
+    *done = 0;
+    if (g->chunk <= 0 || nsteps < g->chunk || g->sur || g->nact == 0) return BBX_OK;
+    if (g->ecg_every > 0 && g->ecg_count < g->ecg_max) return BBX_OK;
+    hipError_t e = hipSuccess;
+    if (!g->d_nbase && (e = dalloc(g, &g->d_nbase, sizeof(int64_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if (!g->d_win && (e = dalloc(g, &g->d_win, kMaxStim * sizeof(StimWin))) != hipSuccess) return hip_fail(e, "hipMalloc");
+    if (g->win_dirty) {
+        StimWin w[kMaxStim] = {};
+        for (size_t k = 0; k < g->stims.size(); k++) {
+            const StimDef &sd = g->stims[k];
+            w[k] = {steps_of(sd.t0, g->dt), steps_of(sd.dur, g->dt),
+                    sd.period > 0 ? steps_of(sd.period, g->dt) : 0, (int64_t)sd.count};
+        }
+        HIP_TRY(hipMemcpy(g->d_win, w, sizeof w, hipMemcpyHostToDevice), "hipMemcpy");
+        g->win_dirty = false;
+    }
+    HIP_TRY(launch_counter(g->d_nbase, g->n, 0, g->stream), "counter");
+    const int nst = g->nvar - 1;
+    while (nsteps - *done >= g->chunk) {
+        const int c = g->cur;
+        if (!g->gexec[c]) {
+            int rc = graph_capture<T>(g, c);
+            if (rc) return rc;
+        }
+        HIP_TRY(hipGraphLaunch(g->gexec[c], g->stream), "hipGraphLaunch");
+        const int64_t n0 = g->n;
+        g->n += g->chunk;                  // chunk even: the V buffer parity is unchanged
+        *done += g->chunk;
+        if (g->nan_every > 0 && n0 / g->nan_every != g->n / g->nan_every)
+            HIP_TRY(launch_nonfinite<T>((const T *)g->d_V[g->cur], g->d_idx, g->dense, (const T *)g->d_st,
+                                        nst, g->nact, g->pitch, g->d_flag, g->stream), "finite check");
+    }
+    return BBX_OK;
+}
+
 template <typename T>
 int step_impl(bbx_grid *g, int64_t nsteps)
 {
@@ -310,6 +407,10 @@ int step_impl(bbx_grid *g, int64_t nsteps)
     const int nst = g->nvar - 1;
     // a fill kernel, not a memset: a caller may capture bbx_step into a graph
     if (g->nan_every > 0) HIP_TRY(launch_fill<int>(g->d_flag, 0, 1, g->stream), "flag clear");
+    int64_t done = 0;
+    int rc = graph_steps<T>(g, nsteps, &done);
+    if (rc) return rc;
+    nsteps -= done;
     for (int64_t s = 0; s < nsteps; s++) {
         const int64_t n = g->n;
         a.Vin = (const T *)g->d_V[g->cur];
@@ -727,6 +828,28 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
         HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
         return BBX_OK;
     }
+    case BBX_READ_ALL_STATE: {
+        // every state variable in box layout, variable after variable (a checkpoint: with
+        // BBX_READ_STEP it restores through bbx_state_set and bbx_clock_set)
+        const size_t need = (size_t)g->nvar * nbox * sizeof(double);
+        if (out_bytes < need) return fail(BBX_EINVAL, "out_bytes too small");
+        DevBuf tmp;
+        double *dst = (double *)out;
+        if (!on_dev) {
+            HIP_TRY(hipMalloc(&tmp.p, need), "hipMalloc");
+            dst = (double *)tmp.p;
+        }
+        for (int v = 0; v < g->nvar; v++) {
+            const T *src = v == 0 ? (const T *)g->d_V[g->cur] : (const T *)g->d_st + (int64_t)(v - 1) * g->pitch;
+            HIP_TRY(launch_to_box<T>(src, v == 0, g->d_idx, g->dense, g->nact, nbox, dst + (int64_t)v * nbox,
+                                     g->stream), "to_box");
+        }
+        if (!on_dev) {
+            HIP_TRY(hipMemcpyAsync(out, tmp.p, need, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+            HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        }
+        return BBX_OK;
+    }
     case BBX_READ_ECG_COUNT: {
         if (on_dev) return fail(BBX_ENOTSUP, "ECG_COUNT is read to host memory only");
         if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
@@ -976,6 +1099,7 @@ int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, dou
         g->scheme = scheme;
         for (int i = 0; i < kMaxParams; i++) g->prm[i] = i < np ? params[i] : 0.0;
         g->n = 0;
+        graph_drop(g);
         return build_table(g);
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
@@ -1043,6 +1167,7 @@ int bbx_stimulus_add(bbx_grid *g, const uint8_t *region, double amplitude, doubl
         }
         g->h_stimbits.swap(bits);
         g->stims.push_back({amplitude, t_start, duration, period, count});
+        graph_drop(g);
         return BBX_OK;
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
@@ -1054,6 +1179,7 @@ int bbx_stimulus_clear(bbx_grid *g)
     g_err.clear();
     if (!g) return fail(BBX_EINVAL, "grid is NULL");
     g->stims.clear();
+    graph_drop(g);
     std::fill(g->h_stimbits.begin(), g->h_stimbits.end(), 0u);
     if (g->d_stimbits && g->nact)
         HIP_TRY(hipMemset(g->d_stimbits, 0, g->nact * sizeof(uint32_t)), "hipMemset");
@@ -1065,6 +1191,7 @@ int bbx_recording_set(bbx_grid *g, double theta)
     try {
         g_err.clear();
         if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        graph_drop(g);
         if (isnan(theta)) { g->rec = 0; return BBX_OK; }
         if (!isfinite(theta)) return fail(BBX_EINVAL, "theta must be finite or NaN");
         return g->prec ? recording_impl<double>(g, theta) : recording_impl<float>(g, theta);
@@ -1150,6 +1277,7 @@ int bbx_tabulation_set(bbx_grid *g, double dv)
         if (dv < 1e-4 || (kTabVmax - kTabVmin) / dv > 1e7) return fail(BBX_EINVAL, "dv out of range");
     }
     g->tab_dv = dv;
+    graph_drop(g);
     return build_table(g);
 }
 
@@ -1162,6 +1290,18 @@ int bbx_integrator_set(bbx_grid *g, int integrator)
     if (integrator == BBX_INTEGRATOR_RK4 && g->sur)
         return fail(BBX_ENOTSUP, "the surrogate stands in for the Euler / Rush-Larsen step");
     g->integrator = integrator;
+    graph_drop(g);
+    return BBX_OK;
+}
+
+int bbx_graph_set(bbx_grid *g, int chunk)
+{
+    g_err.clear();
+    if (!g) return fail(BBX_EINVAL, "grid is NULL");
+    if (chunk < 0 || chunk > 4096 || (chunk & 1)) return fail(BBX_EINVAL, "chunk must be even, 0..4096");
+    if (chunk > 0 && !g->stream) return fail(BBX_ENOTSUP, "graph capture needs a stream other than the null stream");
+    graph_drop(g);
+    g->chunk = chunk;
     return BBX_OK;
 }
 
@@ -1635,6 +1775,114 @@ int bbx_ionic_map(bbx_grid *g, const float *in_dev, int64_t n, float *out_dev)
     return BBX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validation shared by the two ways of attaching a surrogate.
+int surrogate_check(const bbx_grid *g, int nin, int nout, const float *lo, const float *hi,
+                    float dv_max)
+{
+    if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the surrogate runs on FP32 grids");
+    if (g->integrator != BBX_INTEGRATOR_EULER_RL)
+        return fail(BBX_ENOTSUP, "the surrogate stands in for the Euler / Rush-Larsen step");
+    if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN &&
+        g->model != BBX_MODEL_TP06)
+        return fail(BBX_ENOTSUP, "no surrogate step for model %d", g->model);
+    if (nin != g->nvar || nout != g->nvar)
+        return fail(BBX_EINVAL, "network is %d -> %d, the model has %d variables", nin, nout, g->nvar);
+    if (!lo || !hi) return fail(BBX_EINVAL, "lo / hi is NULL");
+    if (!(dv_max >= 0)) return fail(BBX_EINVAL, "dv_max must be >= 0");
+    return BBX_OK;
+}
+
+// Device buffers of the grid's network copy and its step lists (first attachment).
+int surrogate_alloc(bbx_grid *g, int nin, int nout)
+{
+    if (g->snet.w1) return BBX_OK;
+    hipError_t e;
+    g->snet.nin = nin;
+    g->snet.nout = nout;
+    if ((e = dalloc(g, &g->snet.w1, kH * kS1 * sizeof(__bf16))) != hipSuccess ||
+        (e = dalloc(g, &g->snet.w2, kH * kS2 * sizeof(__bf16))) != hipSuccess ||
+        (e = dalloc(g, &g->snet.w3, kP * kS2 * sizeof(__bf16))) != hipSuccess ||
+        (e = dalloc(g, &g->snet.bias, (2 * kH + kP) * sizeof(float))) != hipSuccess ||
+        (e = dalloc(g, &g->snet.norm, 4 * kP * sizeof(float))) != hipSuccess ||
+        (e = dalloc(g, &g->d_slo, kP * sizeof(float))) != hipSuccess ||
+        (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
+        (e = dalloc(g, &g->d_acc_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(g, &g->d_acc_cnt, 2 * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(g, &g->d_fb_total, sizeof(unsigned long long))) != hipSuccess)
+        return hip_fail(e, "hipMalloc");
+    return BBX_OK;
+}
+
+// Box, counters and flags after the weights are in place.
+int surrogate_finish(bbx_grid *g, const float *lo, const float *hi, float dv_max)
+{
+    hipStream_t st = g->stream;
+    HIP_TRY(hipMemcpyAsync(g->d_slo, lo, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
+    HIP_TRY(hipMemcpyAsync(g->d_shi, hi, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
+    HIP_TRY(launch_fill<int>(g->d_acc_cnt, 0, 2, st), "fill");
+    HIP_TRY(launch_fill<int>((int *)g->d_fb_total, 0, 2, st), "fill");
+    HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
+    g->dv_max = dv_max;
+    g->sur = 1;
+    return BBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbx_surrogate_import(bbx_grid *g, int nin, int nout, const uint16_t *weights_bf16,
+                         const float *biases, const float *norm, const float *lo, const float *hi,
+                         float dv_max)
+{
+    try {
+        g_err.clear();
+        if (!g) return fail(BBX_EINVAL, "grid is NULL");
+        if (!weights_bf16 || !biases || !norm) return fail(BBX_EINVAL, "NULL argument");
+        if (nin < 1 || nin > kP || nout < 1 || nout > kP)
+            return fail(BBX_EINVAL, "nin and nout must be in [1, %d]", kP);
+        int rc = surrogate_check(g, nin, nout, lo, hi, dv_max);
+        if (rc) return rc;
+        for (int i = 0; i < 4 * kP; i++)
+            if (!isfinite(norm[i])) return fail(BBX_EINVAL, "normalisation entry %d is not finite", i);
+        for (int i = 0; i < kP; i++)
+            if (norm[3 * kP + i] < 0.f) return fail(BBX_EINVAL, "out_sigma %d is negative", i);
+        // flat FP32 parameters W1 b1 W2 b2 W3 b3 from the BF16 weights (exact) and biases
+        const int nw1 = kH * nin, nw2 = kH * kH, nw3 = nout * kH;
+        std::vector<float> p((size_t)mlp_nparams(nin, nout));
+        auto bf = [](uint16_t b) { uint32_t u = (uint32_t)b << 16; float f; memcpy(&f, &u, 4); return f; };
+        size_t o = 0, w = 0, bo = 0;
+        for (int i = 0; i < nw1; i++) p[o++] = bf(weights_bf16[w++]);
+        for (int i = 0; i < kH; i++) p[o++] = biases[bo++];
+        for (int i = 0; i < nw2; i++) p[o++] = bf(weights_bf16[w++]);
+        for (int i = 0; i < kH; i++) p[o++] = biases[bo++];
+        for (int i = 0; i < nw3; i++) p[o++] = bf(weights_bf16[w++]);
+        for (int i = 0; i < nout; i++) p[o++] = biases[bo++];
+        for (float v : p)
+            if (!isfinite(v)) return fail(BBX_EINVAL, "a network parameter is not finite");
+        rc = surrogate_alloc(g, nin, nout);
+        if (rc) return rc;
+        DevBuf dp;
+        HIP_TRY(hipMalloc(&dp.p, p.size() * sizeof(float)), "hipMalloc");
+        HIP_TRY(hipMemcpyAsync(dp.p, p.data(), p.size() * sizeof(float), hipMemcpyHostToDevice, g->stream),
+                "hipMemcpyAsync");
+        MlpDev d = g->snet;
+        d.w2t = nullptr;
+        d.w3t = nullptr;
+        HIP_TRY(mlp_pack((const float *)dp.p, d, g->stream), "pack");
+        HIP_TRY(hipMemcpyAsync(g->snet.norm, norm, 4 * kP * sizeof(float), hipMemcpyHostToDevice, g->stream),
+                "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+        return surrogate_finish(g, lo, hi, dv_max);
+    } catch (...) {
+        return fail(BBX_ENOMEM, "host allocation failed");
+    }
+}
+
 int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const float *hi, float dv_max)
 {
     try {
@@ -1644,32 +1892,10 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
             g->sur = 0;
             return BBX_OK;
         }
-        if (g->prec != BBX_FP32) return fail(BBX_ENOTSUP, "the surrogate runs on FP32 grids");
-        if (g->integrator != BBX_INTEGRATOR_EULER_RL)
-            return fail(BBX_ENOTSUP, "the surrogate stands in for the Euler / Rush-Larsen step");
-        if (g->model != BBX_MODEL_BARKLEY && g->model != BBX_MODEL_FHN && g->model != BBX_MODEL_CRN &&
-            g->model != BBX_MODEL_TP06)
-            return fail(BBX_ENOTSUP, "no surrogate step for model %d", g->model);
-        if (m->nin != g->nvar || m->nout != g->nvar)
-            return fail(BBX_EINVAL, "network is %d -> %d, the model has %d variables", m->nin, m->nout, g->nvar);
-        if (!lo || !hi) return fail(BBX_EINVAL, "lo / hi is NULL");
-        if (!(dv_max >= 0)) return fail(BBX_EINVAL, "dv_max must be >= 0");
-        hipError_t e = hipSuccess;
-        if (!g->snet.w1) {
-            g->snet.nin = m->nin;
-            g->snet.nout = m->nout;
-            if ((e = dalloc(g, &g->snet.w1, kH * kS1 * sizeof(__bf16))) != hipSuccess ||
-                (e = dalloc(g, &g->snet.w2, kH * kS2 * sizeof(__bf16))) != hipSuccess ||
-                (e = dalloc(g, &g->snet.w3, kP * kS2 * sizeof(__bf16))) != hipSuccess ||
-                (e = dalloc(g, &g->snet.bias, (2 * kH + kP) * sizeof(float))) != hipSuccess ||
-                (e = dalloc(g, &g->snet.norm, 4 * kP * sizeof(float))) != hipSuccess ||
-                (e = dalloc(g, &g->d_slo, kP * sizeof(float))) != hipSuccess ||
-                (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
-                (e = dalloc(g, &g->d_acc_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
-                (e = dalloc(g, &g->d_acc_cnt, 2 * sizeof(int32_t))) != hipSuccess ||
-                (e = dalloc(g, &g->d_fb_total, sizeof(unsigned long long))) != hipSuccess)
-                return hip_fail(e, "hipMalloc");
-        }
+        int rc = surrogate_check(g, m->nin, m->nout, lo, hi, dv_max);
+        if (rc) return rc;
+        rc = surrogate_alloc(g, m->nin, m->nout);
+        if (rc) return rc;
         hipStream_t st = g->stream;
         // the network's device copies are ordered on its own stream: finish them first
         HIP_TRY(hipStreamSynchronize(m->stream), "hipStreamSynchronize");
@@ -1678,14 +1904,7 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
         HIP_TRY(hipMemcpyAsync(g->snet.w3, m->dev.w3, kP * kS2 * sizeof(__bf16), hipMemcpyDeviceToDevice, st), "copy");
         HIP_TRY(hipMemcpyAsync(g->snet.bias, m->dev.bias, (2 * kH + kP) * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
         HIP_TRY(hipMemcpyAsync(g->snet.norm, m->dev.norm, 4 * kP * sizeof(float), hipMemcpyDeviceToDevice, st), "copy");
-        HIP_TRY(hipMemcpyAsync(g->d_slo, lo, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
-        HIP_TRY(hipMemcpyAsync(g->d_shi, hi, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
-        HIP_TRY(hipMemsetAsync(g->d_acc_cnt, 0, 2 * sizeof(int32_t), st), "hipMemsetAsync");
-        HIP_TRY(hipMemsetAsync(g->d_fb_total, 0, sizeof(unsigned long long), st), "hipMemsetAsync");
-        HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
-        g->dv_max = dv_max;
-        g->sur = 1;
-        return BBX_OK;
+        return surrogate_finish(g, lo, hi, dv_max);
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
     }

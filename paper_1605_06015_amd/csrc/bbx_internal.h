@@ -28,6 +28,12 @@ __host__ __device__ constexpr NbOff nb_off(int b)
     return t[b];
 }
 
+// Stimulus window in whole steps (as the host evaluates it): on for n0 + c*per <= n <
+// n0 + c*per + len, c = 0 .. count-1 (per <= 0: once; count <= 0 with per > 0: forever).
+struct StimWin {
+    int64_t n0, len, per, count;
+};
+
 // Arguments of one fused step launch (passed by value in the kernarg segment).
 template <typename T>
 struct StepArgs {
@@ -52,12 +58,18 @@ struct StepArgs {
     const float *tab;          // tabulated voltage-only kinetic terms (FP32 CRN) or null
     // stimulus
     int nstim;
-    uint32_t stim_on;          // bit s: stimulus s active at this step
+    uint32_t stim_on;          // bit s: stimulus s active at this step (host-evaluated)
     const uint32_t *stimbits;  // [nact] bit s: voxel inside stimulus s region
     const T *stim_amp;         // [kMaxStim]
     // activation / APD90 recording
     int rec;
     T theta, tn;
+    // device clock (graph replay): with nbase set, the step is n = *nbase + jstep, and
+    // the kernel evaluates stim_on from win[] and tn = n * dt64 itself, as the host does
+    const int64_t *nbase;
+    int jstep;
+    double dt64;
+    const StimWin *win;
     uint8_t *status;
     T *at, *vmax, *apd;
     T *vrep;                   // rest level until the peak is known, then the 90% level
@@ -132,6 +144,8 @@ template <typename T>
 hipError_t launch_weights(const StepArgs<T> &a, int aniso, double *W, hipStream_t s);
 template <typename T>
 hipError_t launch_fill(T *p, T v, int64_t n, hipStream_t s);
+// *p = v (set) or *p += v (advance), one thread: a graph's device step counter.
+hipError_t launch_counter(int64_t *p, int64_t v, int add, hipStream_t s);
 template <typename T>
 hipError_t launch_fill_tissue(T *box, const int32_t *idx, int64_t nact, T v, hipStream_t s);
 hipError_t launch_crn_table(double vmin, double dv, int n, double dt, float *tab, hipStream_t s);

@@ -17,7 +17,8 @@ constexpr int kS2 = kH + 8;               // LDS row stride (BF16) of 128-wide w
 constexpr int kPart = 2 * kH + kP + 1;    // per-tile partial sums: db1, db2, db3, loss
 constexpr int64_t kMaxBatch = 65536;      // training batch limit
 constexpr int kSurBlock = 768;            // threads per surrogate-step workgroup (12 waves)
-constexpr int kOS = kP + 1;               // row stride (floats) of the output staging
+constexpr int kSurRow = 28;               // staging row (floats) per voxel in the surrogate step:
+                                          // 112 B, so the 16 rows a tile reads hit distinct banks
 constexpr float kGateTol = 1e-3f;         // accepted excursion of a predicted gate outside [0, 1]
 
 // Device copies of one network: BF16 weights in the MFMA layouts (see

@@ -87,7 +87,8 @@ __global__ void k_init_params(float *p, int nin, int nout, uint64_t seed)
     p[e] = v;
 }
 
-// BF16 copies of the weights in the layouts the MFMA loops read.
+// BF16 copies of the weights in the layouts the MFMA loops read.  The transposed
+// copies (w2t, w3t) only exist for training; a grid's inference copy leaves them null.
 __global__ void k_pack(const float *p, int nin, int nout, MlpDev d)
 {
     const POff o = poff(nin, nout);
@@ -98,13 +99,13 @@ __global__ void k_pack(const float *p, int nin, int nout, MlpDev d)
         d.w1[e] = bf(k < nin ? p[o.w1 + m * nin + k] : 0.0f);
         // W3^T: [H (h2)][kS1], permuted order over the (padded) outputs
         const int oo = k < kP ? kperm(k) : kP;
-        d.w3t[e] = bf(oo < nout ? p[o.w3 + oo * kH + m] : 0.0f);
+        if (d.w3t) d.w3t[e] = bf(oo < nout ? p[o.w3 + oo * kH + m] : 0.0f);
     }
     if (e < kH * kS2) {
         const int m = e / kS2, k = e % kS2;
         const int kk = k < kH ? 32 * (k / 32) + kperm(k % 32) : kH;
         d.w2[e] = bf(kk < kH ? p[o.w2 + m * kH + kk] : 0.0f);          // W2[m][kk]
-        d.w2t[e] = bf(kk < kH ? p[o.w2 + kk * kH + m] : 0.0f);         // W2^T[m][kk] = W2[kk][m]
+        if (d.w2t) d.w2t[e] = bf(kk < kH ? p[o.w2 + kk * kH + m] : 0.0f);   // W2^T[m][kk] = W2[kk][m]
         if (m < kP) d.w3[e] = bf(m < nout && kk < kH ? p[o.w3 + m * kH + kk] : 0.0f);
     }
     if (e < 2 * kH + kP) {
@@ -645,13 +646,73 @@ __global__ __launch_bounds__(kBlock) void k_sur_classify(const StepArgs<float> a
             su.acc_list[base + below] = t;
         }
     }
-    if (valid && !ok) update_voxel<float, M>(a, t, idx, Vp, LV);
+    if (valid && !ok) update_voxel<float, M>(a, step_clock(a), t, idx, Vp, LV);
+}
+
+// Hand-over of LDS data between the lanes of one wave: the writes before it are
+// visible to every lane's reads after it (a wave's LDS accesses complete in order).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// SiLU of the 32 pre-activations z[0..7] of one layer into next-layer B fragments
+// h[ks] = units {4g..4g+3 of tile 2ks, 4g..4g+3 of tile 2ks+1}: each stage runs over all 32
+// values before the next, so the transcendental latencies overlap.
+__device__ __forceinline__ void silu_layer(const f4v z[8], bf8 h[4])
+{
+    float e[32];
+#pragma unroll
+    for (int k = 0; k < 32; k++) e[k] = __expf(-z[k >> 2][k & 3]);
+#pragma unroll
+    for (int k = 0; k < 32; k++) e[k] = __builtin_amdgcn_rcpf(1.0f + e[k]);
+#pragma unroll
+    for (int ks = 0; ks < 4; ks++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            h[ks][i] = bf(z[2 * ks][i] * e[8 * ks + i]);
+            h[ks][4 + i] = bf(z[2 * ks + 1][i] * e[8 * ks + 4 + i]);
+        }
+}
+
+// Inference pass of one 16-sample tile (fwd_tile without the saved pre-activations).
+__device__ __forceinline__ void infer_tile(const MlpLds &W, bf8 x, f4v out[2])
+{
+    const int l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+    f4v z[8];
+    bf8 h[4];
+#pragma unroll
+    for (int mt = 0; mt < 8; mt++)
+        z[mt] = mfma(ld8(W.w1 + (16 * mt + j) * kS1 + 8 * g), x, *(const f4v *)(W.bias + 16 * mt + 4 * g));
+    silu_layer(z, h);
+#pragma unroll
+    for (int mt = 0; mt < 8; mt++) {
+        f4v acc = *(const f4v *)(W.bias + kH + 16 * mt + 4 * g);
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+            acc = mfma(ld8(W.w2 + (16 * mt + j) * kS2 + 32 * ks + 8 * g), h[ks], acc);
+        z[mt] = acc;
+    }
+    silu_layer(z, h);
+#pragma unroll
+    for (int mt = 0; mt < 2; mt++) {
+        f4v acc = *(const f4v *)(W.bias + 2 * kH + 16 * mt + 4 * g);
+#pragma unroll
+        for (int ks = 0; ks < 4; ks++)
+            acc = mfma(ld8(W.w3 + (16 * mt + j) * kS2 + 32 * ks + 8 * g), h[ks], acc);
+        out[mt] = acc;
+    }
 }
 
 template <class M, bool ANISO>
 __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, const SurArgs su)
 {
+    constexpr int NV = M::NV;
+    static_assert(NV <= kSurRow, "a voxel's outputs must fit in its staging row");
     const int n = su.acc_cnt[su.parity];
+    const Clock<float> ck = step_clock(a);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         // input-rejected voxels were updated by the classifier; the next step's list
         // (other parity) starts empty
@@ -666,14 +727,18 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
     constexpr int NW = kSurBlock / 64;
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
     __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
-    __shared__ __attribute__((aligned(16))) __bf16 xin[NW][64 * kS1];   // inputs, one row per voxel
-    __shared__ float oout[NW][16 * kOS];                                 // outputs of one tile
-    // persistent workgroups: stage the weights once, then walk the voxel chunks
+    // one staging row per voxel: its normalised input (kP BF16 values) before the
+    // network, its FP32 output increments after
+    __shared__ __attribute__((aligned(16))) float rows[NW][64 * kSurRow];
+    // persistent workgroups: stage the weights once, then walk the voxel chunks; after
+    // this barrier the waves run independently (each uses only its own rows), so one
+    // wave's gathers overlap another's network
     stage_weights(su.net, w1, w2, w3, nullptr, nullptr, bias);
+    __syncthreads();
     const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
-    constexpr int NV = M::NV;
     const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
     const float *nrm = su.net.norm;
+    float *wrows = rows[wv];
 
     const int nwave = (int)gridDim.x * NW, gw = wv * (int)gridDim.x + (int)blockIdx.x;
     const int iters = (n + 64 * nwave - 1) / (64 * nwave);          // uniform over the grid
@@ -681,59 +746,54 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
         const int k = (it * nwave + gw) * 64 + l;
         const bool valid = k < n;
         const int t = valid ? su.acc_list[k] : 0;
+        // only what the update needs after the network stays in registers; the gates
+        // are read again afterwards (from cache)
         int idx = 0;
-        float Vp = 0.f, LV = 0.f, Is = 0.f;
-        float s[NV] = {};
-        bool ok = valid;                                   // the input box was checked
-        __bf16 *xrow = xin[wv] + l * kS1;
+        float Vp = 0.f, LV = 0.f, Is = 0.f, s0 = 0.f;
+        __bf16 xr[kP];
+#pragma unroll
+        for (int f = 0; f < kP; f++) xr[f] = bf(0.0f);
         if (valid) {
             uint32_t bits;
             voxel_of(a, t, idx, bits);
             Vp = a.Vin[idx];
             LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-            Is = stim_current(a, t);
-            s[0] = a.split ? Vp + a.dt * LV : Vp;
+            Is = stim_current(a, t, ck.stim_on);
+            s0 = a.split ? Vp + a.dt * LV : Vp;
+            xr[0] = bf((s0 - nrm[0]) * nrm[kP]);
 #pragma unroll
-            for (int i = 1; i < NV; i++) s[i] = a.st[(i - 1) * a.pitch + t];
+            for (int i = 1; i < NV; i++) xr[i] = bf((a.st[(i - 1) * a.pitch + t] - nrm[i]) * nrm[kP + i]);
         }
-        __syncthreads();                                       // previous chunk done with LDS
+        float *row = wrows + l * kSurRow;
+        wave_sync();                                           // the previous chunk's outputs read
 #pragma unroll
-        for (int f = 0; f < NV; f++) xrow[f] = bf(valid ? (s[f] - nrm[f]) * nrm[kP + f] : 0.0f);
-#pragma unroll
-        for (int f = NV; f < kP; f++) xrow[f] = bf(0.0f);
-        __syncthreads();                                       // weights and inputs staged
+        for (int q = 0; q < kP / 8; q++) *(bf8 *)((__bf16 *)row + 8 * q) = *(const bf8 *)(xr + 8 * q);
+        wave_sync();                                           // the wave's inputs staged
 
-        float *os = oout[wv];
-        float d[NV] = {};
-        const uint64_t want = __ballot(ok);                    // voxels still accepted
+        const uint64_t want = __ballot(valid);
 #pragma unroll 1
         for (int T = 0; T < 4; T++) {
-            if (((want >> (16 * T)) & 0xFFFFull) == 0) continue;    // whole tile rejected
-            const bf8 x = ld8(xin[wv] + (16 * T + j) * kS1 + 8 * g);
-            f4v out[2], z1[8], z2[8];
-            bf8 h1[4], h2[4];
-            fwd_tile(W, x, out, z1, z2, h1, h2);
+            if (((want >> (16 * T)) & 0xFFFFull) == 0) continue;    // no voxel in this tile
+            float *trow = wrows + (16 * T + j) * kSurRow;
+            const bf8 x = ld8((const __bf16 *)trow + 8 * g);
+            f4v out[2];
+            infer_tile(W, x, out);
+            wave_sync();                                       // the tile's inputs all read
+            // output unit 16 mt + 4 g + i of sample j over the input row it came from
 #pragma unroll
             for (int mt = 0; mt < 2; mt++)
-#pragma unroll
-                for (int i = 0; i < 4; i++) os[j * kOS + 16 * mt + 4 * g + i] = out[mt][i];
-            // wave-internal hand-over: the LDS writes above precede these reads in the
-            // wave's in-order LDS queue
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if ((l >> 4) == T)
-#pragma unroll
-                for (int i = 0; i < NV; i++) d[i] = os[j * kOS + i];
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                if (16 * mt + 4 * g < NV) *(f4v *)(trow + 16 * mt + 4 * g) = out[mt];
         }
+        wave_sync();                                           // outputs staged
         if (!valid) continue;
 
+        float d[NV], s[NV];
+        bool ok = true;                                        // the input box was checked
+        s[0] = s0;
 #pragma unroll
         for (int i = 0; i < NV; i++) {
-            d[i] = d[i] * nrm[3 * kP + i] + nrm[2 * kP + i];
+            if (i > 0) s[i] = a.st[(i - 1) * a.pitch + t];
+            d[i] = row[i] * nrm[3 * kP + i] + nrm[2 * kP + i];
             ok = ok && isfinite(d[i]);
         }
         ok = ok && fabsf(d[0]) <= su.dv_max;
@@ -748,7 +808,7 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
         if (rej) {
             if (l == __ffsll((unsigned long long)rej) - 1) atomicAdd(su.fb_total, (unsigned long long)__popcll(rej));
             if (!ok) {
-                update_voxel<float, M>(a, t, idx, Vp, LV);
+                update_voxel<float, M>(a, ck, t, idx, Vp, LV);
                 continue;
             }
         }
@@ -759,7 +819,7 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
             a.st[(i - 1) * a.pitch + t] = i >= M::GATE0 ? fminf(fmaxf(y, 0.0f), 1.0f) : y;
         }
         a.Vout[idx] = Vn;
-        record_voxel(a, t, Vp, Vn);
+        record_voxel(a, t, Vp, Vn, ck.tn);
     }
 }
 
@@ -791,13 +851,27 @@ __global__ void k_ionic(const StepArgs<float> a, const float *in, int64_t n, flo
     for (int i = 1; i < NV; i++) out[k * NV + i] = g[i - 1];
 }
 
+// Compute-unit count of the current device, queried once per device (the network launch
+// takes one persistent workgroup per CU).
+static int cu_count()
+{
+    constexpr int kMaxDev = 64;
+    static int cache[kMaxDev];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDev) return 256;
+    if (cache[dev] == 0) {
+        int n = 0;
+        cache[dev] = hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                             n > 0 ? n : 256;
+    }
+    return cache[dev];
+}
+
 template <class M>
 static hipError_t sur_m(int aniso, const StepArgs<float> &a, const SurArgs &su, hipStream_t s)
 {
-    int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (a.nact == 0) return hipSuccess;
+    const int ncu = cu_count();
     const dim3 gc((unsigned)(a.per_xcd * kXcd)), bc(kBlock);
     if (aniso) hipLaunchKernelGGL((k_sur_classify<M, true>), gc, bc, 0, s, a, su);
     else hipLaunchKernelGGL((k_sur_classify<M, false>), gc, bc, 0, s, a, su);

@@ -79,20 +79,51 @@ __device__ __forceinline__ void record_event(const A &a, I t, T tn, T Vp, T Vn)
     if (s != s0) a.status[t] = s;
 }
 
+// The step's clock: the stimuli that are on and t_n.  Host-evaluated for direct
+// launches; in a replayed graph read from the device step counter (same arithmetic as
+// the host: windows in whole steps, t_n = n dt rounded from FP64).
 template <typename T>
-__device__ __forceinline__ void record_voxel(const StepArgs<T> &a, int t, T Vp, T Vn)
+struct Clock {
+    uint32_t stim_on;
+    T tn;
+};
+
+template <typename T>
+__device__ __forceinline__ Clock<T> step_clock(const StepArgs<T> &a)
+{
+    if (!a.nbase) return {a.stim_on, a.tn};
+    const int64_t n = *a.nbase + a.jstep;
+    uint32_t on = 0;
+    for (int s = 0; s < a.nstim; s++) {
+        const StimWin w = a.win[s];
+        if (n < w.n0 || w.len <= 0) continue;
+        const int64_t r = n - w.n0;
+        bool hit;
+        if (w.per <= 0) {
+            hit = r < w.len;
+        } else {
+            const int64_t c = r / w.per;
+            hit = !(w.count > 0 && c >= w.count) && (r - c * w.per) < w.len;
+        }
+        if (hit) on |= 1u << s;
+    }
+    return {on, (T)((double)n * a.dt64)};
+}
+
+template <typename T>
+__device__ __forceinline__ void record_voxel(const StepArgs<T> &a, int t, T Vp, T Vn, T tn)
 {
     if (!a.rec) return;
-    record_event(a, t, a.tn, Vp, Vn);
+    record_event(a, t, tn, Vp, Vn);
 }
 
 // Stimulus current of tissue voxel t at this step.
 template <typename T>
-__device__ __forceinline__ T stim_current(const StepArgs<T> &a, int t)
+__device__ __forceinline__ T stim_current(const StepArgs<T> &a, int t, uint32_t stim_on)
 {
     T Is = T(0);
-    if (a.stim_on) {
-        const uint32_t sb = a.stimbits[t] & a.stim_on;
+    if (stim_on) {
+        const uint32_t sb = a.stimbits[t] & stim_on;
         for (int s = 0; s < a.nstim; s++)
             if ((sb >> s) & 1u) Is += a.stim_amp[s];
     }
@@ -171,9 +202,10 @@ __device__ __forceinline__ T rk4_voxel(const StepArgs<T> &a, T V0, T *g, T F)
 // the recorder.  RK4: the kinetics take the fourth-order Runge-Kutta step instead of
 // forward Euler / Rush-Larsen.
 template <typename T, class M, bool NT = false, bool RK4 = false>
-__device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int idx, T Vp, T LV)
+__device__ __forceinline__ void update_voxel(const StepArgs<T> &a, const Clock<T> &ck, int t, int idx,
+                                             T Vp, T LV)
 {
-    const T Is = stim_current(a, t);
+    const T Is = stim_current(a, t, ck.stim_on);
 
     T g[M::NV > 1 ? M::NV - 1 : 1];
 #pragma unroll
@@ -199,7 +231,7 @@ __device__ __forceinline__ void update_voxel(const StepArgs<T> &a, int t, int id
     else
         a.Vout[idx] = Vn;
 
-    record_voxel(a, t, Vp, Vn);
+    record_voxel(a, t, Vp, Vn, ck.tn);
 }
 
 }  // namespace bbx

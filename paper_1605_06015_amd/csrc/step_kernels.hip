@@ -61,7 +61,7 @@ __global__ __launch_bounds__(NT ? kStreamBlock : kBlock) void k_step(const StepA
     voxel_of(a, t, idx, bits);         // dense boxes keep no index / bit arrays
     const T Vp = a.Vin[idx];
     const T LV = laplacian<T, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
-    update_voxel<T, M, NT, RK4>(a, t, idx, Vp, LV);
+    update_voxel<T, M, NT, RK4>(a, step_clock(a), t, idx, Vp, LV);
 }
 
 // Dense-box path (every voxel is tissue): a workgroup owns a 64 x 4 column tile
@@ -118,6 +118,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
     __shared__ T ring[3][kPlane];
     const int lb = workgroup_tile<NT, 64>(a);
     if (lb >= a.nblk) return;                       // workgroup-uniform exit
+    const Clock<T> ck = step_clock(a);
     const int bx = lb % a.gx, r = lb / a.gx;
     const int by = r % a.gy, bz = r / a.gy;
     const int z0 = bz * a.zc, z1 = min(a.nz, z0 + a.zc);
@@ -168,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_step_dense(const StepArgs<T> a)
             const bool full = xy_in && z > 0 && z + 1 < a.nz;
             const T LV = full ? laplacian_lds<T, ANISO, true>(a, Pm, Pc, Pp, c, geo, bits, Vp)
                               : laplacian_lds<T, ANISO, false>(a, Pm, Pc, Pp, c, geo, bits, Vp);
-            update_voxel<T, M, NT>(a, idx, idx, Vp, LV);
+            update_voxel<T, M, NT>(a, ck, idx, idx, Vp, LV);
         }
         __syncthreads();                                   // slot of plane z-1 is free
         if (pre) {
@@ -189,6 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
 {
     const int lb = workgroup_tile<NT, 1>(a);
     if (lb >= a.nblk) return;
+    const Clock<T> ck = step_clock(a);
     const int bx = lb % a.gx, r = lb / a.gx;
     const int by = r % a.gy, bz = r / a.gy;
     const int z0 = bz * a.zc, z1 = min(a.nz, z0 + a.zc);
@@ -210,7 +212,7 @@ __global__ __launch_bounds__(kBlock) void k_step_zreg(const StepArgs<T> a)
         const T ny_ = py ? N - Vc : T(0), sy_ = my ? S - Vc : T(0);
         const T up = pz ? Vq - Vc : T(0), dnv = mz ? Vm - Vc : T(0);
         const T LV = a.Dperp * a.ih2 * ((ex_ + wx) + (ny_ + sy_) + (up + dnv));
-        update_voxel<T, M, NT>(a, idx, idx, Vc, LV);
+        update_voxel<T, M, NT>(a, ck, idx, idx, Vc, LV);
         Vm = Vc;
         Vc = Vq;
         Vq = Vnext;

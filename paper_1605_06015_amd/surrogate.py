@@ -70,16 +70,29 @@ def generate_pairs(nx=128, ny=128, nz=64, runs=3, t_ms=1200.0, every_ms=1.0, per
     return S[:k], S1[:k]
 
 
+# Learning-rate schedules of the benchmark's surrogates: (Adam steps, learning rate)
+# stages.  Measured on the held-out cups: for CRN a single stage at 1e-3 (20,000 steps)
+# leaves a network that meets the 1-dt activation-time bar only below the resting
+# potential (0.01% of the voxel updates), and stepping the rate down to 3e-5 lets it take
+# 1.9% at 0.26 dt; for TP06 the same steps made the network worse near rest (2.5% of
+# the updates at 1.35 dt against 1.7% at 0.76 dt with the single stage).
+SCHEDULES = {"crn": ((20000, 1e-3), (15000, 3e-4), (15000, 1e-4), (10000, 3e-5)),
+             "tp06": ((20000, 1e-3),)}
+
+
 def train(S, S1, iters=20000, batch=4096, lr=1e-3, seed=0, stream=None, anchor_grid=None,
-          model="crn"):
-    """Fit the normalisation and train an nvar -> 128 -> 128 -> nvar network.  If
-    anchor_grid is given (a grid with the plain kinetics of `model`), the network is
-    anchored so that the published resting state is an exact fixed point."""
+          model="crn", schedule=None):
+    """Fit the normalisation and train an nvar -> 128 -> 128 -> nvar network: `iters` Adam
+    steps at `lr`, or the stages of `schedule` one after the other (Adam moments carried
+    over).  If anchor_grid is given (a grid with the plain kinetics of `model`), the
+    network is anchored so that the published resting state is an exact fixed point."""
     import torch
     _, nv, _, _, rest, _, _ = _model_setup(model)
     m = B.Mlp(nv, nv, seed=seed, stream=stream)
     stats = m.fit_norm(S, S1)
-    hist = m.train(S, S1, batch, iters, lr, seed=seed + 1)
+    stages = schedule if schedule is not None else ((iters, lr),)
+    hist = np.concatenate([m.train(S, S1, batch, it, r, seed=seed + 1 + k)
+                           for k, (it, r) in enumerate(stages)])
     if anchor_grid is not None:
         s0 = torch.tensor([rest], dtype=torch.float32, device="cuda")
         s1 = torch.empty_like(s0)
@@ -166,12 +179,12 @@ def run_pair(trained, model, geo_seed, nx=96, ny=96, nz=48, t_ms=500.0, v_his=()
     return plain, res, c["dt"]
 
 
-def select_threshold(trained, model, geo_seed=11, margin=0.5, offsets=(-0.2, -0.1, -0.05, -0.02,
+def select_threshold(trained, model, geo_seed=11, margin=1.0, offsets=(-0.2, -0.1, -0.05, -0.02,
                      -0.01, 0.0, 0.01), stream=None):
     """Acceptance threshold v_hi chosen on a held-out cup (geometry seed geo_seed, not the
     benchmark's): among rest + offsets (mV), the one with the largest surrogate share whose
-    activation times stay within margin * dt of the plain run's on every voxel, with the
-    same activated set.  Returns (v_hi or None, the sweep)."""
+    activation times stay within margin * dt of the plain run's on every voxel (the 1-dt
+    bar), with the same activated set.  Returns (v_hi or None, the sweep)."""
     rest = _model_setup(model)[4][0]
     cands = [round(rest + o, 4) for o in offsets]
     _, sweep, dt = run_pair(trained, model, geo_seed, v_his=cands, stream=stream)

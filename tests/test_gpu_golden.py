@@ -192,3 +192,74 @@ def test_fk4_ensemble_full_protocol_against_oracle_maps():
     dapd = np.abs(apd[fp] - apd_o[fp]).max()
     print(f"fk4 ensemble tissue {i}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
     assert dat <= c["dt"] + 1e-9 and dapd <= 0.75, (dat, dapd)
+
+
+SHELL_MAPS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tp06_shell128_at_apd.csv")
+SHELL_TRACES = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tp06_shell128_traces.npz")
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_tp06_shell_s1s2_protocol_against_oracle(prec):
+    """The TP06 S1-S2 protocol on the down-scaled double shell (128x128x96, 600 ms; the
+    S2 wave meets refractory tissue and dies out) against the FP64 oracle's stored
+    results (tests/golden/tp06_shell128_*, made by make_tp06_shell_maps.py): first
+    activation times and APD90 at 4,000 voxels, V at 1,000 voxels every 2 ms, and the
+    pseudo-ECG at eight electrodes every 10 ms.
+    FP64: AT / APD90 within 2e-6 ms, |dV| <= 1e-4 mV (float32 storage), ECG within
+    1e-7 of its largest magnitude.  FP32: AT within 1 dt, APD90 within 0.5 ms (voxels whose
+    S1 beat repolarised before S2), |dV| <= 0.5 mV at every sample, ECG within 1e-2 of its
+    largest magnitude."""
+    import torch
+    from paper_1605_06015_amd import bbx as B
+    c = WL.TP06_3D_SMALL
+    d = np.loadtxt(SHELL_MAPS, delimiter=",", skiprows=2)
+    idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
+    tr = np.load(SHELL_TRACES)
+    tidx, V_o, ecg_o = tr["idx"], tr["V"].astype(np.float64), tr["ecg"]
+    every = int(round((tr["t_ms"][1] - tr["t_ms"][0]) / c["dt"]))
+    ecg_every = int(round((tr["ecg_t_ms"][1] - tr["ecg_t_ms"][0]) / c["dt"]))
+    g3 = WL.tp06_biv(c["nx"], c["ny"], c["nz"], c["h"], c["seed"], c["active"], c["s1_strip"])
+    grid = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], prec)
+    grid.model(B.BBX_MODEL_TP06, [], c["dt"])
+    for v, val in enumerate(WL.TP06_INITIAL):
+        grid.fill(v, val)
+    grid.stimulus(g3["s1"], c["s1_amp"], 0.0, c["s1_ms"])
+    grid.stimulus(g3["s2"], c["s2_amp"], c["s2_t"], c["s2_ms"])
+    grid.record(c["theta"])
+    grid.ecg(g3["electrodes"], every=ecg_every, max_samples=1000)
+    buf = torch.empty(g3["mask"].size, dtype=torch.float64, device="cuda")
+    sel = torch.from_numpy(tidx).cuda()
+    Vg = []
+    for _ in range(V_o.shape[0]):
+        grid.step(every)
+        B.bbx_readout(grid.handle, B.BBX_READ_VAR, 0, None, buf.data_ptr(), buf.numel() * 8, 1)
+        Vg.append(buf[sel].cpu().numpy())
+    Vg = np.array(Vg)
+    ecg = grid.ecg_series()
+    at = grid.read(B.BBX_READ_ACT_TIME).ravel()[idx]
+    apd = grid.read(B.BBX_READ_APD90).ravel()[idx]
+    assert np.isfinite(at_o).mean() > 0.9
+    assert np.array_equal(np.isnan(at), np.isnan(at_o))
+    assert np.array_equal(np.isnan(apd), np.isnan(apd_o))
+    fa, fp = np.isfinite(at_o), np.isfinite(apd_o)
+    # APD90 of the S1 beat is well defined where that beat has repolarised before S2 (2 ms
+    # margin); a voxel still near its 90% level when S2 arrives may cross it before or
+    # after its second upstroke, a difference a rounding of V can decide
+    s1 = fp & (at_o + apd_o < c["s2_t"] - 2.0)
+    dat, dapd = np.abs(at[fa] - at_o[fa]).max(), np.abs(apd[s1] - apd_o[s1]).max()
+    dapd_all = np.abs(apd[fp] - apd_o[fp])
+    dV = np.abs(Vg - V_o)
+    assert ecg.shape == ecg_o.shape, (ecg.shape, ecg_o.shape)
+    decg = np.abs(ecg - ecg_o).max() / np.abs(ecg_o).max()
+    # the S2 response: part of the traced voxels activate a second time after 310 ms
+    late = (tr["t_ms"] > c["s2_t"])[:, None] & (V_o > -40.0)
+    print(f"prec {prec}: |dAT| {dat:.3g} ms, |dAPD90| {dapd:.3g} ms on {int(s1.sum())} voxels repolarised "
+          f"before S2 (all {fp.sum()}: max {dapd_all.max():.3g}, > 0.5 ms at {(dapd_all > 0.5).sum()}), "
+          f"|dV| max {dV.max():.3g} mV, ECG rel {decg:.3g}; voxels re-excited by S2: "
+          f"{int(late.any(axis=0).sum())}")
+    assert s1.sum() > 0.35 * fp.sum()                  # 1,745 of 4,000 in the stored run
+    assert late.any(axis=0).sum() > 0
+    if prec == 1:
+        assert dat <= 2e-6 and dapd <= 2e-6 and dV.max() <= 1e-4 and decg <= 1e-7
+    else:
+        assert dat <= c["dt"] + 1e-9 and dapd <= 0.5 and dV.max() <= 0.5 and decg <= 1e-2

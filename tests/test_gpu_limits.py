@@ -100,7 +100,7 @@ def test_ensemble_at_voxel_limit_last_tissue_matches_alone():
         assert np.array_equal(full[v], alone[v]), v
 
 
-@pytest.mark.parametrize("aniso", [True, False])
+@pytest.mark.parametrize("aniso", ["random", "rotating", False])
 def test_dense_box_beyond_cache_streaming_kernels_sampled(aniso):
     """A dense 512x512x264 box (277 MB of V in FP32, above the 256 MB Infinity Cache, so
     the streaming instantiations of the z-marching kernels run: the LDS ring with rotating
@@ -114,6 +114,10 @@ def test_dense_box_beyond_cache_streaming_kernels_sampled(aniso):
     mask, fib = WL.full_box_rotating(nx, ny, nz)
     if not aniso:
         fib = None
+    elif aniso == "random":
+        # fibres varying in every direction: the tensor-gradient coefficients the kernel
+        # rebuilds are nonzero everywhere (rotating in z alone they vanish)
+        fib = WL.random_fibres(mask.shape, seed=17)
     z, y, x = np.ogrid[0:nz, 0:ny, 0:nx]
     V = -60.0 + 20.0 * np.sin(0.05 * x + 0.3) * np.cos(0.07 * y) + 10.0 * np.sin(0.11 * z)
     g = B.Grid(mask, h, fib, Dpar, Dperp, B.BBX_FP32)

@@ -309,17 +309,30 @@ def test_single_voxel_matches_oracle_cell():
     assert np.all(rel_errs(gpu_state(g, 21), s.state, mask) <= TOL64)
 
 
-@pytest.mark.parametrize("aniso", [False, True])
-def test_dense_box_fp64(aniso):
-    mask, fib = WL.full_box_rotating(21, 13, 7)
+@pytest.mark.parametrize("fibres", ["none", "rotating", "random", "random_2d"])
+@pytest.mark.parametrize("prec", [1, 0])
+def test_dense_box_light_model(fibres, prec):
+    """Dense boxes with a light model take the z-marching kernels (register march when
+    isotropic; LDS rings of V and of fibre products when anisotropic, the face
+    coefficients of the tensor-gradient term rebuilt in the kernel).  Fibres rotating
+    in z only leave those coefficients zero; random fibres exercise them everywhere,
+    including the box faces.  FP64 <= 1e-10 normwise; FP32 <= 1e-5 normwise."""
+    shape = (1, 37, 45) if fibres == "random_2d" else (7, 13, 21)
+    nz, ny, nx = shape
+    mask, fib = WL.full_box_rotating(nx, ny, nz)
+    if fibres.startswith("random"):
+        fib = WL.random_fibres(mask.shape, seed=43)
+    elif fibres == "none":
+        fib = None
     rng = np.random.default_rng(41)
     V0 = rng.uniform(0, 1, mask.shape)
-    p = Problem(mask, 0.5, fib if aniso else None, 1.0, 0.3, O.MODEL_ZFK, [0.13], 0.02,
-                state=V0[None])
+    p = Problem(mask, 0.5, fib, 1.0, 0.3, O.MODEL_ZFK, [0.13], 0.02, state=V0[None])
     s = run_oracle(p, 200)
-    g = make_gpu(p, 1)
+    g = make_gpu(p, prec)
     g.step(200)
-    assert rel_errs(gpu_state(g, 1), s.state, mask)[0] <= TOL64
+    e = rel_errs(gpu_state(g, 1), s.state, mask)[0]
+    print(fibres, prec, "normwise error", e)
+    assert e <= (TOL64 if prec == 1 else 1e-5)
 
 
 @pytest.mark.parametrize("prec,tol", [(1, TOL64), (0, None)])
