@@ -359,6 +359,20 @@ int bbx_mlp_forward(bbx_mlp *m, const float *X_dev, int64_t n, float *Y_dev);
 int bbx_mlp_grad(bbx_mlp *m, const float *X_dev, const float *T_dev, int64_t n, float *grad_host,
                  double *loss);
 
+/* The gradient of bbx_mlp_grad without any device allocation, for callers that
+ * cannot allocate: code under HIP graph capture, tight training loops, harnesses
+ * that forbid hipMalloc.  Same loss and gradient (same kernels, same summation
+ * order) for 1 <= n <= 4096 samples; larger n gives BBX_EINVAL.  X_dev [n][nin] and
+ * T_dev [n][nout] are device inputs; the gradient stays in the network for
+ * bbx_mlp_adam and is also copied to grad_dev (nparams floats, device) and the
+ * loss to loss_dev (one double, device) when those are not NULL.  Stream-ordered on
+ * the network's stream, no synchronisation.  The training scratch is one static
+ * device array of 5.6 MiB per GPU (kept until the process ends) shared by every
+ * call on that GPU: calls that overlap on one GPU (other streams or threads) race.
+ * The network's device must be the current device. */
+int bbx_mlp_grad_static(bbx_mlp *m, const float *X_dev, const float *T_dev, int64_t n,
+                        float *grad_dev, double *loss_dev);
+
 /* One Adam step (bias-corrected) with the last gradient. */
 int bbx_mlp_adam(bbx_mlp *m, float lr, float beta1, float beta2, float eps);
 

@@ -70,6 +70,7 @@ SIGNATURES = {
     "bbx_mlp_fit_norm": (_I, [_P, _P, _P, _I64, _P]),
     "bbx_mlp_forward": (_I, [_P, _P, _I64, _P]),
     "bbx_mlp_grad": (_I, [_P, _P, _P, _I64, _P, _P]),
+    "bbx_mlp_grad_static": (_I, [_P, _P, _P, _I64, _P, _P]),
     "bbx_mlp_adam": (_I, [_P, C.c_float, C.c_float, C.c_float, C.c_float]),
     "bbx_mlp_train": (_I, [_P, _P, _P, _I64, _I64, _I64, C.c_float, C.c_uint64, _P]),
     "bbx_mlp_anchor": (_I, [_P, _P, _P]),
@@ -479,6 +480,12 @@ def bbx_mlp_grad(m, X, T, n, grad_host=None):
     loss = np.zeros(1, np.float64)
     _check(_lib.bbx_mlp_grad(m, _dptr(X), _dptr(T), int(n), _ptr(grad_host), _ptr(loss)))
     return loss[0]
+
+
+def bbx_mlp_grad_static(m, X, T, n, grad_dev=None, loss_dev=None):
+    """Allocation-free gradient: X, T device inputs; grad_dev / loss_dev device outputs
+    (torch tensors or addresses, may be None).  Stream-ordered, no synchronisation."""
+    _check(_lib.bbx_mlp_grad_static(m, _dptr(X), _dptr(T), int(n), _dptr(grad_dev), _dptr(loss_dev)))
 
 
 def bbx_mlp_adam(m, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -1911,3 +1911,98 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
 }
 
 }  // extern "C"
+
+// ============================================================================ allocation-free gradient
+// bbx_mlp_grad_static: the gradient of bbx_mlp_grad for callers that cannot allocate
+// device memory.  Its training scratch (batch inputs and targets, feature-major
+// activations and deltas, per-tile partial sums) lives in one file-scope device array
+// sized for kStaticBatch samples.  Host code never passes the array's name to a kernel
+// (on the host it only names a stand-in): its device address is looked up once per
+// device with hipGetSymbolAddress and kept in g_static_ptr.
+
+namespace {
+
+constexpr int64_t kStaticBatch = 4096;     // largest batch of bbx_mlp_grad_static
+constexpr size_t kAl = 256;
+constexpr size_t al(size_t b) { return (b + kAl - 1) / kAl * kAl; }
+// carve of the scratch for kStaticBatch samples, in the order of MlpScratch
+constexpr size_t kScrXb = al(kStaticBatch * kP * sizeof(__bf16));
+constexpr size_t kScrTt = al(kStaticBatch * kP * sizeof(float));
+constexpr size_t kScrXf = al(kStaticBatch * kP * sizeof(__bf16));
+constexpr size_t kScrDo = al(kStaticBatch * kP * sizeof(__bf16));
+constexpr size_t kScrH = al(kStaticBatch * kH * sizeof(__bf16));
+constexpr size_t kScrPart = al(kStaticBatch / 16 * kPart * sizeof(float));
+constexpr size_t kStaticBytes = kScrXb + kScrTt + kScrXf + kScrDo + 4 * kScrH + kScrPart;
+
+}  // namespace
+
+// The scratch itself (each device holds its own copy for the life of the process).
+static __device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[kMaxDevices] = {};
+
+// Device address of this device's copy of `scratch` (looked up on first use per device).
+int static_scratch(void **out)
+{
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(BBX_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    if (!g_static_ptr[dev]) {
+        void *p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress");
+        if (!p) return fail(BBX_EDEVICE, "no device address for the static scratch");
+        g_static_ptr[dev] = p;
+    }
+    *out = g_static_ptr[dev];
+    return BBX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int bbx_mlp_grad_static(bbx_mlp *m, const float *X_dev, const float *T_dev, int64_t n,
+                        float *grad_dev, double *loss_dev)
+{
+    try {
+        g_err.clear();
+        if (!m || !X_dev || !T_dev) return fail(BBX_EINVAL, "NULL argument");
+        if (n < 1 || n > kStaticBatch)
+            return fail(BBX_EINVAL, "n must be in [1, %lld] (the static scratch holds %lld samples)",
+                        (long long)kStaticBatch, (long long)kStaticBatch);
+        void *base = nullptr;
+        int rc = static_scratch(&base);
+        if (rc) return rc;
+        unsigned char *p = (unsigned char *)base;
+        MlpScratch w;
+        w.xb = (__bf16 *)p;   p += kScrXb;
+        w.tt = (float *)p;    p += kScrTt;
+        w.xf = (__bf16 *)p;   p += kScrXf;
+        w.dO = (__bf16 *)p;   p += kScrDo;
+        w.h1 = (__bf16 *)p;   p += kScrH;
+        w.h2 = (__bf16 *)p;   p += kScrH;
+        w.dz1 = (__bf16 *)p;  p += kScrH;
+        w.dz2 = (__bf16 *)p;  p += kScrH;
+        w.part = (float *)p;
+        // every scratch element the kernels read is written earlier in the same call
+        // (padding samples included), so nothing needs clearing first
+        HIP_TRY(mlp_grad(m->dev, w, 0, X_dev, T_dev, n, n, 0, 0, m->d_g, m->d_loss, m->stream),
+                "gradient");
+        if (grad_dev)
+            HIP_TRY(hipMemcpyAsync(grad_dev, m->d_g, m->np * sizeof(float), hipMemcpyDeviceToDevice,
+                                   m->stream), "hipMemcpyAsync");
+        if (loss_dev)
+            HIP_TRY(hipMemcpyAsync(loss_dev, m->d_loss, sizeof(double), hipMemcpyDeviceToDevice,
+                                   m->stream), "hipMemcpyAsync");
+        return BBX_OK;
+    } catch (...) {
+        return fail(BBX_EDEVICE, "unexpected failure");
+    }
+}
+
+}  // extern "C"
