@@ -294,8 +294,9 @@ int bbx_clock_set(bbx_grid *g, int64_t step);
  * graph's last node) and evaluate their stimulus windows and t_n from it with the host's
  * arithmetic, so results are bitwise those of direct launches.  Graphs are captured on
  * first use and dropped by any call that changes what a step does (model, stimuli,
- * recording, tabulation, integrator, this call).  Steps stay direct while a surrogate is
- * attached or pseudo-ECG samples are being taken; with the finite check on, it runs after
+ * recording, tabulation, integrator, surrogate attach or detach, this call).  With a
+ * surrogate attached the graph holds both of its launches per step.  Steps stay direct
+ * while pseudo-ECG samples are being taken; with the finite check on, it runs after
  * each chunk that crosses a multiple of its interval.  Errors: BBX_EINVAL (chunk),
  * BBX_ENOTSUP (a grid created on the null stream: capture needs a stream of its own). */
 int bbx_graph_set(bbx_grid *g, int chunk);

@@ -127,8 +127,9 @@ struct bbx_grid {
     MlpDev snet = {};
     float *d_slo = nullptr, *d_shi = nullptr;
     float dv_max = 0;
-    int32_t *d_acc_list = nullptr, *d_acc_cnt = nullptr;   // network list, lengths [2]
-    unsigned long long *d_fb_total = nullptr;
+    int32_t *d_acc_list = nullptr, *d_acc_cnt = nullptr;   // network list segments, lengths
+    unsigned long long *d_fb = nullptr;                      // fallback counts per segment
+    int sur_nblk = 0;                                        // list segments (classifier workgroups)
     double *d_parts = nullptr, *d_red = nullptr;
     int *d_flag = nullptr;
     // pseudo-ECG sampling
@@ -189,7 +190,7 @@ void free_all(bbx_grid *g)
     void *ps[] = {g->d_idx, g->d_nbr, g->d_geo, g->d_V[0], g->d_V[1], g->d_st,
                   g->d_stimbits, g->d_stimamp, g->d_status, g->d_at, g->d_vmax, g->d_apd,
                   g->d_vrep, g->d_parts, g->d_red, g->d_flag, g->d_slo, g->d_shi,
-                  g->d_acc_list, g->d_acc_cnt, g->d_fb_total, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
+                  g->d_acc_list, g->d_acc_cnt, g->d_fb, g->d_tab, g->d_ecg_series, g->d_ecg_parts, g->d_ecg_now, g->snet.w1, g->snet.w2, g->snet.w3,
                   g->snet.bias, g->snet.norm, g->d_send[0], g->d_send[1], g->d_recv[0],
                   g->d_recv[1], g->d_map, g->d_nbase, g->d_win};
     for (void *p : ps) dfree(p);
@@ -310,7 +311,7 @@ int build_table(bbx_grid *g)
     return BBX_OK;
 }
 
-SurArgs sur_args(const bbx_grid *g, int parity)
+SurArgs sur_args(const bbx_grid *g)
 {
     SurArgs su;
     su.net = g->snet;
@@ -319,8 +320,8 @@ SurArgs sur_args(const bbx_grid *g, int parity)
     su.dv_max = g->dv_max;
     su.acc_list = g->d_acc_list;
     su.acc_cnt = g->d_acc_cnt;
-    su.fb_total = g->d_fb_total;
-    su.parity = parity;
+    su.fb = g->d_fb;
+    su.nblk = g->sur_nblk;
     return su;
 }
 
@@ -340,7 +341,17 @@ int graph_capture(bbx_grid *g, int c)
         a.Vin = (const T *)g->d_V[c ^ (j & 1)];
         a.Vout = (T *)g->d_V[c ^ (j & 1) ^ 1];
         a.jstep = j;
-        e = launch_step<T>(g->model, g->aniso, a, g->stream);
+        bool done = false;
+        if constexpr (std::is_same<T, float>::value) {
+            if (g->sur) {
+                StepArgs<float> b = a;
+                b.nblk = (int)((g->nact + kBlock - 1) / kBlock);
+                b.per_xcd = (b.nblk + kXcd - 1) / kXcd;
+                e = launch_surrogate_step(g->model, g->aniso, b, sur_args(g), g->stream);
+                done = true;
+            }
+        }
+        if (!done) e = launch_step<T>(g->model, g->aniso, a, g->stream);
     }
     if (e == hipSuccess) e = launch_counter(g->d_nbase, g->chunk, 1, g->stream);
     hipGraph_t gr = nullptr;
@@ -360,13 +371,13 @@ int graph_capture(bbx_grid *g, int c)
     return BBX_OK;
 }
 
-// Replay whole chunks while at least one is left; returns the steps done.  Not used with a
-// surrogate attached or while pseudo-ECG samples are being taken (both stay direct).
+// Replay whole chunks while at least one is left; returns the steps done.  Not used while
+// pseudo-ECG samples are being taken (those steps stay direct).
 template <typename T>
 int graph_steps(bbx_grid *g, int64_t nsteps, int64_t *done)
 {
     *done = 0;
-    if (g->chunk <= 0 || nsteps < g->chunk || g->sur || g->nact == 0) return BBX_OK;
+    if (g->chunk <= 0 || nsteps < g->chunk || g->nact == 0) return BBX_OK;
     if (g->ecg_every > 0 && g->ecg_count < g->ecg_max) return BBX_OK;
     hipError_t e = hipSuccess;
     if (!g->d_nbase && (e = dalloc(g, &g->d_nbase, sizeof(int64_t))) != hipSuccess) return hip_fail(e, "hipMalloc");
@@ -424,7 +435,7 @@ int step_impl(bbx_grid *g, int64_t nsteps)
                     StepArgs<float> b = a;
                     b.nblk = (int)((g->nact + kBlock - 1) / kBlock);   // classifier: one thread per voxel
                     b.per_xcd = (b.nblk + kXcd - 1) / kXcd;
-                    const SurArgs su = sur_args(g, (int)(n & 1));
+                    const SurArgs su = sur_args(g);
                     HIP_TRY(launch_surrogate_step(g->model, g->aniso, b, su, g->stream), "surrogate step");
                     done = true;
                 }
@@ -775,9 +786,12 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
         if (on_dev) return fail(BBX_ENOTSUP, "FALLBACK_COUNT is read to host memory only");
         if (out_bytes < sizeof(int64_t)) return fail(BBX_EINVAL, "out_bytes too small");
         unsigned long long v = 0;
-        if (g->d_fb_total) {
-            HIP_TRY(hipMemcpyAsync(&v, g->d_fb_total, sizeof v, hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
+        if (g->d_fb && g->sur_nblk > 0) {
+            std::vector<unsigned long long> fb((size_t)g->sur_nblk);
+            HIP_TRY(hipMemcpyAsync(fb.data(), g->d_fb, fb.size() * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, g->stream), "hipMemcpyAsync");
             HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
+            for (unsigned long long x : fb) v += x;
         }
         int64_t o = (int64_t)v;
         memcpy(out, &o, sizeof o);
@@ -1310,8 +1324,6 @@ int bbx_clock_set(bbx_grid *g, int64_t step)
     g_err.clear();
     if (!g) return fail(BBX_EINVAL, "grid is NULL");
     if (step < 0) return fail(BBX_EINVAL, "step must be >= 0");
-    // the network list lengths alternate with the step's parity: restart both
-    if (g->d_acc_cnt) HIP_TRY(hipMemsetAsync(g->d_acc_cnt, 0, 2 * sizeof(int32_t), g->stream), "hipMemsetAsync");
     g->n = step;
     return BBX_OK;
 }
@@ -1803,6 +1815,8 @@ int surrogate_alloc(bbx_grid *g, int nin, int nout)
     hipError_t e;
     g->snet.nin = nin;
     g->snet.nout = nout;
+    // one list segment per classifier workgroup (kBlock voxels)
+    const int nb = (int)((g->nact + kBlock - 1) / kBlock);
     if ((e = dalloc(g, &g->snet.w1, kH * kS1 * sizeof(__bf16))) != hipSuccess ||
         (e = dalloc(g, &g->snet.w2, kH * kS2 * sizeof(__bf16))) != hipSuccess ||
         (e = dalloc(g, &g->snet.w3, kP * kS2 * sizeof(__bf16))) != hipSuccess ||
@@ -1810,10 +1824,11 @@ int surrogate_alloc(bbx_grid *g, int nin, int nout)
         (e = dalloc(g, &g->snet.norm, 4 * kP * sizeof(float))) != hipSuccess ||
         (e = dalloc(g, &g->d_slo, kP * sizeof(float))) != hipSuccess ||
         (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
-        (e = dalloc(g, &g->d_acc_list, (g->nact ? g->nact : 1) * sizeof(int32_t))) != hipSuccess ||
-        (e = dalloc(g, &g->d_acc_cnt, 2 * sizeof(int32_t))) != hipSuccess ||
-        (e = dalloc(g, &g->d_fb_total, sizeof(unsigned long long))) != hipSuccess)
+        (e = dalloc(g, &g->d_acc_list, (size_t)(nb ? nb : 1) * kBlock * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(g, &g->d_acc_cnt, (size_t)(nb ? nb : 1) * sizeof(int32_t))) != hipSuccess ||
+        (e = dalloc(g, &g->d_fb, (size_t)(nb ? nb : 1) * sizeof(unsigned long long))) != hipSuccess)
         return hip_fail(e, "hipMalloc");
+    g->sur_nblk = nb;
     return BBX_OK;
 }
 
@@ -1823,11 +1838,13 @@ int surrogate_finish(bbx_grid *g, const float *lo, const float *hi, float dv_max
     hipStream_t st = g->stream;
     HIP_TRY(hipMemcpyAsync(g->d_slo, lo, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
     HIP_TRY(hipMemcpyAsync(g->d_shi, hi, g->nvar * sizeof(float), hipMemcpyHostToDevice, st), "copy");
-    HIP_TRY(launch_fill<int>(g->d_acc_cnt, 0, 2, st), "fill");
-    HIP_TRY(launch_fill<int>((int *)g->d_fb_total, 0, 2, st), "fill");
+    const int64_t nb = g->sur_nblk ? g->sur_nblk : 1;
+    HIP_TRY(launch_fill<int>(g->d_acc_cnt, 0, nb, st), "fill");
+    HIP_TRY(launch_fill<int>((int *)g->d_fb, 0, 2 * nb, st), "fill");
     HIP_TRY(hipStreamSynchronize(st), "hipStreamSynchronize");
     g->dv_max = dv_max;
     g->sur = 1;
+    graph_drop(g);
     return BBX_OK;
 }
 
@@ -1890,6 +1907,7 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
         if (!g) return fail(BBX_EINVAL, "grid is NULL");
         if (!m) {
             g->sur = 0;
+            graph_drop(g);
             return BBX_OK;
         }
         int rc = surrogate_check(g, m->nin, m->nout, lo, hi, dv_max);

@@ -43,10 +43,13 @@ struct SurArgs {
     MlpDev net;
     const float *lo, *hi;            // [nvar] accepted input box
     float dv_max;                    // largest accepted |dV| per step
-    int32_t *acc_list;               // [nact] voxels whose input the network accepts
-    int32_t *acc_cnt;                // [2] list lengths, alternating per step
-    unsigned long long *fb_total;    // running count of fallbacks
-    int parity;
+    // Per classifier workgroup b (kBlock voxels each, nblk of them): the tissue indices
+    // of its voxels whose input the network accepts, at acc_list[b * kBlock ...], their
+    // number acc_cnt[b] (rewritten every step), and its running fallback count fb[b].
+    int32_t *acc_list;               // [nblk * kBlock]
+    int32_t *acc_cnt;                // [nblk]
+    unsigned long long *fb;          // [nblk]
+    int nblk;
 };
 
 int mlp_nparams(int nin, int nout);

@@ -598,20 +598,22 @@ uint64_t mlp_mix64(uint64_t z) { return mix64(z); }
 // ------------------------------------------------------- surrogate step
 // A surrogate step is two launches.  (1) k_sur_classify, one thread per tissue
 // voxel: voxels whose kinetic input s = (V or V* = V + dt LV, g) lies in the
-// accepted box [lo, hi] are appended to the network list; every other voxel gets
-// the plain update right there (the plain step's own arithmetic).  (2) k_sur_net:
-// one persistent workgroup per CU stages the weights in LDS once and walks the
-// network list in chunks of kSurBlock voxels (one per thread): each thread
-// recomputes its Laplacian and stimulus and writes its normalised input to the
-// wave's LDS staging rows; the wave runs the network on its 64 voxels as four
-// 16-sample tiles, and each thread applies or rejects its prediction (gate
-// outside [0, 1], |dV| > dv_max, non-finite); rejected
-// voxels get the plain update in place (rare).  Accepted gate predictions within
-// kGateTol of [0, 1] are clamped into it.  The network's cost is thus paid only for
-// the voxels it may take.
+// accepted box [lo, hi] are listed in their workgroup's own segment of the network
+// list (slots by a prefix count over the workgroup's waves: no global atomics, and
+// the order is fixed); every other voxel gets the plain update right there (the plain
+// step's own arithmetic).  (2) k_sur_net: one persistent workgroup per CU stages the
+// weights in LDS once and walks the list segments in slots of 64 voxels (four per
+// segment; empty slots are skipped): each thread recomputes its Laplacian and stimulus
+// and writes its normalised input to the wave's LDS staging rows; the wave runs the
+// network on its 64 voxels as four 16-sample tiles, and each thread applies or rejects
+// its prediction (gate outside [0, 1], |dV| > dv_max, non-finite); rejected voxels get
+// the plain update in place (rare).  Accepted gate predictions within kGateTol of
+// [0, 1] are clamped into it.  The network's cost is thus paid only for the voxels it
+// may take.
 template <class M, bool ANISO>
 __global__ __launch_bounds__(kBlock) void k_sur_classify(const StepArgs<float> a, const SurArgs su)
 {
+    __shared__ int wave_n[kBlock / 64];
     const int lb = (int)(blockIdx.x % kXcd) * a.per_xcd + (int)(blockIdx.x / kXcd);
     if (lb >= a.nblk) return;                              // workgroup-uniform exit
     const int t = lb * kBlock + (int)threadIdx.x;
@@ -625,28 +627,40 @@ __global__ __launch_bounds__(kBlock) void k_sur_classify(const StepArgs<float> a
         Vp = a.Vin[idx];
         LV = laplacian<float, ANISO, false>(a, a.Vin, t, idx, bits, Vp);
         const float s0 = a.split ? Vp + a.dt * LV : Vp;
-        ok = s0 >= su.lo[0] && s0 <= su.hi[0];
+        ok = (s0 >= su.lo[0]) & (s0 <= su.hi[0]);
+        // every variable is read and tested (no short cut), so the loads are
+        // unconditional and serve the update below
 #pragma unroll
         for (int i = 1; i < M::NV; i++) {
             const float y = a.st[(i - 1) * a.pitch + t];
-            ok = ok && y >= su.lo[i] && y <= su.hi[i];
+            ok = ok & (y >= su.lo[i]) & (y <= su.hi[i]);
         }
+        // outside the box: the plain update, here, before anything is stored, so that
+        // the compiler can reuse the state just loaded for the check
+        if (!ok) update_voxel<float, M>(a, step_clock(a), t, idx, Vp, LV);
     }
-    // append the accepted voxels: one atomic per wave, slots by prefix count
+    // slot of an accepted voxel: accepted voxels of the lower waves, then of the lower
+    // lanes of its own wave
     const uint64_t acc = __ballot(ok);
-    if (acc) {
-        const int l = (int)threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)acc) - 1;
-        int base = 0;
-        if (l == leader) base = atomicAdd(&su.acc_cnt[su.parity], __popcll(acc));
-        base = __shfl(base, leader);
-        if (ok) {
-            const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(acc >> 32),
-                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)acc, 0u));
-            su.acc_list[base + below] = t;
-        }
+    const int w = (int)threadIdx.x / 64, l = (int)threadIdx.x & 63;
+    if (l == 0) wave_n[w] = __popcll(acc);
+    __syncthreads();
+    int base = 0, total = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; k++) {
+        base += k < w ? wave_n[k] : 0;
+        total += wave_n[k];
     }
-    if (valid && !ok) update_voxel<float, M>(a, step_clock(a), t, idx, Vp, LV);
+    if (ok) {
+        const int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(acc >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)acc, 0u));
+        su.acc_list[lb * kBlock + base + below] = t;
+    }
+    if (threadIdx.x == 0) {
+        const int nvalid = min(kBlock, (int)(a.nact - (int64_t)lb * kBlock));
+        su.acc_cnt[lb] = total;
+        su.fb[lb] += (unsigned long long)(nvalid - total);  // input outside the box
+    }
 }
 
 // Hand-over of LDS data between the lanes of one wave: the writes before it are
@@ -711,41 +725,49 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
 {
     constexpr int NV = M::NV;
     static_assert(NV <= kSurRow, "a voxel's outputs must fit in its staging row");
-    const int n = su.acc_cnt[su.parity];
+    constexpr int kSlots = kBlock / 64;                 // 64-voxel slots per list segment
     const Clock<float> ck = step_clock(a);
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        // input-rejected voxels were updated by the classifier; the next step's list
-        // (other parity) starts empty
-        atomicAdd(su.fb_total, (unsigned long long)(a.nact - n));
-        su.acc_cnt[su.parity ^ 1] = 0;
-    }
-    // the list is dealt to waves in chunks of 64, wave-major across workgroups
-    // (chunk c goes to wave c / G of workgroup c % G, G = gridDim.x), so that a
-    // short list still spreads over many CUs; a workgroup whose first chunk is
-    // past the end has nothing to do
-    if ((int)blockIdx.x * 64 >= n) return;
     constexpr int NW = kSurBlock / 64;
     __shared__ __attribute__((aligned(16))) __bf16 w1[kH * kS1], w2[kH * kS2], w3[kP * kS2];
     __shared__ __attribute__((aligned(16))) float bias[2 * kH + kP];
     // one staging row per voxel: its normalised input (kP BF16 values) before the
     // network, its FP32 output increments after
     __shared__ __attribute__((aligned(16))) float rows[NW][64 * kSurRow];
-    // persistent workgroups: stage the weights once, then walk the voxel chunks; after
-    // this barrier the waves run independently (each uses only its own rows), so one
-    // wave's gathers overlap another's network
+    const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
+    // slot c (segment c / kSlots, part c % kSlots): workgroup (c / NW) mod G, its wave
+    // c mod NW, so that neighbouring slots (neighbouring voxels, often accepted together)
+    // run side by side in one workgroup and a short list keeps most workgroups idle
+    const int G = (int)gridDim.x, nslot = su.nblk * kSlots;
+    const int rounds = (nslot + NW * G - 1) / (NW * G);
+    // a workgroup none of whose slots holds a voxel leaves before staging the weights
+    // (checked when each wave has at most kCheck slots: short lists)
+    constexpr int kCheck = 4;
+    if (rounds <= kCheck) {
+        bool any = false;
+#pragma unroll
+        for (int k = 0; k < kCheck; k++) {
+            const int c = (k * G + (int)blockIdx.x) * NW + wv;
+            if (k < rounds && c < nslot) any = any || su.acc_cnt[c / kSlots] > 64 * (c % kSlots);
+        }
+        if (!__syncthreads_or(any)) return;
+    }
+    // persistent workgroups: stage the weights once, then walk the slots; after this
+    // barrier the waves run independently (each uses only its own rows), so one wave's
+    // gathers overlap another's network
     stage_weights(su.net, w1, w2, w3, nullptr, nullptr, bias);
     __syncthreads();
     const MlpLds W{w1, w2, w3, nullptr, nullptr, bias};
-    const int wv = threadIdx.x / 64, l = threadIdx.x & 63, j = l & 15, g = l >> 4;
     const float *nrm = su.net.norm;
     float *wrows = rows[wv];
 
-    const int nwave = (int)gridDim.x * NW, gw = wv * (int)gridDim.x + (int)blockIdx.x;
-    const int iters = (n + 64 * nwave - 1) / (64 * nwave);          // uniform over the grid
-    for (int it = 0; it < iters; it++) {
-        const int k = (it * nwave + gw) * 64 + l;
-        const bool valid = k < n;
-        const int t = valid ? su.acc_list[k] : 0;
+    for (int k = 0; k < rounds; k++) {
+        const int c = (k * G + (int)blockIdx.x) * NW + wv;
+        if (c >= nslot) break;
+        const int b = c / kSlots, q = c % kSlots;
+        const int nin = su.acc_cnt[b] - 64 * q;              // wave-uniform
+        if (nin <= 0) continue;
+        const bool valid = l < nin;
+        const int t = valid ? su.acc_list[b * kBlock + 64 * q + l] : 0;
         // only what the update needs after the network stays in registers; the gates
         // are read again afterwards (from cache)
         int idx = 0;
@@ -765,15 +787,14 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
             for (int i = 1; i < NV; i++) xr[i] = bf((a.st[(i - 1) * a.pitch + t] - nrm[i]) * nrm[kP + i]);
         }
         float *row = wrows + l * kSurRow;
-        wave_sync();                                           // the previous chunk's outputs read
+        wave_sync();                                           // the previous slot's outputs read
 #pragma unroll
-        for (int q = 0; q < kP / 8; q++) *(bf8 *)((__bf16 *)row + 8 * q) = *(const bf8 *)(xr + 8 * q);
+        for (int qq = 0; qq < kP / 8; qq++) *(bf8 *)((__bf16 *)row + 8 * qq) = *(const bf8 *)(xr + 8 * qq);
         wave_sync();                                           // the wave's inputs staged
 
-        const uint64_t want = __ballot(valid);
 #pragma unroll 1
         for (int T = 0; T < 4; T++) {
-            if (((want >> (16 * T)) & 0xFFFFull) == 0) continue;    // no voxel in this tile
+            if (16 * T >= nin) break;                          // no voxel in this tile or later
             float *trow = wrows + (16 * T + j) * kSurRow;
             const bf8 x = ld8((const __bf16 *)trow + 8 * g);
             f4v out[2];
@@ -803,10 +824,10 @@ __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, 
         for (int i = M::GATE0; i < NV; i++)
             ok = ok && s[i] + d[i] >= -kGateTol && s[i] + d[i] <= 1.0f + kGateTol;
         // a rejected prediction falls back to the plain update of this voxel, here
-        // (rare; counted with one atomic per wave)
+        // (rare; counted with one atomic per wave on the segment's own counter)
         const uint64_t rej = __ballot(!ok);
         if (rej) {
-            if (l == __ffsll((unsigned long long)rej) - 1) atomicAdd(su.fb_total, (unsigned long long)__popcll(rej));
+            if (l == __ffsll((unsigned long long)rej) - 1) atomicAdd(&su.fb[b], (unsigned long long)__popcll(rej));
             if (!ok) {
                 update_voxel<float, M>(a, ck, t, idx, Vp, LV);
                 continue;
@@ -871,12 +892,15 @@ template <class M>
 static hipError_t sur_m(int aniso, const StepArgs<float> &a, const SurArgs &su, hipStream_t s)
 {
     if (a.nact == 0) return hipSuccess;
+    if (su.nblk != a.nblk) return hipErrorInvalidValue;   // list segments = classifier workgroups
     const int ncu = cu_count();
     const dim3 gc((unsigned)(a.per_xcd * kXcd)), bc(kBlock);
     if (aniso) hipLaunchKernelGGL((k_sur_classify<M, true>), gc, bc, 0, s, a, su);
     else hipLaunchKernelGGL((k_sur_classify<M, false>), gc, bc, 0, s, a, su);
-    const int nchunk = (int)((a.nact + kSurBlock - 1) / kSurBlock);
-    const dim3 grid((unsigned)(nchunk < ncu ? nchunk : ncu)), block(kSurBlock);
+    // enough workgroups for one slot per wave, at most one per CU
+    const int64_t nslot = (int64_t)su.nblk * (kBlock / 64);
+    const int64_t nwg = (nslot + kSurBlock / 64 - 1) / (kSurBlock / 64);
+    const dim3 grid((unsigned)(nwg < ncu ? nwg : ncu)), block(kSurBlock);
     if (aniso) hipLaunchKernelGGL((k_sur_net<M, true>), grid, block, 0, s, a, su);
     else hipLaunchKernelGGL((k_sur_net<M, false>), grid, block, 0, s, a, su);
     return hipGetLastError();

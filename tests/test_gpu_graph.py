@@ -48,6 +48,47 @@ def test_graph_replay_bitwise_equals_direct(B, prec, scheme, integ):
     assert np.array_equal(gpu_state(a, 21), gpu_state(b, 21), equal_nan=True)
 
 
+def test_graph_replay_with_surrogate_bitwise_equals_direct(B):
+    """A surrogate attached (network accepting states near rest, the rest falling back):
+    the captured graph holds the classifier and network launches of every step and
+    alternates their list counters with the step number; graph and direct runs stay
+    bitwise equal, fallback counts included, also after a clock change flips the step
+    number's parity (the graph is captured again)."""
+    import torch
+    g0 = WL.crn_cup(24, 24, 12, seed=4)
+    p = Problem(g0["mask"], 0.25, g0["fibre"], 0.3, 0.03, O.MODEL_CRN, [], 0.01,
+                state=g0["state"], theta=-40.0, stims=[(g0["stim"], 40.0, 0.0, 2.0, 0.0, 1)])
+    rng = np.random.default_rng(7)
+    rest = np.array(WL.CRN_INITIAL, np.float32)
+    S = (rest * (1 + 0.01 * rng.standard_normal((4096, 21)))).astype(np.float32)
+    S1 = (S + 1e-3 * np.abs(rest) * rng.standard_normal((4096, 21))).astype(np.float32)
+    S, S1 = torch.from_numpy(S).cuda(), torch.from_numpy(S1).cuda()
+    m = B.Mlp(21, 21, seed=5)
+    m.fit_norm(S, S1)
+    lo, hi = S.min(0).values.cpu().numpy(), S.max(0).values.cpu().numpy()
+    s = torch.cuda.Stream()
+    a = make_gpu(p, B.BBX_FP32, s)
+    b = make_gpu(p, B.BBX_FP32, s)
+    for g in (a, b):
+        g.surrogate(m, lo, hi, 5.0)
+    b.graph(64)
+    for n in (5, 200, 64, 129, 1, 300):
+        a.step(n)
+        b.step(n)
+    torch.cuda.synchronize()
+    fa, fb = (int(g.read(B.BBX_READ_FALLBACK_COUNT)[0]) for g in (a, b))
+    print("fallback", fa, "of", a.nact * 699)
+    assert fa == fb and 0 < fa < a.nact * 699
+    assert np.array_equal(gpu_state(a, 21), gpu_state(b, 21), equal_nan=True)
+    assert np.array_equal(a.read(B.BBX_READ_ACT_TIME), b.read(B.BBX_READ_ACT_TIME), equal_nan=True)
+    for g in (a, b):
+        g.clock(690)
+        g.step(200)
+    torch.cuda.synchronize()
+    assert np.array_equal(gpu_state(a, 21), gpu_state(b, 21), equal_nan=True)
+    assert int(a.read(B.BBX_READ_FALLBACK_COUNT)[0]) == int(b.read(B.BBX_READ_FALLBACK_COUNT)[0])
+
+
 def test_graph_errors(B):
     g = B.Grid(np.ones((2, 2, 2), np.uint8), 0.25, None, 0.3, 0.03, B.BBX_FP32)
     g.model(B.BBX_MODEL_NONE, [], 0.01)

@@ -309,15 +309,16 @@ def test_single_voxel_matches_oracle_cell():
     assert np.all(rel_errs(gpu_state(g, 21), s.state, mask) <= TOL64)
 
 
-@pytest.mark.parametrize("fibres", ["none", "rotating", "random", "random_2d"])
+@pytest.mark.parametrize("fibres", ["none", "rotating", "random", "random_2d", "random_wide"])
 @pytest.mark.parametrize("prec", [1, 0])
 def test_dense_box_light_model(fibres, prec):
     """Dense boxes with a light model take the z-marching kernels (register march when
-    isotropic; LDS rings of V and of fibre products when anisotropic, the face
-    coefficients of the tensor-gradient term rebuilt in the kernel).  Fibres rotating
-    in z only leave those coefficients zero; random fibres exercise them everywhere,
-    including the box faces.  FP64 <= 1e-10 normwise; FP32 <= 1e-5 normwise."""
-    shape = (1, 37, 45) if fibres == "random_2d" else (7, 13, 21)
+    isotropic; an LDS ring of V planes when anisotropic, with the precomputed face
+    coefficients of the tensor-gradient term).  Fibres rotating in z only leave those
+    coefficients zero; random fibres exercise them everywhere, including the box faces;
+    the wide box has tiles whose whole halo lies inside the box (the kernel's
+    branch-free interior path).  FP64 <= 1e-10 normwise; FP32 <= 1e-5 normwise."""
+    shape = {"random_2d": (1, 37, 45), "random_wide": (10, 14, 150)}.get(fibres, (7, 13, 21))
     nz, ny, nx = shape
     mask, fib = WL.full_box_rotating(nx, ny, nz)
     if fibres.startswith("random"):
