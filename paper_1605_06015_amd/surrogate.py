@@ -127,8 +127,9 @@ def attach(grid, trained, margin=0.02, dv_cap=None):
 def run_pair(trained, model, geo_seed, nx=96, ny=96, nz=48, t_ms=500.0, v_his=(), stream=None):
     """The plain FP32 run and one surrogate run per acceptance threshold v_hi on a cup of
     the workload's shape (geometry seed geo_seed), t_ms long.  Returns the plain run's
-    activation times and seconds and, per threshold, a dict of share, activation-time and
-    APD90 errors against the plain run, and seconds."""
+    activation-time and APD90 maps (tissue order) and seconds and, per threshold, a dict of
+    share, activation-time and APD90 errors against the plain run, seconds, and the
+    surrogate run's own maps ("at", "apd")."""
     import torch
     mid, nv, c, geo, _, amp, dur = _model_setup(model)
     g = geo(nx, ny, nz, seed=geo_seed, active=c["active"], h=c["h"])
@@ -175,7 +176,7 @@ def run_pair(trained, model, geo_seed, nx=96, ny=96, nz=48, t_ms=500.0, v_his=()
             at_max=float(dat.max()) if dat.size else None, at_mean=float(dat.mean()) if dat.size else None,
             apd_max=float(dapd.max()) if dapd.size else None,
             apd_mean=float(dapd.mean()) if dapd.size else None,
-            sec=q["sec"], speed_vs_plain=plain["sec"] / q["sec"])
+            sec=q["sec"], speed_vs_plain=plain["sec"] / q["sec"], at=q["at"], apd=q["apd"])
     return plain, res, c["dt"]
 
 
@@ -188,6 +189,7 @@ def select_threshold(trained, model, geo_seed=11, margin=1.0, offsets=(-0.2, -0.
     rest = _model_setup(model)[4][0]
     cands = [round(rest + o, 4) for o in offsets]
     _, sweep, dt = run_pair(trained, model, geo_seed, v_his=cands, stream=stream)
+    sweep = {v: {k: x for k, x in r.items() if k not in ("at", "apd")} for v, r in sweep.items()}
     ok = [v for v in cands if sweep[v]["same_activated"] and sweep[v]["at_max"] is not None
           and sweep[v]["at_max"] <= margin * dt]
     best = max(ok, key=lambda v: (sweep[v]["share"], -v)) if ok else None
