@@ -186,7 +186,7 @@ def test_full_size_ensemble_few_steps(B):
     """The 96-tissue workload (24.0 M voxels, sides drawn from 64..768) in the launch configuration
     the benchmark times (graph mode, tuned tile): after 4 steps with S1 on, the smallest,
     a middle and the largest tissue match the FP64 oracle (FP32: |du| <= 1e-5, gates
-    <= 1e-5 absolute)."""
+    <= 1e-5 absolute and within 1e-3 of their own value)."""
     c = WL.FK4_ENSEMBLE
     w = WL.fk4_ensemble(n=c["n"], side_lo=c["side_lo"], side_hi=c["side_hi"], seed=c["seed"])
     e = B.Ensemble(w["nx"], w["ny"], c["h"], w["Dpar"], w["Dperp"], w["angle"], B.BBX_MODEL_FK4,
@@ -219,7 +219,10 @@ def test_full_size_ensemble_few_steps(B):
                 o.stimuli.append(O.Stimulus(reg, amp, int(round(t0 / c["dt"])), int(round(dur / c["dt"]))))
         o.step(4)
         for v in range(4):
-            assert np.abs(e.get(i, v) - o.state[v, 0]).max() <= 1e-5, (i, v)
+            d = np.abs(e.get(i, v) - o.state[v, 0])
+            assert d.max() <= 1e-5, (i, v)
+            if v > 0:       # gates: also within 1e-3 of their own value
+                assert np.all(d <= 1e-3 * np.abs(o.state[v, 0]) + 1e-9), (i, v)
     assert e.read(B.BBX_READ_NAN_FLAG, 0)[0] == 0
 
 

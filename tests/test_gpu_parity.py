@@ -145,7 +145,8 @@ def test_crn_small_cup_fp64_through_upstroke():
 def test_crn_full_size_few_steps(prec, tol):
     """The 128x128x64 cup (367k tissue voxels) in the launch configuration the benchmark
     times: every tissue voxel after 3 steps with the stimulus on.  FP32: |dV| <= 1e-3 mV
-    and gates/concentrations within 1e-5 normwise."""
+    and concentrations within 1e-5 normwise; gates within 1e-5 absolute and 1e-3 of their
+    own value (so a gate that stays small, x_r ~ 3e-5 at rest, is checked too)."""
     p = crn_problem(128, 128, 64, seed=1)
     s = run_oracle(p, 3, nthreads=8)
     g = make_gpu(p, prec)
@@ -155,12 +156,16 @@ def test_crn_full_size_few_steps(prec, tol):
     if prec == 1:
         assert np.all(e <= tol), e
     else:
-        # gates live in [0, 1]: absolute error; concentrations: normwise relative
+        # gates live in [0, 1]: absolute and pointwise relative error; concentrations:
+        # normwise relative
         m = p.mask == 1
         assert np.abs(x[0][m] - s.state[0][m]).max() <= 1e-3
         assert np.all(e[1:6] <= 1e-5), e
         for v in range(6, 21):
-            assert np.abs(x[v][m] - s.state[v][m]).max() <= 1e-5, v
+            d = np.abs(x[v][m] - s.state[v][m])
+            rel = (d / (np.abs(s.state[v][m]) + 1e-9)).max()
+            print("gate", v, "abs", d.max(), "rel", rel)
+            assert d.max() <= 1e-5 and rel <= 1e-3, (v, d.max(), rel)
 
 
 def test_crn_fp32_within_0p5mV_and_1dt():
