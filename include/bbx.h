@@ -425,7 +425,8 @@ int bbx_surrogate_set(bbx_grid *g, const bbx_mlp *m, const float *lo, const floa
  * corners' mean; each crossing of a u piece with a v piece is a point.
  *   stats [7] (host): count, mean x, y, z, standard deviation (population) of x, y,
  *         z, coordinates in mm (x_p = h (x, y, z)), from FP64 sums in a fixed order
- *         (deterministic);
+ *         (deterministic);  a slab grid searches its own planes only and reports global
+ *         coordinates (z of the whole box), so the slabs' points together are the box's;
  *   points (host, may be NULL): the first min(count, max_points) points, [k][3] mm,
  *         in an order that varies from run to run (sort to compare);
  *   npoints (may be NULL): the number of points found.

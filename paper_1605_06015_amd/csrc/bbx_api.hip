@@ -1382,6 +1382,11 @@ int tips_impl(bbx_grid *g, int vu, double ul, int vv, double vl, double *stats, 
     HIP_TRY(launch_fill<int>((int *)cnt, 0, 2, g->stream), "fill");
     TipLaunch<T> L = {};
     L.nx = g->nx; L.ny = g->ny; L.nz = g->nz; L.dense = g->dense;
+    // a slab searches its own planes only (its halo planes are its neighbours' own) and
+    // reports global coordinates
+    L.z0 = g->slab ? 1 : 0;
+    L.z1 = g->slab ? g->nz - 1 : g->nz;
+    L.zoff = g->slab ? g->zoff : 0;
     L.h = g->h; L.ul = ul; L.vl = vl;
     L.map = g->d_map;
     const T *V = (const T *)g->d_V[g->cur], *st = (const T *)g->d_st;
@@ -1392,7 +1397,7 @@ int tips_impl(bbx_grid *g, int vu, double ul, int vv, double vl, double *stats, 
     L.pts = (double *)pts.p;
     L.max_pts = cap;
     L.count = cnt;
-    if (g->nx >= 2 && g->ny >= 2 && g->nact > 0) {
+    if (g->nx >= 2 && g->ny >= 2 && g->nact > 0 && L.z1 > L.z0) {
         HIP_TRY(launch_tips<T>(L, g->stream), "tips");
     } else {
         HIP_TRY(launch_fill<double>(out, 0.0, 7, g->stream), "fill");

@@ -99,6 +99,8 @@ hipError_t launch_step(int model, int aniso, const StepArgs<T> &a, hipStream_t s
 template <typename T>
 struct TipLaunch {
     int nx, ny, nz, dense;
+    int z0, z1;                  // planes searched (a slab's own planes)
+    int zoff;                    // global index of plane 0 (slabs), for the coordinates
     double h, ul, vl;
     const int32_t *map;
     const T *u_box, *u_list, *v_box, *v_list;

@@ -70,19 +70,20 @@ __device__ __forceinline__ int pieces(const double c[4], double s[2][4])
     return 0;
 }
 
+// Cells of planes z0 .. z1-1; plane z is reported at h (z + zoff) (a slab's global plane).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_tips(int nx, int ny, int nz, double h, int dense,
-                                                 const int32_t *map, TipField<T> fu, double ul,
-                                                 TipField<T> fv, double vl, double *part,
-                                                 double *pts, int64_t max_pts,
+__global__ __launch_bounds__(kBlock) void k_tips(int nx, int ny, int z0, int z1, int zoff, double h,
+                                                 int dense, const int32_t *map, TipField<T> fu,
+                                                 double ul, TipField<T> fv, double vl,
+                                                 double *part, double *pts, int64_t max_pts,
                                                  unsigned long long *count)
 {
     __shared__ double sh[kTipSums][kBlock];
     double acc[kTipSums] = {0, 0, 0, 0, 0, 0, 0};
-    const int64_t cx = nx - 1, cy = ny - 1, ncell = cx * cy * (int64_t)nz;
+    const int64_t cx = nx - 1, cy = ny - 1, ncell = cx * cy * (int64_t)(z1 - z0);
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t c = (int64_t)blockIdx.x * kBlock + threadIdx.x; c < ncell; c += stride) {
-        const int64_t x = c % cx, r = c / cx, y = r % cy, z = r / cy;
+        const int64_t x = c % cx, r = c / cx, y = r % cy, z = z0 + r / cy;
         const int64_t b00 = x + nx * (y + (int64_t)ny * z);
         const int64_t bb[4] = {b00, b00 + 1, b00 + nx, b00 + nx + 1};
         if (!dense && (map[bb[0]] < 0 || map[bb[1]] < 0 || map[bb[2]] < 0 || map[bb[3]] < 0)) continue;
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(kBlock) void k_tips(int nx, int ny, int nz, double 
                 if (!(s >= 0.0 && s <= 1.0 && t >= 0.0 && t <= 1.0)) continue;
                 const double X = h * ((double)x + (su[i][0] + s * rx));
                 const double Y = h * ((double)y + (su[i][1] + s * ry));
-                const double Z = h * (double)z;
+                const double Z = h * (double)(z + zoff);
                 acc[0] += 1.0;
                 acc[1] += X; acc[2] += Y; acc[3] += Z;
                 acc[4] += X * X; acc[5] += Y * Y; acc[6] += Z * Z;
@@ -169,8 +170,9 @@ hipError_t launch_tips(const TipLaunch<T> &L, hipStream_t s)
 {
     TipField<T> fu{L.u_box, L.u_list, L.dense ? nullptr : L.map};
     TipField<T> fv{L.v_box, L.v_list, L.dense ? nullptr : L.map};
-    hipLaunchKernelGGL((k_tips<T>), dim3(kTipBlocks), dim3(kBlock), 0, s, L.nx, L.ny, L.nz, L.h,
-                       L.dense, L.map, fu, L.ul, fv, L.vl, L.part, L.pts, L.max_pts, L.count);
+    hipLaunchKernelGGL((k_tips<T>), dim3(kTipBlocks), dim3(kBlock), 0, s, L.nx, L.ny, L.z0, L.z1,
+                       L.zoff, L.h, L.dense, L.map, fu, L.ul, fv, L.vl, L.part, L.pts, L.max_pts,
+                       L.count);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tips_final, dim3(1), dim3(64), 0, s, L.part, kTipBlocks, L.out);

@@ -118,6 +118,42 @@ def test_crn_cup_slabs_equal_whole_box(B, prec, nslab, scheme):
     assert np.isfinite(at_w[m]).sum() > 0
 
 
+@pytest.mark.parametrize("prec", [1, 0])
+def test_slab_tips_are_the_whole_box_tips(B, prec):
+    """Phase singularities of two smooth fields set on the cup (40x40x24) split into 4
+    tissue-balanced slabs: each slab searches its own planes and reports global
+    coordinates, so the slabs' points together are the whole box's, bit for bit, and
+    the count-weighted means of their FP64 sums are the whole box's."""
+    g0 = WL.crn_cup(40, 40, 24, seed=3)
+    mask = g0["mask"]
+    z, y, x = np.meshgrid(*(np.arange(n) for n in mask.shape), indexing="ij")
+    u = np.sin(0.35 * x + 0.1 * z) + 0.3 * np.sin(0.2 * y)
+    v = np.sin(0.3 * y - 0.05 * z) + 0.3 * np.cos(0.25 * x)
+    h = 0.25
+    w = B.Grid(mask, h, None, 1.0, 1.0, prec)
+    w.model(B.BBX_MODEL_BARKLEY, [0.75, 0.02, 0.02], 0.001)
+    w.set(0, u)
+    w.set(1, v)
+    st_w, p_w = w.tips(0, 0.0, 1, 0.0)
+    zb = B.bbx_slab_bounds(mask, 4)
+    parts = []
+    for k in range(4):
+        z0, z1 = int(zb[k]), int(zb[k + 1])
+        g = B.Grid.slab(mask, z0, z1, h, None, 1.0, 1.0, prec)
+        g.model(B.BBX_MODEL_BARKLEY, [0.75, 0.02, 0.02], 0.001)
+        g.set(0, slab_view(u, z0, z1))
+        g.set(1, slab_view(v, z0, z1))
+        parts.append(g.tips(0, 0.0, 1, 0.0))
+    p_s = np.concatenate([p for _, p in parts])
+    n_s = sum(st[0] for st, _ in parts)
+    print("tips: whole", st_w[0], "slabs", [st[0] for st, _ in parts])
+    assert st_w[0] > 20 and n_s == st_w[0] and p_s.shape == p_w.shape
+    kw, ks = np.lexsort(p_w.T[::-1]), np.lexsort(p_s.T[::-1])
+    assert np.array_equal(p_w[kw], p_s[ks])
+    mean_s = sum(st[0] * st[1:4] for st, _ in parts) / n_s
+    assert np.allclose(mean_s, st_w[1:4], rtol=1e-12, atol=0)
+
+
 def test_tp06_shell_slabs_equal_whole_box_and_ecg_sums(B):
     """The down-scaled TP06 double shell (128x128x96) in 8 tissue-balanced slabs, FP32,
     200 steps of the S1 wave: bitwise equal V; the slabs' pseudo-ECGs sum to the whole
