@@ -823,7 +823,7 @@ def main():
                     help="run the full 1 s TP06 scroll-wave protocol (and S1 alone) and write "
                          "its summary to OUT.json, instead of the benchmark")
     ap.add_argument("--profile", choices=["crn", "crn_tab", "stencil", "stencil_iso", "ensemble", "tp06",
-                                          "train"],
+                                          "train", "surrogate"],
                     default=None,
                     help="counter-collection mode: a few steps of one workload, then one plain "
                          "256 MiB device copy whose byte count calibrates FETCH_SIZE/WRITE_SIZE")
@@ -868,6 +868,18 @@ def main():
             m.fit_norm(S, S1)
             m.train(S, S1, 4096, args.warmup + args.steps, 1e-3)
             m.close()
+        elif args.profile == "surrogate":
+            # the surrogate step on the CRN cup with every voxel offered to the network
+            # (a network trained for 4,000 steps on one paced run; accept-all input box)
+            from paper_1605_06015_amd import surrogate as SU
+            S, S1 = SU.generate_pairs(runs=1, t_ms=600.0, per_sample=2048, seed=2, stream=stream,
+                                      model="crn")
+            tr = SU.train(S, S1, batch=4096, seed=0, stream=stream, model="crn", schedule=((4000, 1e-3),))
+            del S, S1
+            grid, _ = crn_workload(B.BBX_FP32, stream)
+            grid.surrogate(tr.mlp, np.full(21, -1e30, np.float32), np.full(21, 1e30, np.float32), 1e30)
+            grid.step(args.warmup + args.steps)
+            grid.close()
         elif args.profile == "stencil_iso":
             _stencil_case(stream, np.ones((384, 512, 512), np.uint8), 0.2, None, args.steps,
                           args.warmup, 8)
