@@ -30,6 +30,10 @@
  *     null stream).  bbx_step is asynchronous except for its optional
  *     finite-value check (bbx_nan_check_set).
  *   - Threading: a grid is not thread-safe; distinct grids are independent.
+ *   - Log: with the environment variable BBX_LOG set to a non-zero value (read
+ *     once, at the library's first log), every failed call writes its code and
+ *     message, and grid creation, model set-up and surrogate attachment write
+ *     one line each, to stderr, prefixed "bbx: ".
  */
 #ifndef BBX_H
 #define BBX_H

@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <mutex>
@@ -21,6 +22,28 @@ namespace {
 
 thread_local std::string g_err;
 
+// Host-side log on stderr, on when the environment variable BBX_LOG is set to a
+// non-zero value when the library first logs: set-up calls and every failed call.
+bool log_on()
+{
+    static const bool on = [] {
+        const char *v = getenv("BBX_LOG");
+        return v && *v && strcmp(v, "0") != 0;
+    }();
+    return on;
+}
+
+void log_line(const char *fmt, ...)
+{
+    if (!log_on()) return;
+    char buf[640];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "bbx: %s\n", buf);
+}
+
 int fail(int code, const char *fmt, ...)
 {
     char buf[512];
@@ -29,6 +52,7 @@ int fail(int code, const char *fmt, ...)
     vsnprintf(buf, sizeof buf, fmt, ap);
     va_end(ap);
     g_err = buf;
+    log_line("error %d: %s", code, buf);
     return code;
 }
 
@@ -883,8 +907,11 @@ int readout_impl(bbx_grid *g, int what, int var, const uint8_t *region, void *ou
 int bbx::api_error(int code, const char *msg)
 {
     g_err = msg;
+    log_line("error %d: %s", code, msg);
     return code;
 }
+
+void bbx::api_log(const char *msg) { log_line("%s", msg); }
 
 void bbx::api_clear_error() { g_err.clear(); }
 
@@ -940,6 +967,11 @@ int grid_create_common(int nx, int ny, int nz, double h, const uint8_t *mask, co
         return rc;
     }
     g->h_stimbits.assign((size_t)g->nact, 0u);
+    log_line("grid %p: %dx%dx%d box, %lld tissue voxels (%s), %s, %s, planes [%d, %d) own, "
+             "explicit diffusion dt bound %g ms", (void *)g, nx, ny, nz, (long long)g->nact,
+             g->dense ? "dense" : "tissue list", g->aniso ? "anisotropic" : "isotropic",
+             precision == BBX_FP64 ? "FP64" : "FP32", own0, own1,
+             g->wsum_max > 0 ? 2.0 / g->wsum_max : 0.0);
     *out = g;
     return BBX_OK;
 }
@@ -1114,6 +1146,8 @@ int bbx_model_set(bbx_grid *g, int model, const double *params, int nparams, dou
         for (int i = 0; i < kMaxParams; i++) g->prm[i] = i < np ? params[i] : 0.0;
         g->n = 0;
         graph_drop(g);
+        log_line("grid %p: model %d (%d variables), dt %g ms, %s scheme", (void *)g, model, nv, dt,
+                 scheme == BBX_SCHEME_SPLIT ? "split" : "additive");
         return build_table(g);
     } catch (...) {
         return fail(BBX_ENOMEM, "host allocation failed");
@@ -1850,6 +1884,8 @@ int surrogate_finish(bbx_grid *g, const float *lo, const float *hi, float dv_max
     g->dv_max = dv_max;
     g->sur = 1;
     graph_drop(g);
+    log_line("grid %p: surrogate attached (%d -> 128 -> 128 -> %d, |dV| <= %g mV per step)", (void *)g,
+             g->snet.nin, g->snet.nout, dv_max);
     return BBX_OK;
 }
 

@@ -89,6 +89,7 @@ constexpr int kTileY = kBlock / kTileX;
 // The calling thread's last-error message, shared by all entry points.
 int api_error(int code, const char *msg);
 void api_clear_error();
+void api_log(const char *msg);   // one line on stderr when BBX_LOG is set
 
 // Launchers (step_kernels.hip).  Return hipSuccess or the launch error.
 template <typename T>

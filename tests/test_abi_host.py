@@ -151,3 +151,25 @@ def test_slab_validation_before_device(bbx):
     lib = bbx._lib
     assert lib.bbx_halo_pack(None, 0, None, 0) == E
     assert lib.bbx_halo_unpack(None, 1, None, 0) == E
+
+
+def test_log_switch_reports_failures(bbx):
+    """BBX_LOG=1 makes a failing call write its code and message to stderr (a child
+    process, so that the switch is read fresh); without it the library stays silent."""
+    import subprocess
+    import sys
+    code = ("import numpy as np; from paper_1605_06015_amd import bbx as B\n"
+            "try:\n"
+            "    B.bbx_slab_bounds(np.ones((4, 3, 3), np.uint8), 9)\n"
+            "except B.BBXError as e:\n"
+            "    print('raised', e.code)\n")
+    out = {}
+    for flag in ("1", "0"):
+        env = dict(os.environ, BBX_LOG=flag)
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True,
+                           text=True, timeout=120)
+        assert r.returncode == 0, r.stderr
+        assert "raised" in r.stdout
+        out[flag] = r.stderr
+    assert "bbx: error -1: nslab must be in [1, nz]" in out["1"]
+    assert "bbx:" not in out["0"]
