@@ -438,22 +438,28 @@ def copy_bandwidth(stream, nbytes=1 << 30, reps=20):
     return 2 * nbytes * reps / sec / 1e9
 
 
-def surrogate_shell(stream, tr, v_hi, t_ms):
-    """The trained TP06 surrogate-with-fallback against the plain FP32 step on the
-    512x512x384 double shell (25.2 M tissue voxels), S1 strip only, t_ms of the wave's
-    spread: step time of each and the activation-time error over the voxels either run
-    activated (APD90 needs the full beat and is not recorded in so short a run)."""
+def _shell_runs(stream, tr, g3, t_ms, v_his):
+    """The plain FP32 TP06 run and one surrogate run per threshold in v_his on a double
+    shell g3 (S1 strip only), t_ms long: step times, network share, and the activation-time
+    error against the plain run over the voxels both activated (APD90 needs the full beat
+    and is not recorded in so short a run)."""
     import torch
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import surrogate as SU
     from paper_1605_06015_amd import workloads as WL
-    nsteps = None
-    res = {}
-    mask = shell_geometry()["mask"].astype(bool)
-    for name in ("plain", "surrogate"):
-        grid, _, c = tp06_workload(stream, with_s2=False)
-        nsteps = int(round(t_ms / c["dt"]))
-        if name == "surrogate":
+    c = WL.TP06_3D
+    nsteps = int(round(t_ms / c["dt"]))
+    mask = g3["mask"].astype(bool)
+
+    def one(v_hi):
+        grid = B.Grid(g3["mask"], c["h"], g3["fibre"], c["Dpar"], c["Dperp"], B.BBX_FP32, stream)
+        grid.model(B.BBX_MODEL_TP06, [], c["dt"])
+        for v, val in enumerate(WL.TP06_INITIAL):
+            grid.fill(v, val)
+        grid.stimulus(g3["s1"], c["s1_amp"], 0.0, c["s1_ms"])
+        grid.record(c["theta"])
+        grid.nan_check(0)
+        if v_hi is not None:
             lo, hi, dv = SU.accepted_box(tr.stats, nvar=len(WL.TP06_INITIAL))
             hi[0] = v_hi
             grid.surrogate(tr.mlp, lo, hi, dv)
@@ -464,26 +470,66 @@ def surrogate_shell(stream, tr, v_hi, t_ms):
         grid.step(nsteps - 10)
         ev[1].record(stream)
         torch.cuda.synchronize()
-        sec = ev[0].elapsed_time(ev[1]) / 1e3
-        fb = int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]) if name == "surrogate" else 0
         if grid.read(B.BBX_READ_NAN_FLAG)[0]:
-            raise RuntimeError(f"non-finite state in the shell {name} run")
-        res[name] = dict(at=grid.read(B.BBX_READ_ACT_TIME)[mask], sec=sec, fb=fb, nact=grid.nact,
-                         dt=c["dt"])
+            raise RuntimeError("non-finite state in a shell run")
+        out = dict(at=grid.read(B.BBX_READ_ACT_TIME)[mask], per=ev[0].elapsed_time(ev[1]) / 1e3 / (nsteps - 10),
+                   fb=int(grid.read(B.BBX_READ_FALLBACK_COUNT)[0]) if v_hi is not None else 0,
+                   nact=grid.nact)
         grid.close()
-    p, q = res["plain"], res["surrogate"]
-    fa, fq = np.isfinite(p["at"]), np.isfinite(q["at"])
-    both = fa & fq
-    dat = np.abs(p["at"][both] - q["at"][both])
-    per_p, per_q = p["sec"] / (nsteps - 10), q["sec"] / (nsteps - 10)
-    return {"workload": f"TP06 512x512x384 double shell ({p['nact']} tissue voxels), S1 strip, first "
-                        f"{t_ms:.0f} ms, FP32", "accepted_v_below_mV": v_hi,
-            "value": p["nact"] / per_q, "unit": "voxel-updates/s", "ms_per_step": per_q * 1e3,
-            "plain_ms_per_step": per_p * 1e3, "speedup_vs_plain": per_p / per_q,
-            "surrogate_share": 1.0 - q["fb"] / (q["nact"] * float(nsteps)),
-            "activated_voxels": int(fa.sum()), "same_activated_set": bool(np.array_equal(fa, fq)),
-            "at_err_vs_plain_ms": {"max": float(dat.max()) if dat.size else None,
-                                   "mean": float(dat.mean()) if dat.size else None, "dt": p["dt"]}}
+        return out
+
+    plain = one(None)
+    res = {}
+    for v_hi in v_his:
+        q = one(v_hi)
+        fa, fq = np.isfinite(plain["at"]), np.isfinite(q["at"])
+        both = fa & fq
+        dat = np.abs(plain["at"][both] - q["at"][both])
+        res[float(v_hi)] = dict(share=1.0 - q["fb"] / (q["nact"] * float(nsteps)),
+                                same_activated=bool(np.array_equal(fa, fq)),
+                                at_max=float(dat.max()) if dat.size else None,
+                                at_mean=float(dat.mean()) if dat.size else None,
+                                ms_per_step=q["per"] * 1e3, speed_vs_plain=plain["per"] / q["per"])
+    return plain, res, c["dt"]
+
+
+def surrogate_shell(stream, tr, t_ms, v_hi_cup):
+    """The trained TP06 surrogate-with-fallback against the plain FP32 step on the
+    512x512x384 double shell (25.2 M tissue voxels), S1 strip only, the first t_ms of the
+    wave's spread.  The acceptance threshold is chosen on a held-out shell of the same
+    family (256x256x192, geometry seed 11), run for the same time, by the cup's rule (the
+    largest network share whose activation times stay within 1 dt of the plain run's,
+    same activated set): on a shell, resting tissue waits longer for the wave than on the
+    cup, so a threshold chosen on the cup does not carry over.  If no threshold meets the
+    rule there, the shell runs at the cup's threshold (v_hi_cup) and says so."""
+    from paper_1605_06015_amd import workloads as WL
+    c = WL.TP06_3D
+    rest = WL.TP06_INITIAL[0]
+    cands = [round(rest + o, 4) for o in (-0.2, -0.1, -0.05, -0.02, -0.01, 0.0, 0.01)]
+    held = WL.tp06_biv(256, 256, 192, c["h"], 11, c["active"], c["s1_strip"])
+    _, sweep, dt = _shell_runs(stream, tr, held, t_ms, cands)
+    ok = [v for v in cands if sweep[v]["same_activated"] and sweep[v]["at_max"] is not None
+          and sweep[v]["at_max"] <= dt]
+    v_hi = max(ok, key=lambda v: (sweep[v]["share"], -v)) if ok else None
+    sel = {"held_out": "double shell 256x256x192, geometry seed 11 (the benchmark shell: "
+                       f"512x512x384, seed {c['seed']})", "rule": "largest share with AT within "
+                       "1 dt of plain", "chosen_v_hi_mV": v_hi, "sweep": {str(k): v for k, v in sweep.items()}}
+    if v_hi is None:
+        v_hi = v_hi_cup
+        sel["note"] = ("no threshold met the accuracy rule on the held-out shell; the benchmark "
+                       "shell runs at the threshold chosen on the held-out cup")
+    plain, res, dt = _shell_runs(stream, tr, shell_geometry(), t_ms, (v_hi,))
+    r = res[float(v_hi)]
+    return {"workload": f"TP06 512x512x384 double shell ({plain['nact']} tissue voxels), S1 strip, "
+                        f"first {t_ms:.0f} ms, FP32",
+            "threshold_selection": sel, "accepted_v_below_mV": v_hi,
+            "value": plain["nact"] / (r["ms_per_step"] * 1e-3), "unit": "voxel-updates/s",
+            "ms_per_step": r["ms_per_step"], "plain_ms_per_step": plain["per"] * 1e3,
+            "speedup_vs_plain": r["speed_vs_plain"], "surrogate_share": r["share"],
+            "activated_voxels": int(np.isfinite(plain["at"]).sum()),
+            "same_activated_set": r["same_activated"],
+            "at_within_1dt": bool(r["at_max"] is not None and r["at_max"] <= dt and r["same_activated"]),
+            "at_err_vs_plain_ms": {"max": r["at_max"], "mean": r["at_mean"], "dt": dt}}
 
 
 def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
@@ -558,7 +604,7 @@ def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
                                           "soft_bound_ms": 2.0},
                 "error_vs_fp64_oracle": vs_oracle})
     if shell_ms and model == "tp06":
-        out["shell_512x512x384"] = surrogate_shell(stream, tr, v_hi, shell_ms)
+        out["shell_512x512x384"] = surrogate_shell(stream, tr, shell_ms, v_hi)
     return out
 
 
