@@ -91,11 +91,13 @@ static int chi(int nx, int ny, int nz, const uint8_t *mask, int x, int y, int z)
  *  Wbar:   chi_{p+q}/h^2 * { D^p_jj on faces q=+-q_j;
  *                            +D^p_jk/2 on edges q=+-(q_j+q_k);
  *                            -D^p_jk/2 on edges q=+-(q_j-q_k);  0 on corners }
- *          (each unordered pair j<k gives one edge weight: reading G5);
+ *          (each unordered pair j<k gives one edge weight, as quadratic
+ *          exactness requires);
  *  Wtilde: chi_{p+q} chi_{p-q}/(4h^2) * (+-) sum_j (D^{p+q_j}_jk - D^{p-q_j}_jk)
  *          on faces q=+-q_k, 0 elsewhere.
  * D at a void or out-of-box neighbour inside Wtilde is replaced by D^p
- * (reading G6).  Returns 0, or -1 if a tissue fibre has (near) zero length. */
+ * (the paper leaves that case open).  Returns 0, or -1 if a tissue fibre has
+ * (near) zero length. */
 int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
                 const double *fibre, double Dpar, double Dperp,
                 int64_t nact, const int64_t *act, double *W)
@@ -162,7 +164,8 @@ int orc_weights(int nx, int ny, int nz, double h, const uint8_t *mask,
 }
 
 /* (L u)_p = sum_q W^p_q u_{p+q}, written in the equivalent difference form
- * sum_{q!=0} W^p_q (u_{p+q} - u_p) (reading G13); out-of-box q have W = 0. */
+ * sum_{q!=0} W^p_q (u_{p+q} - u_p) (the difference form: equal in exact arithmetic,
+ * and a constant field stays exactly constant); out-of-box q have W = 0. */
 static double apply_L(int nx, int ny, int nz, const double *w, const double *u, int64_t idx)
 {
     int x = (int)(idx % nx), y = (int)((idx / nx) % ny), z = (int)(idx / ((int64_t)nx * ny));
@@ -248,7 +251,8 @@ static void zfk_rates(const double *p, const double *y, double *rate)
 }
 
 /* Cubic FitzHugh-Nagumo `fhncub`, eq (FHN): u' = (u - u^3/3 - v)/eps,
- * v' = eps (u + beta - gamma v) (cubic term per eq (fhn): reading G3). */
+ * v' = eps (u + beta - gamma v) (the ODE's cubic term; the discrete update's
+ * printed square is taken as a misprint). */
 static void fhn_rates(const double *p, const double *y, double *rate)
 {
     double eps = p[0], bet = p[1], gam = p[2];
@@ -587,8 +591,8 @@ int orc_model_eval(int model, const double *p, const double *y,
 
 /* ------------------------------------------------------------------------- */
 /* Stimulus: I_stim,p(n) = sum_s A_s [p in R_s] [step n inside a window of s] */
-/* (external current term of eq (monodomain); reading G4: positive A         */
-/* depolarises; reading G12: windows in whole steps).                        */
+/* (external current term of eq (monodomain): a positive A depolarises;      */
+/* windows are counted in whole steps).                                      */
 /* ------------------------------------------------------------------------- */
 /* Right-hand side of one voxel's kinetics at state y, with the forcing F (stimulus,
  * plus L V in the additive scheme) added to dV/dt: out[0] = -I_ion + F; gates
@@ -635,7 +639,7 @@ static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t c
 
 /* ------------------------------------------------------------------------- */
 /* Time stepping ("Splitting the problem into parts"; eq (Euler); eqs (RL),  */
-/* (RLcoeff) in the corrected order y_{n+1} = B + A y_n: reading G1).        */
+/* (RLcoeff) in the order y_{n+1} = B + A y_n, the one exact for frozen V).  */
 /* ------------------------------------------------------------------------- */
 /*
  * Advances state (box layout [nvar][nbox]) by nsteps steps, the first of
@@ -647,7 +651,7 @@ static int stim_on(int64_t n, int64_t n0, int64_t len, int64_t period, int64_t c
  * integrator = I_RK4 every variable instead takes one classical RK4 step of its ODE,
  * with I_stim (additive: and LV) held constant through the stages.
  * If record != 0, activation time, peak and APD90 are detected from the pair
- * (V_n, V_{n+1}) per voxel (reading G23): status 0 -> 1 on the first upward
+ * (V_n, V_{n+1}) per voxel: status 0 -> 1 on the first upward
  * crossing of theta (AT linearly interpolated), 1 -> 2 at the first decrease
  * (vmax = V_n), 2 -> 3 at the first downward crossing of
  * vrest + 0.1 (vmax - vrest) (APD90 = interpolated time - AT).
