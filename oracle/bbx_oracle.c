@@ -26,14 +26,16 @@
  *     continuous no-flux problem conserves it for any tensor).
  *   - Courtemanche-Ramirez-Nattel 1998 cell model: transcribed from the
  *     original model publication (not part of the paper); parity partially
- *     pinned, by that publication's resting state and action-potential shape.
+ *     pinned, by that publication's resting state and action-potential shape,
+ *     and by charge conservation of its concentration equations.
  *   - four-variable Fenton-Karma-type minimal model (Bueno-Orovio, Cherry &
  *     Fenton 2008, epicardial set): transcribed from that publication; pinned
  *     by its exact resting state and the closed-form subthreshold relaxation;
  *     its suprathreshold constants are partially pinned (action-potential shape).
  *   - ten Tusscher-Panfilov 2006 ventricular model (epicardial): transcribed
- *     from its publications; parity partially pinned, by its resting state and
- *     action-potential shape.
+ *     from its publications; parity partially pinned, by its resting state,
+ *     action-potential shape and charge conservation of its concentration
+ *     equations.
  */
 #include <math.h>
 #include <stdint.h>

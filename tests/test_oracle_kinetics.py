@@ -3,7 +3,8 @@ test system (eq (Euler)), Rush-Larsen exactness for frozen voltage (eqs (RL),
 (RLcoeff), corrected order), first-order convergence of the coupled
 Euler/Rush-Larsen stepper to an accurate ODE solution, the special cases of
 the Barkley / FHN / ZFK kinetics, and the published resting state and action
-potential of the Courtemanche-Ramirez-Nattel model."""
+potential of the Courtemanche-Ramirez-Nattel model, and charge conservation of the
+Courtemanche-Ramirez-Nattel and ten Tusscher-Panfilov concentration equations."""
 import numpy as np
 import pytest
 from scipy.integrate import solve_ivp
@@ -382,3 +383,88 @@ def test_tp06_removable_singularity_and_branch(Vs):
         if Vs == 15.0:
             assert abs(r0[0] - 0.5 * (rm[0] + rp[0])) < 1e-6 * max(1.0, abs(r0[0]))
     assert np.all(np.isfinite(r0)) and np.all(np.isfinite(t0[7:])) and np.all(t0[7:] > 0)
+
+
+# ------------------------------------------------ charge conservation (both ionic models)
+# Every transmembrane current of the two detailed models is carried by one ion species,
+# and every intracellular calcium flux moves calcium between compartments, so the total
+# charge of membrane plus cell contents, Q = Cm V - F sum_k z_k vol_k c_k (buffered calcium
+# counted in full), is constant along the continuous kinetics.  The check is independent
+# of the current formulas themselves: it catches a current dropped from, or added twice
+# to, a concentration equation, a wrong stoichiometric factor (3 Na per Na/K pump or
+# exchanger cycle), a wrong compartment volume ratio or a wrong buffer factor.  Each
+# model's own constants (capacitance, volumes, buffers, Faraday's constant) are those of
+# its publication, restated here.
+
+def _random_states(rng, n, base, ranges):
+    Y = np.tile(np.array(base, float), (n, 1))
+    Y[:, 0] = rng.uniform(-90.0, 50.0, n)
+    for i, (lo, hi) in ranges.items():
+        Y[:, i] = rng.uniform(lo, hi, n)
+    gates = [i for i in range(1, Y.shape[1]) if i not in ranges]
+    Y[:, gates] = rng.uniform(0.0, 1.0, (n, len(gates)))
+    return Y
+
+
+def _buffered(c, total, k):
+    """d(c + total c / (c + k)) / dc: the rapid-buffering factor."""
+    return 1.0 + total * k / (c + k) ** 2
+
+
+def test_crn_charge_conserved_by_rates():
+    """CRN: Cm V' = F (Vi (Nai' + Ki' + 2 CaiT') + 2 Vup Caup' + 2 Vrel CarelT') at any state
+    (Cm pF, volumes um^3, F C/mmol: both sides in pA), with CaiT buffered by troponin and
+    calmodulin and CarelT by calsequestrin."""
+    Cm, Vi, Vup, Vrel, F = 100.0, 13668.0, 1109.52, 96.48, 96.4867
+    rng = np.random.default_rng(31)
+    ranges = {1: (5.0, 20.0), 2: (125.0, 145.0), 3: (2e-5, 2e-3), 4: (0.3, 3.0), 5: (0.1, 3.0)}
+    for y in _random_states(rng, 400, WL.CRN_INITIAL, ranges):
+        r, _, _ = O.model_eval(O.MODEL_CRN, [], y)
+        bi = _buffered(y[3], 0.07, 0.0005) + _buffered(y[3], 0.05, 0.00238) - 1.0
+        brel = _buffered(y[5], 10.0, 0.8)
+        mem = Cm * r[0]
+        ions = F * (Vi * (r[1] + r[2] + 2.0 * r[3] * bi) + 2.0 * Vup * r[4] + 2.0 * Vrel * r[5] * brel)
+        scale = abs(mem) + F * (Vi * (abs(r[1]) + abs(r[2]) + 2 * abs(r[3]) * bi)
+                                + 2 * Vup * abs(r[4]) + 2 * Vrel * abs(r[5]) * brel)
+        assert abs(mem - ions) <= 1e-12 * scale + 1e-12, (y[0], mem, ions)
+
+
+def test_tp06_charge_conserved_by_rates():
+    """TP06: Cm V' = F (Vc (Ki' + Nai' + 2 CaiT') + 2 Vsr CaSRT' + 2 Vss CassT') at any state
+    (Cm uF, volumes uL, F C/mol: both sides in nA), each calcium pool with its own buffer."""
+    Cm, Vc, Vsr, Vss, F = 0.185, 0.016404, 0.001094, 0.00005468, 96485.3415
+    rng = np.random.default_rng(32)
+    ranges = {1: (125.0, 145.0), 2: (5.0, 20.0), 3: (2e-5, 2e-3), 4: (2e-5, 5e-3), 5: (0.5, 5.0),
+              6: (0.0, 1.0)}
+    for y in _random_states(rng, 400, WL.TP06_INITIAL, ranges):
+        r, _, _ = O.model_eval(O.MODEL_TP06, [], y)
+        bc, bss, bsr = _buffered(y[3], 0.2, 0.001), _buffered(y[4], 0.4, 0.00025), _buffered(y[5], 10.0, 0.3)
+        mem = Cm * r[0]
+        ions = F * (Vc * (r[1] + r[2] + 2.0 * r[3] * bc) + 2.0 * Vsr * r[5] * bsr + 2.0 * Vss * r[4] * bss)
+        scale = abs(mem) + F * (Vc * (abs(r[1]) + abs(r[2]) + 2 * abs(r[3]) * bc)
+                                + 2 * Vsr * abs(r[5]) * bsr + 2 * Vss * abs(r[4]) * bss)
+        assert abs(mem - ions) <= 1e-12 * scale + 1e-12, (y[0], mem, ions)
+
+
+def test_tp06_stepper_charge_drift_first_order():
+    """Over a whole action potential the stepped cell's charge changes by the stimulus
+    charge Cm amp dur plus a drift of the explicit scheme (the buffered calcium pools are
+    advanced in their free concentrations), which halves with dt."""
+    Cm, Vc, Vsr, Vss, F = 0.185, 0.016404, 0.001094, 0.00005468, 96485.3415
+
+    def Q(y):
+        cai = y[3] + 0.2 * y[3] / (y[3] + 0.001)
+        css = y[4] + 0.4 * y[4] / (y[4] + 0.00025)
+        csr = y[5] + 10.0 * y[5] / (y[5] + 0.3)
+        return Cm * y[0] - F * (Vc * (y[1] + y[2] + 2 * cai) + 2 * Vsr * csr + 2 * Vss * css)
+
+    amp, dur, drift = 52.0, 1.0, []
+    for dt in (0.02, 0.01):
+        s = tp06_cell(dt, stim=[O.Stimulus(ONE, amp, 0, int(round(dur / dt)))])
+        y0 = s.state[:, 0, 0, 0].copy()
+        s.step(int(round(400.0 / dt)))
+        y1 = s.state[:, 0, 0, 0]
+        assert -86.5 < y1[0] < -84.0                    # back at rest after one beat
+        drift.append(Q(y1) - Q(y0) - Cm * amp * dur)
+    assert abs(drift[1]) < 0.15 * Cm * amp * dur        # small beside the stimulus charge
+    assert 1.8 < drift[0] / drift[1] < 2.2              # first order in dt
