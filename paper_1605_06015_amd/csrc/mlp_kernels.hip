@@ -724,7 +724,8 @@ template <class M, bool ANISO>
 __global__ __launch_bounds__(kSurBlock) void k_sur_net(const StepArgs<float> a, const SurArgs su)
 {
     constexpr int NV = M::NV;
-    static_assert(NV <= kSurRow, "a voxel's outputs must fit in its staging row");
+    // outputs are written four at a time (units 4g..4g+3 of a 16-unit tile)
+    static_assert((NV + 3) / 4 * 4 <= kSurRow, "a voxel's outputs must fit in its staging row");
     constexpr int kSlots = kBlock / 64;                 // 64-voxel slots per list segment
     const Clock<float> ck = step_clock(a);
     constexpr int NW = kSurBlock / 64;
