@@ -28,7 +28,24 @@ sys.path.insert(0, ROOT)
 
 METRIC = "voxel-updates/s (FP32 plain vs surrogate) at ≤1dt activation-time error; %HBM roof"
 HBM_PEAK_GBS = 8000.0
-VALU_PEAK_GINST = 614.4   # 256 CUs x 2.4 GHz x one wave64 VALU instruction per CU-cycle
+# VALU issue on gfx950, in issue slots: one slot is one SIMD quad-cycle (the time a SIMD
+# takes to issue a wave64 instruction with no pairing), so the chip has 256 CUs x 4 SIMDs
+# x 2.4 GHz / 4 = 614.4 G slots/s.  Measured slot costs per wave64 instruction (the issue-
+# rate probe paper_1605_06015_amd/measure/valu_issue_rate.hip and its counters): a
+# 2-source operation (mul, add, integer, compare, select) can pair with another in one
+# slot (1,175 G mul/s = 1.9 per CU-cycle), a 3-source FMA takes a whole slot (626 G/s), a
+# transcendental two (301 G/s).  The floor of a kernel is its counters' mix at those
+# costs; SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2 counts the slots it actually used.
+VALU_SLOT_PEAK_G = 256 * 4 * 2.4 / 4
+VALU_SLOTS_TRANS, VALU_SLOTS_FMA, VALU_SLOTS_OTHER = 2.0, 1.0, 0.5
+
+
+def valu_floor_slots(ctr) -> float:
+    """Issue slots a kernel's VALU mix needs at best (per-class costs above)."""
+    n, tr, fma = ctr["valu_insts_per_launch"], ctr["valu_trans_per_launch"], ctr["valu_fma_per_launch"]
+    return VALU_SLOTS_TRANS * tr + VALU_SLOTS_FMA * fma + VALU_SLOTS_OTHER * (n - tr - fma)
+
+
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 STEP_SOURCES = [os.path.join(ROOT, "paper_1605_06015_amd", "csrc", f)
                 for f in ("step_kernels.hip", "step_device.h", "kinetics.h", "bbx_internal.h")]
@@ -971,14 +988,24 @@ def main():
            "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes_per_voxel": CRN_BYTES_PER_VOXEL,
            "layout_bytes_per_voxel": CRN_LAYOUT_BYTES_PER_VOXEL,
            "note": "the step's 77 MB (layout) working set stays in the 256 MB Infinity Cache"}
-    if ctr and ctr.get("valu_insts_per_launch"):
-        # the binding resource: VALU issue (one wave64 instruction per CU per cycle, 256
-        # CUs at 2.4 GHz) and latency; the VALU instructions per launch come from the
-        # committed counters of this same kernel source
-        gi = ctr["valu_insts_per_launch"] / per_launch / 1e9
-        roof = {"bound": "alu", "achieved": round(gi, 1), "peak": VALU_PEAK_GINST,
-                "unit": "G wave-instructions/s", "frac": round(gi / VALU_PEAK_GINST, 4),
-                "traffic": traffic, "insts_per_launch": ctr["valu_insts_per_launch"]}
+    if ctr and ctr.get("valu_slots_used_per_launch"):
+        # the binding resource: VALU issue and latency.  achieved = the issue slots the
+        # kernel's instruction mix needs at best, per second; beside it, the share of the
+        # chip's slots the kernel actually occupied (both from the committed counters of
+        # this same kernel source, over the differenced per-launch time)
+        floor = valu_floor_slots(ctr)
+        gs = floor / per_launch / 1e9
+        used = ctr["valu_slots_used_per_launch"] / (VALU_SLOT_PEAK_G * 1e9 * per_launch)
+        roof = {"bound": "alu", "achieved": round(gs, 1), "peak": VALU_SLOT_PEAK_G,
+                "unit": "G VALU issue slots/s", "frac": round(gs / VALU_SLOT_PEAK_G, 4),
+                "traffic": traffic, "issue_busy": round(used, 4),
+                "valu_per_launch": {"insts": ctr["valu_insts_per_launch"],
+                                    "trans": ctr["valu_trans_per_launch"],
+                                    "fma": ctr["valu_fma_per_launch"],
+                                    "slots_floor": round(floor),
+                                    "slots_used": ctr["valu_slots_used_per_launch"]},
+                "slot_costs": {"transcendental": VALU_SLOTS_TRANS, "fma": VALU_SLOTS_FMA,
+                               "other": VALU_SLOTS_OTHER}}
     else:
         roof = {"bound": "hbm", "achieved": hbm["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": hbm["frac"], "traffic": traffic,

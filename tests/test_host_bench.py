@@ -21,16 +21,30 @@ def test_bench_refuses_more_than_one_gpu():
 
 
 def test_counter_summary_is_consistent():
-    """The committed counter file of the headline kernel: bytes add up, the VALU count
-    is there, and the traffic is within 10% of the bytes the library's layout moves (and
-    not below the algorithmic floor)."""
+    """The committed counter file of the headline kernel: taken on the current kernel
+    sources (else the benchmark line drops its traffic and VALU figures), bytes add up,
+    the traffic is within 10% of the bytes the library's layout moves (and not below the
+    algorithmic floor), and the VALU mix is complete: its classes fit in the total and the
+    issue slots the kernel used are at least the floor of its mix."""
     d = json.load(open(os.path.join(ROOT, "profiles", "step_crn_cup128_fp32_traffic.json")))
+    assert d["source_hash"] == bench.source_hash()
     assert d["bytes_per_launch"] == d["bytes_read"] + d["bytes_written"]
-    assert d["valu_insts_per_launch"] > 0 and d["waves_per_launch"] > 0
     layout = bench.CRN_LAYOUT_BYTES_PER_VOXEL * 367000
     assert 0.9 * layout <= d["bytes_per_launch"] <= 1.1 * layout
     assert d["bytes_per_launch"] >= bench.CRN_BYTES_PER_VOXEL * 367000
-    assert len(d["source_hash"]) == 16
+    n, tr, fma = d["valu_insts_per_launch"], d["valu_trans_per_launch"], d["valu_fma_per_launch"]
+    assert d["waves_per_launch"] > 0 and 0 < tr and 0 < fma and tr + fma < n
+    assert bench.valu_floor_slots(d) <= d["valu_slots_used_per_launch"] <= n + tr
+
+
+def test_valu_slot_model():
+    """Issue-slot costs: a 2-source instruction half a slot, a 3-source FMA one, a
+    transcendental two; the chip's 1,024 SIMDs issue 614.4 G slots/s at 2.4 GHz."""
+    assert bench.VALU_SLOT_PEAK_G == 614.4
+    only = lambda n, tr=0, fma=0: bench.valu_floor_slots(
+        {"valu_insts_per_launch": n, "valu_trans_per_launch": tr, "valu_fma_per_launch": fma})
+    assert only(100) == 50 and only(100, tr=100) == 200 and only(100, fma=100) == 100
+    assert only(10, tr=2, fma=3) == 2 * 2 + 3 + 0.5 * 5
 
 
 def test_golden_maps_match_the_workload():
