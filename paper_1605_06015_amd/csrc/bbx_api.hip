@@ -1850,12 +1850,13 @@ int surrogate_check(const bbx_grid *g, int nin, int nout, const float *lo, const
 // Device buffers of the grid's network copy and its step lists (first attachment).
 int surrogate_alloc(bbx_grid *g, int nin, int nout)
 {
-    if (g->snet.w1) return BBX_OK;
+    if (g->sur_nblk) return BBX_OK;                 // set once every buffer below is in place
     hipError_t e;
     g->snet.nin = nin;
     g->snet.nout = nout;
     // one list segment per classifier workgroup (kBlock voxels)
     const int nb = (int)((g->nact + kBlock - 1) / kBlock);
+    const size_t bytes0 = g->bytes;
     if ((e = dalloc(g, &g->snet.w1, kH * kS1 * sizeof(__bf16))) != hipSuccess ||
         (e = dalloc(g, &g->snet.w2, kH * kS2 * sizeof(__bf16))) != hipSuccess ||
         (e = dalloc(g, &g->snet.w3, kP * kS2 * sizeof(__bf16))) != hipSuccess ||
@@ -1865,9 +1866,20 @@ int surrogate_alloc(bbx_grid *g, int nin, int nout)
         (e = dalloc(g, &g->d_shi, kP * sizeof(float))) != hipSuccess ||
         (e = dalloc(g, &g->d_acc_list, (size_t)(nb ? nb : 1) * kBlock * sizeof(int32_t))) != hipSuccess ||
         (e = dalloc(g, &g->d_acc_cnt, (size_t)(nb ? nb : 1) * sizeof(int32_t))) != hipSuccess ||
-        (e = dalloc(g, &g->d_fb, (size_t)(nb ? nb : 1) * sizeof(unsigned long long))) != hipSuccess)
+        (e = dalloc(g, &g->d_fb, (size_t)(nb ? nb : 1) * sizeof(unsigned long long))) != hipSuccess) {
+        // a failed attempt keeps nothing, so that a later one starts from scratch
+        void **ps[] = {(void **)&g->snet.w1, (void **)&g->snet.w2, (void **)&g->snet.w3,
+                       (void **)&g->snet.bias, (void **)&g->snet.norm, (void **)&g->d_slo,
+                       (void **)&g->d_shi, (void **)&g->d_acc_list, (void **)&g->d_acc_cnt,
+                       (void **)&g->d_fb};
+        for (void **p : ps) {
+            dfree(*p);
+            *p = nullptr;
+        }
+        g->bytes = bytes0;
         return hip_fail(e, "hipMalloc");
-    g->sur_nblk = nb;
+    }
+    g->sur_nblk = nb > 0 ? nb : 1;
     return BBX_OK;
 }
 
