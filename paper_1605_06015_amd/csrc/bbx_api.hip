@@ -413,7 +413,10 @@ int graph_steps(bbx_grid *g, int64_t nsteps, int64_t *done)
             w[k] = {steps_of(sd.t0, g->dt), steps_of(sd.dur, g->dt),
                     sd.period > 0 ? steps_of(sd.period, g->dt) : 0, (int64_t)sd.count};
         }
-        HIP_TRY(hipMemcpy(g->d_win, w, sizeof w, hipMemcpyHostToDevice), "hipMemcpy");
+        // ordered after the replays still in flight on the grid's stream (which read the
+        // old table), and finished before w goes out of scope
+        HIP_TRY(hipMemcpyAsync(g->d_win, w, sizeof w, hipMemcpyHostToDevice, g->stream), "hipMemcpyAsync");
+        HIP_TRY(hipStreamSynchronize(g->stream), "hipStreamSynchronize");
         g->win_dirty = false;
     }
     HIP_TRY(launch_counter(g->d_nbase, g->n, 0, g->stream), "counter");
