@@ -65,6 +65,27 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
     return lib
 
 
+PROBE_SRC = os.path.join(PKG, "measure", "valu_issue_rate.hip")
+PROBE = os.path.join(BUILD, "valu_issue_rate")
+
+
+def build_probe(verbose: bool = False) -> str:
+    """Compile the VALU issue-rate probe (a standalone measurement program behind the ALU
+    roofline's slot costs, not part of the library) into _build/valu_issue_rate."""
+    os.makedirs(BUILD, exist_ok=True)
+    cmd = [HIPCC, "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wall", "-o", PROBE, PROBE_SRC]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc failed for {PROBE_SRC}:\n{r.stdout}\n{r.stderr}")
+    if verbose:
+        print("built", PROBE)
+    return PROBE
+
+
 if __name__ == "__main__":
-    build(verbose=True, sanitize="--sanitize" in sys.argv)
+    if "--probe" in sys.argv:
+        build_probe(verbose=True)
+    else:
+        build(verbose=True, sanitize="--sanitize" in sys.argv)
     sys.exit(0)

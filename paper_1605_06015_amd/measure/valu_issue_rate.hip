@@ -4,10 +4,8 @@
 // per-class issue costs that the ALU roofline of the step kernels is computed with:
 // 2-source operations (mul, add, integer add, compare, select) issue at two wave64
 // instructions per CU-cycle, a 3-source FMA at one, a transcendental (exp, rcp) at a
-// half.  Not part of the library; built and run by hand:
-//   hipcc -O3 --offload-arch=gfx950 -Xclang -target-feature -Xclang -packed-fp32-ops \
-//         -o /tmp/valu_issue_rate paper_1605_06015_amd/measure/valu_issue_rate.hip
-//   /tmp/valu_issue_rate
+// half.  Not part of the library; built by `python -m paper_1605_06015_amd.build --probe`
+// (or the package's build step) into _build/valu_issue_rate, and run by hand.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
