@@ -33,8 +33,8 @@ HBM_PEAK_GBS = 8000.0
 # x 2.4 GHz / 4 = 614.4 G slots/s.  Measured slot costs per wave64 instruction (the issue-
 # rate probe paper_1605_06015_amd/measure/valu_issue_rate.hip and its counters): a
 # 2-source operation (mul, add, integer, compare, select) can pair with another in one
-# slot (1,175 G mul/s = 1.9 per CU-cycle), a 3-source FMA takes a whole slot (626 G/s), a
-# transcendental two (301 G/s).  The floor of a kernel is its counters' mix at those
+# slot (1,172 G mul/s = 1.9 per CU-cycle), a 3-source FMA takes a whole slot (622 G/s), a
+# transcendental two (302 G/s).  The floor of a kernel is its counters' mix at those
 # costs; SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2 counts the slots it actually used.
 VALU_SLOT_PEAK_G = 256 * 4 * 2.4 / 4
 VALU_SLOTS_TRANS, VALU_SLOTS_FMA, VALU_SLOTS_OTHER = 2.0, 1.0, 0.5
