@@ -2,9 +2,9 @@
 // vector instruction, measured on independent dependency chains (8 per thread, 32,768
 // operations per thread) with every SIMD holding 8 waves.  The rates it prints fix the
 // per-class issue costs that the ALU roofline of the step kernels is computed with:
-// 2-source operations (mul, add, integer add, compare, select) issue at two wave64
-// instructions per CU-cycle, a 3-source FMA at one, a transcendental (exp, rcp) at a
-// half.  Not part of the library; built by `python -m paper_1605_06015_amd.build --probe`
+// 2-source operations (mul, add, integer add, compare, select) pair, up to two wave64
+// instructions per CU-cycle (measured 1.7-1.9), a 3-source FMA issues at one, a
+// transcendental (exp, rcp) at a half.  Not part of the library; built by `python -m paper_1605_06015_amd.build --probe`
 // (or the package's build step) into _build/valu_issue_rate, and run by hand.
 #include <hip/hip_runtime.h>
 
