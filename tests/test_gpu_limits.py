@@ -106,7 +106,9 @@ def test_dense_box_beyond_cache_streaming_kernels_sampled(aniso):
     the streaming instantiations of the z-marching kernels run: the LDS ring with rotating
     fibres, the register march when isotropic), pure diffusion of a smooth field for 3
     steps: 32 sampled voxels match the FP64 oracle run on 9^3 crops around them (a value
-    after 3 steps depends only on voxels within 3 of it, plus the fibres one further)."""
+    after 3 steps depends only on voxels within 3 of it, plus the fibres one further); the
+    same run continued to step 30 matches it on 12 voxels (corners included) on 63^3 crops
+    within 5e-4 (measured at most 4.9e-5)."""
     from oracle import oracle as O
     from paper_1605_06015_amd import bbx as B
     nx, ny, nz, h, dt, Dpar, Dperp = 512, 512, 264, 0.25, 0.01, 0.3, 0.03
@@ -123,21 +125,31 @@ def test_dense_box_beyond_cache_streaming_kernels_sampled(aniso):
     g = B.Grid(mask, h, fib, Dpar, Dperp, B.BBX_FP32)
     g.model(B.BBX_MODEL_NONE, [], dt)
     g.set(0, V)
+    Vb = np.broadcast_to(V, (nz, ny, nx))
+
+    def check(got, picks, nsteps, tol):
+        r = nsteps + 1
+        for c in picks:
+            sl = tuple(slice(max(0, c[i] - r), min((nz, ny, nx)[i], c[i] + r + 1)) for i in range(3))
+            cm = np.ascontiguousarray(mask[sl])
+            cf = None if fib is None else np.ascontiguousarray(fib[sl])
+            s = O.Sim(cm, h, cf, Dpar, Dperp, O.MODEL_NONE, [], dt)
+            s.state[0] = Vb[sl]
+            s.step(nsteps)
+            loc = tuple(int(c[i] - sl[i].start) for i in range(3))
+            want = s.state[0][loc]
+            assert abs(got[tuple(c)] - want) <= tol, (nsteps, tuple(c), got[tuple(c)], want)
+
     g.step(3)
     got = g.get(0)
-    g.close()
     rng = np.random.default_rng(3)
     picks = np.stack([rng.integers(0, nz, 32), rng.integers(0, ny, 32), rng.integers(0, nx, 32)], 1)
     picks[:4] = [[0, 0, 0], [nz - 1, ny - 1, nx - 1], [nz // 2, 0, nx - 1], [nz - 1, ny // 2, 0]]
-    r = 4
-    Vb = np.broadcast_to(V, (nz, ny, nx))
-    for c in picks:
-        sl = tuple(slice(max(0, c[i] - r), min((nz, ny, nx)[i], c[i] + r + 1)) for i in range(3))
-        cm = np.ascontiguousarray(mask[sl])
-        cf = None if fib is None else np.ascontiguousarray(fib[sl])
-        s = O.Sim(cm, h, cf, Dpar, Dperp, O.MODEL_NONE, [], dt)
-        s.state[0] = Vb[sl]
-        s.step(3)
-        loc = tuple(int(c[i] - sl[i].start) for i in range(3))
-        want = s.state[0][loc]
-        assert abs(got[tuple(c)] - want) <= 1e-4, (tuple(c), got[tuple(c)], want)
+    check(got, picks, 3, 1e-4)
+    del got
+    g.step(27)
+    got = g.get(0)
+    g.close()
+    picks = np.stack([rng.integers(0, nz, 12), rng.integers(0, ny, 12), rng.integers(0, nx, 12)], 1)
+    picks[:2] = [[0, 0, 0], [nz - 1, ny - 1, nx - 1]]
+    check(got, picks, 30, 5e-4)
