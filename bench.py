@@ -307,6 +307,8 @@ def barkley_line(stream):
 
 
 GOLDEN_MAPS = os.path.join(ROOT, "tests", "golden", "crn_cup128_at_apd.csv")
+# the FP64 oracle's maps of the TP06 cup of the surrogate comparison (same geometry, 500 ms)
+GOLDEN_MAPS_TP06 = os.path.join(ROOT, "tests", "golden", "tp06_cup128_at_apd.csv")
 GOLDEN_TRACES = os.path.join(ROOT, "tests", "golden", "crn_cup128_v_traces.npz")
 
 
@@ -554,12 +556,11 @@ def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
     runs of the cup (outside the timed region), anchor the resting state, choose the
     acceptance threshold v_hi on a held-out cup (another geometry seed, 96x96x48), then time
     the full run of the benchmark cup with the plain FP32 kinetics and with the surrogate,
-    and compare activation-time and APD90 maps (against the plain run, and for CRN against
-    the FP64 oracle's stored maps)."""
+    and compare activation-time and APD90 maps (against the plain run, and against the FP64
+    oracle's stored maps of the cup)."""
     import torch
     from paper_1605_06015_amd import bbx as B
     from paper_1605_06015_amd import surrogate as SU
-    from paper_1605_06015_amd import workloads as WL
     mid, nv, c, geo, rest, amp, dur = SU._model_setup(model)
     t0 = time.perf_counter()
     S, S1 = SU.generate_pairs(runs=3, t_ms=1200.0, per_sample=2048, seed=2, stream=stream, model=model)
@@ -590,12 +591,13 @@ def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
         return out
     plain, res, dt = SU.run_pair(tr, model, c["seed"], 128, 128, 64, t_ms, (v_hi,), stream)
     r = res[float(v_hi)]
-    # against the FP64 oracle's stored maps of this cup (CRN, the full 500 ms)
-    vs_oracle = "not measured (the stored oracle maps cover the CRN cup over 500 ms)"
-    if model == "crn" and abs(t_ms - 500.0) < 1e-9 and os.path.exists(GOLDEN_MAPS):
-        d = np.loadtxt(GOLDEN_MAPS, delimiter=",", skiprows=2)
+    # against the FP64 oracle's stored maps of this cup (the full 500 ms)
+    golden = {"crn": GOLDEN_MAPS, "tp06": GOLDEN_MAPS_TP06}[model]
+    vs_oracle = "not measured (the stored oracle maps cover the 500 ms run)"
+    if abs(t_ms - 500.0) < 1e-9 and os.path.exists(golden):
+        d = np.loadtxt(golden, delimiter=",", skiprows=2)
         gidx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
-        g = WL.crn_cup(128, 128, 64, seed=c["seed"], active=c["active"], h=c["h"])
+        g = geo(128, 128, 64, seed=c["seed"], active=c["active"], h=c["h"])
         pos = np.searchsorted(np.flatnonzero(g["mask"].ravel()), gidx)
         vs_oracle = {}
         for name, at, apd in (("surrogate", r["at"], r["apd"]), ("plain", plain["at"], plain["apd"])):

@@ -127,18 +127,29 @@ def test_crn_headline_500ms_tabulated_against_oracle_maps():
 TP06_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "tp06_cup64_at_apd.csv")
 
 
+# (box, geometry seed, stored maps): the small test cup, and the cup of the benchmark's
+# TP06 surrogate comparison
+TP06_CUPS = {"cup64": ((64, 64, 32), 5, TP06_GOLDEN),
+             "cup128": ((128, 128, 64), 1, os.path.join(os.path.dirname(os.path.abspath(__file__)),
+                                                        "golden", "tp06_cup128_at_apd.csv"))}
+
+
+@pytest.mark.parametrize("cup", ["cup64", "cup128"])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_tp06_cup_500ms_against_oracle_maps(prec):
-    """TP06 on a 64x64x32 cup for 500 ms (dt 0.02 ms) against the FP64 oracle's activation
-    times and APD90 at 4,000 seeded tissue voxels (tests/golden/tp06_cup64_at_apd.csv, made
-    by make_tp06_cup_maps.py).  FP64 to the file's 9 significant digits (2e-6 ms).  FP32:
-    same activated voxels, activation times within 1 dt, APD90 within 0.5 ms: at the 90%
-    level a single FP64 oracle cell repolarises at 2.1 mV/ms, so the 0.5 mV bar moves the
-    crossing by about 0.24 ms; the bound leaves room for slopes down to 1 mV/ms in tissue."""
+def test_tp06_cup_500ms_against_oracle_maps(prec, cup):
+    """TP06 on a 64x64x32 cup, and on the 128x128x64 cup of the benchmark's TP06 surrogate
+    comparison, for 500 ms (dt 0.02 ms) against the FP64 oracle's activation times and
+    APD90 at 4,000 seeded tissue voxels (tests/golden/tp06_cup64_at_apd.csv and
+    tp06_cup128_at_apd.csv, made by make_tp06_cup_maps.py and make_tp06_cup128_maps.py).
+    FP64 to the file's 9 significant digits (2e-6 ms).  FP32: same activated voxels,
+    activation times within 1 dt, APD90 within 0.5 ms: at the 90% level a single FP64
+    oracle cell repolarises at 2.1 mV/ms, so the 0.5 mV bar moves the crossing by about
+    0.24 ms; the bound leaves room for slopes down to 1 mV/ms in tissue."""
     from paper_1605_06015_amd import bbx as B
-    d = np.loadtxt(TP06_GOLDEN, delimiter=",", skiprows=2)
+    (nx, ny, nz), seed, path = TP06_CUPS[cup]
+    d = np.loadtxt(path, delimiter=",", skiprows=2)
     idx, at_o, apd_o = d[:, 0].astype(np.int64), d[:, 1], d[:, 2]
-    g = WL.tp06_cup(64, 64, 32, seed=5, h=0.25)
+    g = WL.tp06_cup(nx, ny, nz, seed=seed, active=0.35, h=0.25)
     grid = B.Grid(g["mask"], 0.25, g["fibre"], 0.3, 0.03, prec)
     grid.model(B.BBX_MODEL_TP06, [], 0.02)
     for v in range(19):
@@ -154,7 +165,7 @@ def test_tp06_cup_500ms_against_oracle_maps(prec):
     assert fa.mean() > 0.9 and fp.mean() > 0.9
     dat = np.abs(at[fa] - at_o[fa]).max()
     dapd = np.abs(apd[fp] - apd_o[fp]).max()
-    print(f"tp06 prec {prec}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
+    print(f"tp06 {cup} prec {prec}: max |dAT| {dat:.3g} ms, max |dAPD90| {dapd:.3g} ms")
     if prec == 1:
         assert dat <= 2e-6 and dapd <= 2e-6, (dat, dapd)
     else:

@@ -5,6 +5,7 @@ import subprocess
 import sys
 
 import numpy as np
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
@@ -64,13 +65,16 @@ def test_golden_maps_match_the_workload():
     assert np.corrcoef(dist, at)[0, 1] > 0.8
 
 
-def test_tp06_golden_maps_match_the_workload():
-    """The stored TP06 oracle maps belong to the current 64x64x32 TP06 cup."""
-    path = os.path.join(ROOT, "tests", "golden", "tp06_cup64_at_apd.csv")
+@pytest.mark.parametrize("name,shape,seed", [("tp06_cup64_at_apd.csv", (64, 64, 32), 5),
+                                              ("tp06_cup128_at_apd.csv", (128, 128, 64), 1)])
+def test_tp06_golden_maps_match_the_workload(name, shape, seed):
+    """The stored TP06 oracle maps belong to the current TP06 cups (the 64x64x32 test cup
+    and the 128x128x64 cup of the benchmark's surrogate comparison)."""
+    path = os.path.join(ROOT, "tests", "golden", name)
     d = np.loadtxt(path, delimiter=",", skiprows=2)
     idx, at = d[:, 0].astype(np.int64), d[:, 1]
     assert len(idx) == 4000 and len(np.unique(idx)) == 4000
-    g = WL.tp06_cup(64, 64, 32, seed=5, h=0.25)
+    g = WL.tp06_cup(*shape, seed=seed, active=0.35, h=0.25)
     assert np.all(g["mask"].ravel()[idx] == 1)
     z, y, x = np.unravel_index(idx, g["mask"].shape)
     stim = np.argwhere(g["stim"] == 1).mean(axis=0)
