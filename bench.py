@@ -517,8 +517,8 @@ def surrogate_shell(stream, tr, t_ms, v_hi_cup):
     512x512x384 double shell (25.2 M tissue voxels), S1 strip only, the first t_ms of the
     wave's spread.  The acceptance threshold is chosen on a held-out shell of the same
     family (256x256x192, geometry seed 11), run for the same time, by the cup's rule (the
-    largest network share whose activation times stay within 1 dt of the plain run's,
-    same activated set): on a shell, resting tissue waits longer for the wave than on the
+    largest network share whose activation times stay within half a step of the plain
+    run's, same activated set): on a shell, resting tissue waits longer for the wave than on the
     cup, so a threshold chosen on the cup does not carry over.  If no threshold meets the
     rule there, the shell runs at the cup's threshold (v_hi_cup) and says so."""
     from paper_1605_06015_amd import workloads as WL
@@ -528,11 +528,11 @@ def surrogate_shell(stream, tr, t_ms, v_hi_cup):
     held = WL.tp06_biv(256, 256, 192, c["h"], 11, c["active"], c["s1_strip"])
     _, sweep, dt = _shell_runs(stream, tr, held, t_ms, cands)
     ok = [v for v in cands if sweep[v]["same_activated"] and sweep[v]["at_max"] is not None
-          and sweep[v]["at_max"] <= dt]
+          and sweep[v]["at_max"] <= 0.5 * dt]
     v_hi = max(ok, key=lambda v: (sweep[v]["share"], -v)) if ok else None
     sel = {"held_out": "double shell 256x256x192, geometry seed 11 (the benchmark shell: "
                        f"512x512x384, seed {c['seed']})", "rule": "largest share with AT within "
-                       "1 dt of plain", "chosen_v_hi_mV": v_hi, "sweep": {str(k): v for k, v in sweep.items()}}
+                       "0.5 dt of plain", "chosen_v_hi_mV": v_hi, "sweep": {str(k): v for k, v in sweep.items()}}
     if v_hi is None:
         v_hi = v_hi_cup
         sel["note"] = ("no threshold met the accuracy rule on the held-out shell; the benchmark "
@@ -579,7 +579,7 @@ def surrogate_line(stream, model="crn", t_ms=500.0, shell_ms=None):
            "unit": "voxel-updates/s",
            "threshold_selection": {"held_out": "cup 96x96x48, geometry seed 11 (the benchmark cup: seed "
                                                f"{c['seed']})", "rule": "largest share with AT within "
-                                               "1 dt of plain", "chosen_v_hi_mV": v_hi,
+                                               "0.5 dt of plain (headroom under the 1-dt bar)", "chosen_v_hi_mV": v_hi,
                                    "sweep": {str(k): v for k, v in sweep.items()},
                                    "seconds": round(t3 - t2, 2)},
            "training": {"pairs": tr.npairs, "schedule": [list(x) for x in SU.SCHEDULES[model]], "batch": 4096,

@@ -180,12 +180,14 @@ def run_pair(trained, model, geo_seed, nx=96, ny=96, nz=48, t_ms=500.0, v_his=()
     return plain, res, c["dt"]
 
 
-def select_threshold(trained, model, geo_seed=11, margin=1.0, offsets=(-0.2, -0.1, -0.05, -0.02,
+def select_threshold(trained, model, geo_seed=11, margin=0.5, offsets=(-0.2, -0.1, -0.05, -0.02,
                      -0.01, 0.0, 0.01), stream=None):
     """Acceptance threshold v_hi chosen on a held-out cup (geometry seed geo_seed, not the
     benchmark's): among rest + offsets (mV), the one with the largest surrogate share whose
-    activation times stay within margin * dt of the plain run's on every voxel (the 1-dt
-    bar), with the same activated set.  Returns (v_hi or None, the sweep)."""
+    activation times stay within margin * dt of the plain run's on every voxel, with the
+    same activated set.  The default half step leaves room under the 1-dt bar for the spread
+    between cups (measured: a TP06 threshold at 0.98 dt on the held-out cup gave 1.1 dt on
+    the benchmark's).  Returns (v_hi or None, the sweep)."""
     rest = _model_setup(model)[4][0]
     cands = [round(rest + o, 4) for o in offsets]
     _, sweep, dt = run_pair(trained, model, geo_seed, v_his=cands, stream=stream)

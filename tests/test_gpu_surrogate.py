@@ -323,7 +323,7 @@ def test_tp06_surrogate_pipeline(env):
 def test_benchmark_surrogate_threshold_held_out(model):
     """The benchmark's surrogate measurement: the acceptance threshold is chosen on a
     held-out cup (another geometry seed) as the largest-share threshold whose activation
-    times stay within 1 dt of the plain run's; on the benchmark's own cup (not seen by the
+    times stay within half a step of the plain run's; on the benchmark's own cup (not seen by the
     choice) the surrogate must keep the same activated set and activation times within
     2 dt of the plain run (whether it meets 1 dt there is what the benchmark reports),
     with the network taking part of the work."""
